@@ -1,0 +1,197 @@
+/*
+ * lpp.h -- C ABI of the MI355X LPP power-spectrum-multipole library (liblpp.so).
+ *
+ * The library estimates, from a galaxy catalog with shapes and a random
+ * catalog, the local-plane-parallel (LPP, endpoint line of sight) multipoles
+ * of the power spectra of a projected rank-2 tensor field and of the density
+ * field (Kurita & Takada, arXiv:2202.11839, Sec. III.A):
+ *
+ *   DD_l    density auto, Legendre moments            (eq. lpp_dens_app)
+ *   GD_L    shape-density cross, m=2 assoc. Legendre  (eqs. lpp_estimator_cross_Xiij, def_of_Xiij)
+ *   PLUS_l  "plus" shape auto P_+ = P_EE + P_BB       (eq. lpp_estimator_auto_+)
+ *   MINUS_L "minus" shape auto P_- = P_EE - P_BB,
+ *           m=4 assoc. Legendre                       (eqs. lpp_estimator_auto_-, def_of_Xiijkl)
+ *   EE_l, BB_l  (P_+ +- sum_L C_lL Re P_-)/2, the Legendre content of the
+ *           truncated m=4 series (eq. relation_pm_EB)
+ *
+ * per k-shell, with the FKP-style normalisation I and the shot noise of the
+ * monopoles (subtracted from DD_l0 and PLUS_l0, and reported separately).
+ * Real parts are the spectra; imaginary parts are parity-odd diagnostics
+ * that vanish for a parity-invariant field (Sec. II.C).
+ *
+ * Conventions
+ *   - Forward transforms carry exp(-i k.x) (Sec. I, conventions).
+ *   - Positions are Cartesian comoving coordinates; the observer sits at
+ *     config.observer; each object's line of sight is xhat = (x-o)/|x-o|.
+ *   - Shapes (g1, g2) are the components of the projected tensor in the
+ *     (e_theta, e_phi) basis of the object's own line of sight, gamma =
+ *     g1 + i g2 = e_ij(xhat) gamma_ij (Sec. II.B, eq. gamma_def), where
+ *     (e_theta, e_phi, xhat) are the columns of the standard rotation
+ *     S(xhat) (App. E, eq. def_standard_rotation); phi = 0 at the poles.
+ *   - Mesh: node c at box_origin + c*H, H = box_size/mesh_n, periodic;
+ *     NGP/CIC/TSC assignment, optional interlacing (second grid shifted by
+ *     H/2 on all axes) and compensation by prod_i sinc(pi n_i/N)^p.
+ *   - k-shells: bin b holds the modes n != 0 with T_b <= |n|^2 < T_{b+1},
+ *     T_b = ceil((b*dn_num/dn_den)^2) (integers; |n| in units of
+ *     kf = 2 pi/box_size).  Default width N/(2 n_kbins), i.e. bins up to
+ *     the Nyquist frequency.  n_kbins*dn must not exceed N/2.
+ *
+ * Ownership and errors
+ *   - Every function returns an lpp_status and never throws; after any
+ *     error the plan remains valid.
+ *   - Catalog and result buffers belong to the caller and are never freed
+ *     by the library.  Device workspace is either provided by the caller
+ *     (lpp_set_workspace; the caller owns it and keeps it alive while the
+ *     plan uses it) or, if none is set, allocated by the plan on first use
+ *     and released by lpp_plan_destroy.
+ *   - Catalogs (host or device) are checked on the device (non-finite
+ *     values, objects outside the box or at the observer, zero random
+ *     weight) before any mass assignment; the status is returned after the
+ *     check synchronises, and nothing else has run.
+ *   - Calls on one plan must not overlap; different plans are independent.
+ */
+#ifndef LPP_H
+#define LPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LPP_OK = 0,
+  LPP_E_INVALID = 1,      /* bad argument or configuration                        */
+  LPP_E_NONFINITE = 2,    /* NaN/Inf in a catalog column                          */
+  LPP_E_OUT_OF_BOX = 3,   /* an object outside [origin, origin + box)^3           */
+  LPP_E_AT_OBSERVER = 4,  /* an object closer than 1e-6 box to the observer       */
+  LPP_E_NO_RANDOMS = 5,   /* the random catalog has zero total weight             */
+  LPP_E_WORKSPACE = 6,    /* caller workspace smaller than lpp_workspace_size     */
+  LPP_E_NOMEM = 7,        /* device or host allocation failed                     */
+  LPP_E_DEVICE = 8,       /* HIP runtime error or no device                       */
+  LPP_E_UNSUPPORTED = 9   /* valid request outside what this build supports       */
+} lpp_status;
+
+enum { LPP_F32 = 0, LPP_F64 = 1 };
+enum { LPP_DD = 1u, LPP_GD = 2u, LPP_PLUS = 4u, LPP_MINUS = 8u, LPP_ALL = 15u };
+
+typedef struct lpp_plan_s* lpp_plan;
+
+typedef struct {
+  int32_t mesh_n;          /* N: power of two, 16 <= N <= 1024                     */
+  double box_size;         /* side of the cubic box                                */
+  double box_origin[3];    /* lower corner of the box                              */
+  double observer[3];      /* observer position (origin of the lines of sight)     */
+  int32_t assignment;      /* 1 NGP, 2 CIC, 3 TSC                                  */
+  int32_t interlacing;     /* 0 or 1                                               */
+  int32_t compensate;      /* 0 or 1: divide by the assignment window              */
+  int32_t precision;       /* LPP_F32 or LPP_F64: deposit and FFT arithmetic; the
+                              shell sums, I and the shot noise are always FP64     */
+  int32_t lmax;            /* even, 0..8; DD/PLUS l = 0..lmax, GD L = 2..lmax,
+                              MINUS L = 4..lmax                                    */
+  uint32_t spectra;        /* bitmask of LPP_DD | LPP_GD | LPP_PLUS | LPP_MINUS    */
+  int32_t n_kbins;         /* number of k-shells, >= 1                             */
+  int32_t dn_num, dn_den;  /* bin width dn_num/dn_den in units of kf; both 0 for
+                              the default N/(2 n_kbins)                            */
+} lpp_config;
+
+typedef struct {
+  int64_t n;               /* number of objects, >= 1                              */
+  int32_t on_device;       /* 1: pointers are device pointers                      */
+  int32_t dtype;           /* LPP_F32 or LPP_F64, for every column                 */
+  const void* x;           /* positions, n each                                    */
+  const void* y;
+  const void* z;
+  const void* w;           /* weights; NULL = 1                                    */
+  const void* nbar;        /* mean density at the object (randoms: enters I);
+                              NULL = sum(w_gal)/box_size^3, a survey that fills
+                              the whole box                                       */
+  const void* g1;          /* galaxies: shape components; randoms: NULL           */
+  const void* g2;
+} lpp_catalog;
+
+typedef struct {           /* every array is caller-allocated, sized by lpp_result_layout */
+  int64_t* n_modes;        /* [n_kbins] modes per shell (bit-exact)                 */
+  double* k_eff;           /* [n_kbins] mean |k| over the shell                     */
+  double* k_lo;            /* [n_kbins] shell edges                                 */
+  double* k_hi;
+  double* re;              /* [n_series][n_kbins] real parts (spectra)              */
+  double* im;              /* [n_series][n_kbins] imaginary parts (diagnostics)     */
+  double alpha;            /* sum w_gal / sum w_ran                                 */
+  double norm_I;           /* alpha sum_ran w^2 nbar                                */
+  double shot_dd;          /* (sum w_gal^2 + alpha^2 sum w_ran^2) / I               */
+  double shot_plus;        /* sum w_gal^2 |gamma|^2 / I                             */
+  double sum_w_gal;
+  double sum_w_ran;
+} lpp_result;
+
+/* Plan lifetime.  lpp_plan_create validates the configuration and builds the
+ * host tables (bin thresholds, harmonic coefficients); it touches no device. */
+lpp_status lpp_plan_create(const lpp_config* cfg, lpp_plan* out);
+lpp_status lpp_plan_destroy(lpp_plan plan);
+
+/* Device workspace needed for catalogs of up to max_gal / max_ran objects. */
+lpp_status lpp_workspace_size(lpp_plan plan, int64_t max_gal, int64_t max_ran, size_t* bytes);
+/* Use caller-owned device memory (>= lpp_workspace_size bytes, 256-byte aligned). */
+lpp_status lpp_set_workspace(lpp_plan plan, void* device_ptr, size_t bytes);
+/* Launch on this HIP stream (hipStream_t; NULL = the default stream). */
+lpp_status lpp_set_stream(lpp_plan plan, void* hip_stream);
+
+/* Output layout: number of series and of k-shells. */
+lpp_status lpp_result_layout(lpp_plan plan, int32_t* n_series, int32_t* n_kbins);
+/* Name of series i ("DD_l0", "GD_L2", "PLUS_l0", "MINUS_L4", "EE_l0", "BB_l0", ...);
+ * NULL if i is out of range.  The string lives as long as the plan. */
+const char* lpp_series_name(lpp_plan plan, int32_t i);
+
+/* One estimate: catalogs in, multipoles per shell, normalisation and shot
+ * noise out (Sec. III.A).  Synchronises the plan's stream before returning. */
+lpp_status lpp_estimate(lpp_plan plan, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out);
+
+/* n independent estimates (mock catalogs of any sizes) through the same plan;
+ * per_catalog_status[i] receives each one's status, and the call returns
+ * LPP_OK if all succeeded, otherwise the first failure's status. */
+lpp_status lpp_estimate_batch(lpp_plan plan, int32_t n, const lpp_catalog* gals, const lpp_catalog* rans,
+                              lpp_result* outs, lpp_status* per_catalog_status);
+
+/* Building blocks, exposed for testing and for callers with their own meshes.
+ * All meshes are complex, index x + N*(y + N*z), interleaved (re, im), of the
+ * plan's precision (float2 or double2), on the device. */
+
+/* Mass-assign the weights w of a catalog (times `scale`) onto `mesh` (N^3
+ * complex; real part = the grid, imaginary part = the interlaced grid if the
+ * plan interlaces, else 0).  The mesh is overwritten. */
+lpp_status lpp_deposit_weights(lpp_plan plan, const lpp_catalog* cat, double scale, void* mesh);
+
+/* In-place forward 3D DFT (exp(-2 pi i n.c/N)) of an N^3 complex device mesh. */
+lpp_status lpp_fft3d(lpp_plan plan, void* mesh);
+
+/* Per-stage timing.  When on, the plan records a pair of HIP events on its
+ * stream around every kernel group of lpp_estimate and accumulates the
+ * elapsed milliseconds and kernel launches per stage (enum below) until
+ * lpp_reset_profile.  Off by default; costs two event records per group. */
+enum {
+  LPP_STAGE_SORT = 0,    /* catalog sort by tile (count, scan, scatter)        */
+  LPP_STAGE_DEPOSIT = 1, /* mass assignment kernels                            */
+  LPP_STAGE_FFT_X = 2,   /* unit-stride FFT pass                               */
+  LPP_STAGE_FFT_YZ = 3,  /* strided FFT passes (y and z, same kernel)          */
+  LPP_STAGE_BIN = 4,     /* base construction and shell binning kernels        */
+  LPP_STAGE_OTHER = 5,   /* mesh clears and partial-sum reductions             */
+  LPP_N_STAGES = 6
+};
+lpp_status lpp_set_profiling(lpp_plan plan, int32_t on);
+/* ms[i], launches[i] for stages i < n (stages beyond LPP_N_STAGES read 0). */
+lpp_status lpp_get_profile(lpp_plan plan, double* ms, int64_t* launches, int32_t n);
+lpp_status lpp_reset_profile(lpp_plan plan);
+
+/* Message for a status code (static string). */
+const char* lpp_status_string(lpp_status s);
+
+/* Library version string. */
+const char* lpp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPP_H */

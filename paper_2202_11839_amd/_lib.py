@@ -1,0 +1,279 @@
+"""ctypes binding of liblpp.so (include/lpp.h): argument marshalling only.
+
+Every step of the estimator runs in the library's HIP kernels; this module
+passes pointers and sizes and never computes any part of the result.  PyTorch
+provides the device memory (the plan's workspace is a torch uint8 tensor) and
+the stream (torch's current stream).  If the shared library is missing the
+import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblpp.so")
+
+LPP_F32, LPP_F64 = 0, 1
+LPP_DD, LPP_GD, LPP_PLUS, LPP_MINUS, LPP_ALL = 1, 2, 4, 8, 15
+STATUS = ["LPP_OK", "LPP_E_INVALID", "LPP_E_NONFINITE", "LPP_E_OUT_OF_BOX", "LPP_E_AT_OBSERVER",
+          "LPP_E_NO_RANDOMS", "LPP_E_WORKSPACE", "LPP_E_NOMEM", "LPP_E_DEVICE", "LPP_E_UNSUPPORTED"]
+
+EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace", "lpp_set_stream",
+           "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
+           "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
+           "lpp_reset_profile"]
+STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
+
+
+class LppError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{what}: {name}")
+
+
+class Config(C.Structure):
+    _fields_ = [("mesh_n", C.c_int32), ("box_size", C.c_double), ("box_origin", C.c_double * 3),
+                ("observer", C.c_double * 3), ("assignment", C.c_int32), ("interlacing", C.c_int32),
+                ("compensate", C.c_int32), ("precision", C.c_int32), ("lmax", C.c_int32),
+                ("spectra", C.c_uint32), ("n_kbins", C.c_int32), ("dn_num", C.c_int32), ("dn_den", C.c_int32)]
+
+
+class CatalogStruct(C.Structure):
+    _fields_ = [("n", C.c_int64), ("on_device", C.c_int32), ("dtype", C.c_int32),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("w", C.c_void_p),
+                ("nbar", C.c_void_p), ("g1", C.c_void_p), ("g2", C.c_void_p)]
+
+
+class ResultStruct(C.Structure):
+    _fields_ = [("n_modes", C.c_void_p), ("k_eff", C.c_void_p), ("k_lo", C.c_void_p), ("k_hi", C.c_void_p),
+                ("re", C.c_void_p), ("im", C.c_void_p), ("alpha", C.c_double), ("norm_I", C.c_double),
+                ("shot_dd", C.c_double), ("shot_plus", C.c_double), ("sum_w_gal", C.c_double),
+                ("sum_w_ran", C.c_double)]
+
+
+_LIB = None
+
+
+def load() -> C.CDLL:
+    """Load the in-tree liblpp.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2202_11839_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.lpp_plan_create.argtypes = [C.POINTER(Config), C.POINTER(P)]
+    lib.lpp_plan_destroy.argtypes = [P]
+    lib.lpp_workspace_size.argtypes = [P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
+    lib.lpp_set_workspace.argtypes = [P, P, C.c_size_t]
+    lib.lpp_set_stream.argtypes = [P, P]
+    lib.lpp_result_layout.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.lpp_series_name.argtypes = [P, C.c_int32]
+    lib.lpp_series_name.restype = C.c_char_p
+    lib.lpp_estimate.argtypes = [P, C.POINTER(CatalogStruct), C.POINTER(CatalogStruct), C.POINTER(ResultStruct)]
+    lib.lpp_estimate_batch.argtypes = [P, C.c_int32, C.POINTER(CatalogStruct), C.POINTER(CatalogStruct),
+                                       C.POINTER(ResultStruct), C.POINTER(C.c_int32)]
+    lib.lpp_deposit_weights.argtypes = [P, C.POINTER(CatalogStruct), C.c_double, P]
+    lib.lpp_fft3d.argtypes = [P, P]
+    lib.lpp_status_string.argtypes = [C.c_int]
+    lib.lpp_status_string.restype = C.c_char_p
+    lib.lpp_version.restype = C.c_char_p
+    lib.lpp_set_profiling.argtypes = [P, C.c_int32]
+    lib.lpp_get_profile.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+    lib.lpp_reset_profile.argtypes = [P]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or C.c_int
+    for name in ("lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace",
+                 "lpp_set_stream", "lpp_result_layout", "lpp_estimate", "lpp_estimate_batch",
+                 "lpp_deposit_weights", "lpp_fft3d", "lpp_set_profiling", "lpp_get_profile",
+                 "lpp_reset_profile"):
+        getattr(lib, name).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise LppError(st, what)
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class _Cols:
+    """Keeps the arrays behind a CatalogStruct alive."""
+
+    def __init__(self, cat, dtype: int, keep: list):
+        self.keep = keep
+        cols = {}
+        first = cat.x
+        on_dev = _is_torch(first) and first.is_cuda
+        np_dtype = np.float64 if dtype == LPP_F64 else np.float32
+        n = int(first.shape[0])
+        for name in ("x", "y", "z", "w", "nbar", "g1", "g2"):
+            a = getattr(cat, name, None)
+            if a is None:
+                cols[name] = None
+                continue
+            if on_dev:
+                import torch
+                tdt = torch.float64 if dtype == LPP_F64 else torch.float32
+                if a.dtype != tdt or not a.is_contiguous() or not a.is_cuda:
+                    raise TypeError(f"device column {name} must be a contiguous CUDA tensor of {tdt}")
+                cols[name] = a.data_ptr()
+                keep.append(a)
+            else:
+                arr = np.ascontiguousarray(a, dtype=np_dtype)
+                keep.append(arr)
+                cols[name] = arr.ctypes.data
+            if int(a.shape[0]) != n:
+                raise ValueError(f"column {name} has {a.shape[0]} rows, expected {n}")
+        self.struct = CatalogStruct(n, 1 if on_dev else 0, dtype, cols["x"], cols["y"], cols["z"], cols["w"],
+                                    cols["nbar"], cols["g1"], cols["g2"])
+
+
+class Plan:
+    """One estimator configuration (mesh, box, observer, assignment, multipoles, bins)."""
+
+    def __init__(self, mesh_n: int, box_size: float, box_origin, observer=(0.0, 0.0, 0.0), assignment: int = 3,
+                 interlacing: int = 1, compensate: int = 1, precision: str = "f32", lmax: int = 4,
+                 spectra: int = LPP_ALL, n_kbins: int = 16, dn=None):
+        self.lib = load()
+        cfg = Config()
+        cfg.mesh_n = mesh_n
+        cfg.box_size = box_size
+        cfg.box_origin = (C.c_double * 3)(*box_origin)
+        cfg.observer = (C.c_double * 3)(*observer)
+        cfg.assignment = assignment
+        cfg.interlacing = interlacing
+        cfg.compensate = compensate
+        cfg.precision = LPP_F64 if precision in ("f64", LPP_F64) else LPP_F32
+        cfg.lmax = lmax
+        cfg.spectra = spectra
+        cfg.n_kbins = n_kbins
+        cfg.dn_num, cfg.dn_den = (0, 0) if dn is None else dn
+        self.cfg = cfg
+        self.precision = cfg.precision
+        h = C.c_void_p()
+        _check(self.lib.lpp_plan_create(C.byref(cfg), C.byref(h)), "lpp_plan_create")
+        self.handle = h
+        ns, nb = C.c_int32(), C.c_int32()
+        _check(self.lib.lpp_result_layout(h, C.byref(ns), C.byref(nb)), "lpp_result_layout")
+        self.n_series, self.n_kbins = ns.value, nb.value
+        self.series = [self.lib.lpp_series_name(h, i).decode() for i in range(self.n_series)]
+        self._ws = None
+        self._ws_cap = (0, 0)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.lpp_plan_destroy(h)
+            self.handle = None
+
+    # ---- device plumbing (torch owns memory and stream) ----
+    def _prepare_device(self, n_gal: int, n_ran: int):
+        import torch
+        if not torch.cuda.is_available():
+            raise LppError(8, "no HIP device")
+        self.lib.lpp_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if n_gal > self._ws_cap[0] or n_ran > self._ws_cap[1]:
+            ng, nr = max(n_gal, self._ws_cap[0]), max(n_ran, self._ws_cap[1])
+            sz = C.c_size_t()
+            _check(self.lib.lpp_workspace_size(self.handle, ng, nr, C.byref(sz)), "lpp_workspace_size")
+            self._ws = None
+            self._ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device="cuda")
+            ptr = (self._ws.data_ptr() + 255) // 256 * 256
+            _check(self.lib.lpp_set_workspace(self.handle, C.c_void_p(ptr), int(sz.value)), "lpp_set_workspace")
+            self._ws_cap = (ng, nr)
+
+    def _result(self):
+        nb, ns = self.n_kbins, self.n_series
+        arrs = dict(n_modes=np.zeros(nb, np.int64), k_eff=np.zeros(nb), k_lo=np.zeros(nb), k_hi=np.zeros(nb),
+                    re=np.zeros((ns, nb)), im=np.zeros((ns, nb)))
+        rs = ResultStruct(*(arrs[k].ctypes.data for k in ("n_modes", "k_eff", "k_lo", "k_hi", "re", "im")))
+        return arrs, rs
+
+    @staticmethod
+    def _pack(arrs, rs, series) -> Dict:
+        out = dict(arrs)
+        out["series"] = list(series)
+        for k in ("alpha", "norm_I", "shot_dd", "shot_plus", "sum_w_gal", "sum_w_ran"):
+            out[k] = float(getattr(rs, k))
+        return out
+
+    def estimate(self, gal, ran, dtype: Optional[int] = None) -> Dict:
+        """Multipoles of one catalog pair; returns numpy arrays (re/im [series, bin], n_modes, k_eff, ...)."""
+        dt = self._dtype(gal) if dtype is None else dtype
+        keep: list = []
+        cg = _Cols(gal, dt, keep)
+        cr = _Cols(ran, dt, keep)
+        self._prepare_device(cg.struct.n, cr.struct.n)
+        arrs, rs = self._result()
+        _check(self.lib.lpp_estimate(self.handle, C.byref(cg.struct), C.byref(cr.struct), C.byref(rs)),
+               "lpp_estimate")
+        return self._pack(arrs, rs, self.series)
+
+    def estimate_batch(self, gals: List, rans: List, dtype: Optional[int] = None):
+        n = len(gals)
+        dt = self._dtype(gals[0]) if dtype is None else dtype
+        keep: list = []
+        cg = [_Cols(g, dt, keep) for g in gals]
+        cr = [_Cols(r, dt, keep) for r in rans]
+        self._prepare_device(max(c.struct.n for c in cg), max(c.struct.n for c in cr))
+        G = (CatalogStruct * n)(*[c.struct for c in cg])
+        R = (CatalogStruct * n)(*[c.struct for c in cr])
+        res = [self._result() for _ in range(n)]
+        RS = (ResultStruct * n)(*[r[1] for r in res])
+        st = (C.c_int32 * n)()
+        self.lib.lpp_estimate_batch(self.handle, n, G, R, RS, st)
+        outs = []
+        for i in range(n):
+            if st[i] != 0:
+                outs.append(LppError(st[i], f"catalog {i}"))
+            else:
+                outs.append(self._pack(res[i][0], RS[i], self.series))
+        return outs
+
+    def deposit_weights(self, cat, scale: float, mesh) -> None:
+        """Mass-assign cat.w * scale onto ``mesh`` (torch complex tensor N^3 on the device)."""
+        keep: list = []
+        cc = _Cols(cat, self._dtype(cat), keep)
+        self._prepare_device(1, cc.struct.n)
+        _check(self.lib.lpp_deposit_weights(self.handle, C.byref(cc.struct), float(scale),
+                                            C.c_void_p(mesh.data_ptr())), "lpp_deposit_weights")
+
+    def fft3d(self, mesh) -> None:
+        """In-place forward 3D DFT of a contiguous complex torch tensor of shape (N, N, N) [z, y, x]."""
+        import torch
+        self.lib.lpp_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        _check(self.lib.lpp_fft3d(self.handle, C.c_void_p(mesh.data_ptr())), "lpp_fft3d")
+
+    def set_profiling(self, on: bool) -> None:
+        _check(self.lib.lpp_set_profiling(self.handle, 1 if on else 0), "lpp_set_profiling")
+        _check(self.lib.lpp_reset_profile(self.handle), "lpp_reset_profile")
+
+    def profile(self) -> Dict[str, tuple]:
+        """{stage: (milliseconds, kernel launches)} accumulated since set_profiling."""
+        n = len(STAGES)
+        ms = (C.c_double * n)()
+        ln = (C.c_int64 * n)()
+        _check(self.lib.lpp_get_profile(self.handle, ms, ln, n), "lpp_get_profile")
+        return {STAGES[i]: (ms[i], ln[i]) for i in range(n)}
+
+    def _dtype(self, cat) -> int:
+        x = cat.x
+        if _is_torch(x):
+            import torch
+            return LPP_F64 if x.dtype == torch.float64 else LPP_F32
+        return LPP_F64 if np.asarray(x).dtype == np.float64 else LPP_F32
+
+
+def version() -> str:
+    return load().lpp_version().decode()

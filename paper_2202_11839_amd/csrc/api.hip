@@ -1,0 +1,861 @@
+// C ABI of liblpp (include/lpp.h): plan validation, workspace, catalog
+// staging and the per-estimate pipeline
+//
+//   FP64 catalog sums (alpha, I, shot noise, input checks)
+//   -> counting sort of the density set (galaxies and randoms, weights w and
+//      -alpha w) and of the shape set (galaxies, weights w*gamma) by tile
+//   -> density base: deposit, FFT, unpack/combine -> B_delta, DD_l0 shells
+//   -> shape base:   deposit (both grids), FFT, combine -> B_gamma, PLUS_l0
+//   -> every other field: deposit, FFT, multiply by its harmonic and by the
+//      base, FP64 shell sums
+//   -> prefactors, normalisation, shot noise and the E/B map on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lpp_internal.h"
+
+using namespace lpp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int64_t igcd(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace
+
+struct lpp_plan_s {
+  lpp_config cfg{};
+  Tables tab;
+  Geometry geo{};
+  hipStream_t stream = nullptr;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  int64_t cap_gal = 0, cap_ran = 0;
+  // small tables owned by the plan
+  void* tabs = nullptr;
+  int64_t* d_thr = nullptr;
+  void* d_tw = nullptr;
+  void* d_phase = nullptr;
+  void* d_invw = nullptr;
+  int device = -1;
+  // per-stage timing with HIP events on the plan's stream
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;     // pairs (start, stop)
+  std::vector<int> ev_stage;      // stage of each pair
+  std::vector<int> ev_launch;     // kernel launches inside each pair
+  size_t ev_used = 0;             // pairs recorded since the last collection
+  double prof_ms[LPP_N_STAGES] = {0};
+  int64_t prof_launches[LPP_N_STAGES] = {0};
+};
+
+namespace {
+
+hipError_t prof_begin(lpp_plan_s* p) {
+  if (!p->prof_on) return hipSuccess;
+  if (2 * (p->ev_used + 1) > p->ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      p->ev.push_back(e);
+    }
+    p->ev_stage.push_back(0);
+    p->ev_launch.push_back(0);
+  }
+  return hipEventRecord(p->ev[2 * p->ev_used], p->stream);
+}
+
+hipError_t prof_end(lpp_plan_s* p, int stage, int launches) {
+  if (!p->prof_on) return hipSuccess;
+  p->ev_stage[p->ev_used] = stage;
+  p->ev_launch[p->ev_used] = launches;
+  const hipError_t r = hipEventRecord(p->ev[2 * p->ev_used + 1], p->stream);
+  ++p->ev_used;
+  return r;
+}
+
+// after the stream has synchronised
+void prof_collect(lpp_plan_s* p) {
+  for (size_t i = 0; i < p->ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) == hipSuccess) {
+      p->prof_ms[p->ev_stage[i]] += ms;
+      p->prof_launches[p->ev_stage[i]] += p->ev_launch[i];
+    }
+  }
+  p->ev_used = 0;
+}
+
+size_t real_size(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? 8 : 4; }
+size_t mesh_bytes(const lpp_plan_s* p) {
+  const size_t n = static_cast<size_t>(p->cfg.mesh_n);
+  return n * n * n * 2 * real_size(p);
+}
+int tile_of_plan(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? kTileF64 : kTileF32; }
+int64_t ntiles(const lpp_plan_s* p) {
+  const int64_t nt = p->cfg.mesh_n / tile_of_plan(p);
+  return nt * nt * nt;
+}
+bool need_density(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_DD | LPP_GD)) != 0; }
+bool need_shape(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_GD | LPP_PLUS | LPP_MINUS)) != 0; }
+int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size()); }
+
+// Workspace layout (offsets in bytes), computed for capacities (ng, nr).
+struct Layout {
+  size_t mesh[4];  // Bd, Bg, W0, W1
+  size_t key_d, fx_d, fy_d, fz_d, wr_d;
+  size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
+  size_t tile_of, rank, counts_d, starts_d, counts_g, starts_g;
+  size_t stage_gal, stage_ran;
+  size_t sums_partial, sums_out;
+  size_t bin_partial, acc;
+  size_t total;
+};
+
+Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  const size_t M = mesh_bytes(p), rs = real_size(p);
+  const bool dn = need_density(p), sh = need_shape(p);
+  const bool il = p->cfg.interlacing != 0;
+  L.mesh[0] = dn ? take(M) : 0;
+  L.mesh[1] = sh ? take(M) : 0;
+  L.mesh[2] = take(M);
+  L.mesh[3] = (sh && il) ? take(M) : 0;
+  const size_t nd = static_cast<size_t>(ng + nr);
+  const size_t gg = static_cast<size_t>(ng);
+  L.key_d = take(4 * nd);
+  L.fx_d = take(rs * nd);
+  L.fy_d = take(rs * nd);
+  L.fz_d = take(rs * nd);
+  L.wr_d = take(rs * nd);
+  L.key_g = take(4 * gg);
+  L.fx_g = take(rs * gg);
+  L.fy_g = take(rs * gg);
+  L.fz_g = take(rs * gg);
+  L.wr_g = take(rs * gg);
+  L.wi_g = take(rs * gg);
+  L.tile_of = take(4 * nd);
+  L.rank = take(4 * nd);
+  const size_t nt = static_cast<size_t>(ntiles(p));
+  L.counts_d = take(4 * nt);
+  L.starts_d = take(4 * (nt + 1));
+  L.counts_g = take(4 * nt);
+  L.starts_g = take(4 * (nt + 1));
+  L.stage_gal = take(8 * 7 * gg);
+  L.stage_ran = take(8 * 5 * static_cast<size_t>(nr));
+  L.sums_partial = take(8 * 8 * static_cast<size_t>(catalog_sum_blocks()));
+  L.sums_out = take(8 * 16);
+  const int nb = p->cfg.n_kbins;
+  L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * bin_blocks(p->cfg.mesh_n));
+  L.acc = take(8 * (2 * static_cast<size_t>(nb) * (n_acc(p) + 1) + 2 * static_cast<size_t>(nb)));
+  L.total = off;
+  return L;
+}
+
+char* wsp(lpp_plan_s* p, size_t off) { return static_cast<char*>(p->ws) + off; }
+
+lpp_status hip_status(hipError_t e) {
+  if (e == hipSuccess) return LPP_OK;
+  if (e == hipErrorOutOfMemory) return LPP_E_NOMEM;
+  return LPP_E_DEVICE;
+}
+
+#define LPP_TRY(expr)                         \
+  do {                                        \
+    const hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
+lpp_status ensure_device(lpp_plan_s* p) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return LPP_E_DEVICE;
+  if (p->device < 0) {
+    int d = 0;
+    LPP_TRY(hipGetDevice(&d));
+    p->device = d;
+  }
+  return LPP_OK;
+}
+
+lpp_status ensure_tables(lpp_plan_s* p) {
+  lpp_status s = ensure_device(p);
+  if (s != LPP_OK) return s;
+  if (p->tabs) return LPP_OK;
+  const int N = p->cfg.mesh_n, nb = p->cfg.n_kbins;
+  const size_t rs = real_size(p);
+  const size_t o_thr = 0;
+  const size_t o_tw = align_up(8 * (nb + 1));
+  const size_t o_ph = o_tw + align_up(2 * rs * N);
+  const size_t o_iw = o_ph + align_up(2 * rs * (3 * N + 1));
+  const size_t total = o_iw + align_up(rs * N);
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + o_thr, p->tab.thr.data(), 8 * (nb + 1));
+  const int pw = p->cfg.assignment;
+  for (int m = 0; m < N; ++m) {
+    const double a = -2.0 * M_PI * m / N;
+    const int n = m < N / 2 ? m : m - N;
+    double w1 = 1.0;
+    if (p->cfg.compensate && n != 0) {
+      const double x = M_PI * n / N;
+      w1 = std::pow(std::sin(x) / x, pw);
+    }
+    if (rs == 8) {
+      double* tw = reinterpret_cast<double*>(host.data() + o_tw);
+      tw[2 * m] = std::cos(a);
+      tw[2 * m + 1] = std::sin(a);
+      reinterpret_cast<double*>(host.data() + o_iw)[m] = 1.0 / w1;
+    } else {
+      float* tw = reinterpret_cast<float*>(host.data() + o_tw);
+      tw[2 * m] = static_cast<float>(std::cos(a));
+      tw[2 * m + 1] = static_cast<float>(std::sin(a));
+      reinterpret_cast<float*>(host.data() + o_iw)[m] = static_cast<float>(1.0 / w1);
+    }
+  }
+  for (int m = 0; m <= 3 * N; ++m) {
+    const double a = -M_PI * (m - 1.5 * N) / N;  // exp(-i pi (nx+ny+nz)/N)
+    if (rs == 8) {
+      double* ph = reinterpret_cast<double*>(host.data() + o_ph);
+      ph[2 * m] = std::cos(a);
+      ph[2 * m + 1] = std::sin(a);
+    } else {
+      float* ph = reinterpret_cast<float*>(host.data() + o_ph);
+      ph[2 * m] = static_cast<float>(std::cos(a));
+      ph[2 * m + 1] = static_cast<float>(std::sin(a));
+    }
+  }
+  void* d = nullptr;
+  LPP_TRY(hipMalloc(&d, total));
+  const hipError_t e = hipMemcpy(d, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_status(e);
+  }
+  p->tabs = d;
+  char* c = static_cast<char*>(d);
+  p->d_thr = reinterpret_cast<int64_t*>(c + o_thr);
+  p->d_tw = c + o_tw;
+  p->d_phase = c + o_ph;
+  p->d_invw = c + o_iw;
+  return LPP_OK;
+}
+
+lpp_status ensure_workspace(lpp_plan_s* p, int64_t ng, int64_t nr) {
+  const Layout L = layout(p, ng, nr);
+  if (p->ws && ng <= p->cap_gal && nr <= p->cap_ran) return LPP_OK;
+  if (p->ws && !p->own_ws) {
+    // caller workspace: must be large enough for this request
+    if (L.total > p->ws_bytes) return LPP_E_WORKSPACE;
+    p->cap_gal = ng;
+    p->cap_ran = nr;
+    return LPP_OK;
+  }
+  if (p->ws && p->own_ws) {
+    (void)hipFree(p->ws);
+    p->ws = nullptr;
+  }
+  void* d = nullptr;
+  if (hipMalloc(&d, L.total) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPP_E_NOMEM;
+  }
+  p->ws = d;
+  p->ws_bytes = L.total;
+  p->own_ws = true;
+  p->cap_gal = ng;
+  p->cap_ran = nr;
+  return LPP_OK;
+}
+
+// Make a device RawCat for a catalog, staging host columns into the workspace.
+lpp_status stage(lpp_plan_s* p, const lpp_catalog* c, size_t stage_off, int ncols_max, RawCat& out) {
+  out = RawCat{c->x, c->y, c->z, c->w, c->nbar, c->g1, c->g2, c->n, c->dtype};
+  if (c->on_device) return LPP_OK;
+  const size_t es = c->dtype == LPP_F64 ? 8 : 4;
+  const size_t col = es * static_cast<size_t>(c->n);
+  char* base = wsp(p, stage_off);
+  const void* src[7] = {c->x, c->y, c->z, c->w, c->nbar, c->g1, c->g2};
+  const void** dst[7] = {&out.x, &out.y, &out.z, &out.w, &out.nbar, &out.g1, &out.g2};
+  int k = 0;
+  for (int i = 0; i < 7; ++i) {
+    if (!src[i]) {
+      *dst[i] = nullptr;
+      continue;
+    }
+    if (k >= ncols_max) return LPP_E_INVALID;
+    char* d = base + static_cast<size_t>(k) * col;
+    LPP_TRY(hipMemcpyAsync(d, src[i], col, hipMemcpyHostToDevice, p->stream));
+    *dst[i] = d;
+    ++k;
+  }
+  return LPP_OK;
+}
+
+lpp_status check_catalog_args(const lpp_catalog* c, bool shapes) {
+  if (!c || c->n < 1 || !c->x || !c->y || !c->z) return LPP_E_INVALID;
+  if (c->dtype != LPP_F32 && c->dtype != LPP_F64) return LPP_E_INVALID;
+  if (shapes && (!c->g1 || !c->g2)) return LPP_E_INVALID;
+  if (c->n > (int64_t{1} << 31) - 1) return LPP_E_UNSUPPORTED;
+  return LPP_OK;
+}
+
+template <typename T>
+ObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
+  ObjSet<T> o{};
+  if (shape_set) {
+    o.key = reinterpret_cast<uint32_t*>(wsp(p, L.key_g));
+    o.fx = reinterpret_cast<T*>(wsp(p, L.fx_g));
+    o.fy = reinterpret_cast<T*>(wsp(p, L.fy_g));
+    o.fz = reinterpret_cast<T*>(wsp(p, L.fz_g));
+    o.wr = reinterpret_cast<T*>(wsp(p, L.wr_g));
+    o.wi = reinterpret_cast<T*>(wsp(p, L.wi_g));
+  } else {
+    o.key = reinterpret_cast<uint32_t*>(wsp(p, L.key_d));
+    o.fx = reinterpret_cast<T*>(wsp(p, L.fx_d));
+    o.fy = reinterpret_cast<T*>(wsp(p, L.fy_d));
+    o.fz = reinterpret_cast<T*>(wsp(p, L.fz_d));
+    o.wr = reinterpret_cast<T*>(wsp(p, L.wr_d));
+    o.wi = nullptr;
+  }
+  o.n = n;
+  return o;
+}
+
+// sort the catalogs (cats[0..k)) into one set; wscale per catalog
+template <typename T>
+lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const double* wscale, int k, bool shape,
+                    ObjSet<T> out) {
+  const int64_t nt = ntiles(p);
+  uint32_t* counts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.counts_g : L.counts_d));
+  uint32_t* starts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.starts_g : L.starts_d));
+  uint32_t* tile_of = reinterpret_cast<uint32_t*>(wsp(p, L.tile_of));
+  uint32_t* rank = reinterpret_cast<uint32_t*>(wsp(p, L.rank));
+  const int tile = tile_of_plan(p);
+  LPP_TRY(prof_begin(p));
+  LPP_TRY(launch_fill_zero(counts, 4 * static_cast<size_t>(nt), p->stream));
+  int64_t off = 0;
+  for (int i = 0; i < k; ++i) {
+    LPP_TRY(launch_tile_count<T>(cats[i], p->geo, tile, counts, rank + off, tile_of + off, p->stream));
+    off += cats[i].n;
+  }
+  LPP_TRY(launch_scan(counts, starts, static_cast<int>(nt), p->stream));
+  off = 0;
+  for (int i = 0; i < k; ++i) {
+    LPP_TRY(launch_scatter<T>(cats[i], p->geo, wscale[i], shape ? 1 : 0, starts, rank + off, tile_of + off, out, 0,
+                              p->stream));
+    off += cats[i].n;
+  }
+  LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2 + 2 * k));
+  return LPP_OK;
+}
+
+// sums[0..8) galaxies, [8..16) randoms (see launch_catalog_sums)
+lpp_status catalog_sums(lpp_plan_s* p, const Layout& L, const RawCat& g, const RawCat* r, double nbar_default,
+                        double* host16) {
+  double* part = reinterpret_cast<double*>(wsp(p, L.sums_partial));
+  double* out = reinterpret_cast<double*>(wsp(p, L.sums_out));
+  LPP_TRY(launch_catalog_sums(g, p->geo, nbar_default, part, catalog_sum_blocks(), out, p->stream));
+  if (r) LPP_TRY(launch_catalog_sums(*r, p->geo, nbar_default, part, catalog_sum_blocks(), out + 8, p->stream));
+  LPP_TRY(hipMemcpyAsync(host16, out, 8 * (r ? 16 : 8), hipMemcpyDeviceToHost, p->stream));
+  LPP_TRY(hipStreamSynchronize(p->stream));
+  return LPP_OK;
+}
+
+lpp_status sums_status(const double* s) {
+  if (s[4] > 0) return LPP_E_NONFINITE;
+  if (s[5] > 0) return LPP_E_OUT_OF_BOX;
+  if (s[6] > 0) return LPP_E_AT_OBSERVER;
+  return LPP_OK;
+}
+
+template <typename T>
+lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out) {
+  const lpp_config& cfg = p->cfg;
+  lpp_status s;
+  if ((s = check_catalog_args(gal, need_shape(p))) != LPP_OK) return s;
+  if ((s = check_catalog_args(ran, false)) != LPP_OK) return s;
+  if (!out || !out->re || !out->im || !out->n_modes || !out->k_eff || !out->k_lo || !out->k_hi) return LPP_E_INVALID;
+  if ((s = ensure_tables(p)) != LPP_OK) return s;
+  if ((s = ensure_workspace(p, gal->n, ran->n)) != LPP_OK) return s;
+  const Layout L = layout(p, p->cap_gal, p->cap_ran);
+  const int N = cfg.mesh_n, nb = cfg.n_kbins;
+  const double vol = cfg.box_size * cfg.box_size * cfg.box_size;
+
+  RawCat rg, rr;
+  lpp_catalog gcat = *gal, rcat = *ran;
+  rcat.g1 = rcat.g2 = nullptr;  // shapes of randoms are ignored
+  if (!need_shape(p)) gcat.g1 = gcat.g2 = nullptr;
+  if ((s = stage(p, &gcat, L.stage_gal, 7, rg)) != LPP_OK) return s;
+  if ((s = stage(p, &rcat, L.stage_ran, 5, rr)) != LPP_OK) return s;
+
+  // FP64 sums; nbar defaults to sum(w_gal)/V
+  double sums[16];
+  if ((s = catalog_sums(p, L, rg, nullptr, 0.0, sums)) != LPP_OK) return s;
+  if ((s = sums_status(sums)) != LPP_OK) return s;
+  const double nbar_default = sums[0] / vol;
+  if ((s = catalog_sums(p, L, rg, &rr, nbar_default, sums)) != LPP_OK) return s;
+  if ((s = sums_status(sums + 8)) != LPP_OK) return s;
+  const double swg = sums[0], swr = sums[8];
+  if (!(swr != 0.0)) return LPP_E_NO_RANDOMS;
+  const double alpha = swg / swr;
+  const double I = alpha * sums[10];
+  if (!(I > 0.0) || !std::isfinite(I)) return LPP_E_NO_RANDOMS;
+  out->alpha = alpha;
+  out->norm_I = I;
+  out->shot_dd = (sums[1] + alpha * alpha * sums[9]) / I;
+  out->shot_plus = sums[3] / I;
+  out->sum_w_gal = swg;
+  out->sum_w_ran = swr;
+
+  const hipStream_t st = p->stream;
+  const size_t M = mesh_bytes(p);
+  void* Bd = wsp(p, L.mesh[0]);
+  void* Bg = wsp(p, L.mesh[1]);
+  void* W0 = wsp(p, L.mesh[2]);
+  void* W1 = wsp(p, L.mesh[3]);
+  const int tile = tile_of_plan(p);
+  const bool il = cfg.interlacing != 0;
+
+  ObjSet<T> setd = objset<T>(p, L, false, gal->n + ran->n);
+  ObjSet<T> setg = objset<T>(p, L, true, gal->n);
+  const uint32_t* starts_d = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d));
+  const uint32_t* starts_g = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_g));
+  if (need_density(p)) {
+    const RawCat cs[2] = {rg, rr};
+    const double ws[2] = {1.0, -alpha};
+    if ((s = sort_set<T>(p, L, cs, ws, 2, false, setd)) != LPP_OK) return s;
+  }
+  if (need_shape(p)) {
+    const double ws[1] = {1.0};
+    if ((s = sort_set<T>(p, L, &rg, ws, 1, true, setg)) != LPP_OK) return s;
+  }
+
+  const int na = n_acc(p);
+  double* acc = reinterpret_cast<double*>(wsp(p, L.acc));  // [na+1][2nb] then counts[nb], ksum[nb]
+  const int scratch = na;                                    // slot for unrequested monopoles
+  double* partial = reinterpret_cast<double*>(wsp(p, L.bin_partial));
+  LPP_TRY(launch_fill_zero(acc, 8 * (2 * static_cast<size_t>(nb) * (na + 1) + 2 * static_cast<size_t>(nb)), st));
+  BinArgs ba{};
+  ba.N = N;
+  ba.nb = nb;
+  ba.interlace = il ? 1 : 0;
+  ba.compensate = cfg.compensate;
+  ba.thr = p->d_thr;
+  ba.phase = p->d_phase;
+  ba.invw = p->d_invw;
+  ba.partial = partial;
+  ba.nblocks = bin_blocks(N);
+  const FieldSpec s0 = make_spec(0, 0, 0, 0);
+  bool counted = false;
+
+  // The base kernels write rows [re, im, cnt, ksum] of width 4*nb; they are
+  // reduced into the scratch slot (followed by the counts slot) and copied to
+  // the host, which places the monopoles and keeps the mode counts.
+  double* tmp4 = acc + static_cast<size_t>(2) * nb * scratch;
+  // kernel groups, each timed as one stage when profiling is on
+  auto zero = [&](void* m) -> hipError_t {
+    hipError_t e = prof_begin(p);
+    if (e == hipSuccess) e = launch_fill_zero(m, M, st);
+    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_OTHER, 1);
+    return e;
+  };
+  auto deposit = [&](const ObjSet<T>& set, const uint32_t* starts, const FieldSpec& f, int mode,
+                     void* m) -> hipError_t {
+    hipError_t e = prof_begin(p);
+    if (e == hipSuccess) e = launch_deposit<T>(set, starts, p->geo, tile, f, mode, m, st);
+    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
+    return e;
+  };
+  auto fft = [&](void* m) -> hipError_t {
+    hipError_t e = prof_begin(p);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, st);
+    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
+    if (e == hipSuccess) e = prof_begin(p);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, st);
+    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
+    return e;
+  };
+  std::vector<double> host_acc;
+  // ---- bases ----
+  // Because the reduce kernel adds full rows, run the bases first into the
+  // scratch slot and copy their re/im parts to the requested slots on the host.
+  std::vector<double> base_dd(2 * nb, 0.0), base_gg(2 * nb, 0.0), counts(nb, 0.0), ksum(nb, 0.0);
+  std::vector<double> tmp(4 * nb);
+  auto fetch_base = [&](std::vector<double>& reim) -> lpp_status {
+    LPP_TRY(launch_fill_zero(tmp4, 8 * 4 * static_cast<size_t>(nb), st));
+    LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 4 * nb, tmp4, st));
+    LPP_TRY(hipMemcpyAsync(tmp.data(), tmp4, 8 * 4 * nb, hipMemcpyDeviceToHost, st));
+    LPP_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < 2 * nb; ++b) reim[b] = tmp[b];
+    if (!counted) {
+      for (int b = 0; b < nb; ++b) {
+        counts[b] = tmp[2 * nb + b];
+        ksum[b] = tmp[3 * nb + b];
+      }
+      counted = true;
+    }
+    return LPP_OK;
+  };
+  if (need_density(p)) {
+    LPP_TRY(zero(W0));
+    LPP_TRY(deposit(setd, starts_d, s0, 0, W0));
+    LPP_TRY(fft(W0));
+    LPP_TRY(prof_begin(p));
+    LPP_TRY(launch_base_dd<T>(ba, W0, Bd, st));
+    LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+    if ((s = fetch_base(base_dd)) != LPP_OK) return s;
+  }
+  if (need_shape(p)) {
+    LPP_TRY(zero(W0));
+    LPP_TRY(deposit(setg, starts_g, s0, 1, W0));
+    LPP_TRY(fft(W0));
+    if (il) {
+      LPP_TRY(zero(W1));
+      LPP_TRY(deposit(setg, starts_g, s0, 2, W1));
+      LPP_TRY(fft(W1));
+    }
+    LPP_TRY(prof_begin(p));
+    LPP_TRY(launch_base_gg<T>(ba, W0, il ? W1 : nullptr, Bg, st));
+    LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+    if ((s = fetch_base(base_gg)) != LPP_OK) return s;
+  }
+  LPP_TRY(launch_fill_zero(acc, 8 * 2 * static_cast<size_t>(nb) * (na + 1), st));
+
+  // ---- all other fields ----
+  for (const Field& f : p->tab.fields) {
+    double* slot = acc + static_cast<size_t>(2) * nb * f.series;
+    if (f.fam == FAM_DD) {
+      LPP_TRY(zero(W0));
+      LPP_TRY(deposit(setd, starts_d, f.spec, 0, W0));
+      LPP_TRY(fft(W0));
+      LPP_TRY(prof_begin(p));
+      LPP_TRY(launch_bin_dd<T>(ba, f.spec, W0, Bd, st));
+      LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+    } else {
+      LPP_TRY(zero(W0));
+      LPP_TRY(deposit(setg, starts_g, f.spec, 1, W0));
+      LPP_TRY(fft(W0));
+      if (il) {
+        LPP_TRY(zero(W1));
+        LPP_TRY(deposit(setg, starts_g, f.spec, 2, W1));
+        LPP_TRY(fft(W1));
+      }
+      const void* base = (f.fam == FAM_GD) ? Bd : Bg;
+      const int kind = (f.fam == FAM_MINUS) ? 1 : 0;
+      LPP_TRY(prof_begin(p));
+      LPP_TRY(launch_bin_gg<T>(ba, f.spec, W0, il ? W1 : nullptr, base, kind, st));
+      LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+    }
+    LPP_TRY(prof_begin(p));
+    LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 2 * nb, slot, st));
+    LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
+  }
+  host_acc.assign(static_cast<size_t>(2) * nb * (na + 1), 0.0);
+  LPP_TRY(hipMemcpyAsync(host_acc.data(), acc, 8 * host_acc.size(), hipMemcpyDeviceToHost, st));
+  LPP_TRY(hipStreamSynchronize(st));
+  prof_collect(p);
+  if (p->tab.dd0 >= 0)
+    for (int b = 0; b < 2 * nb; ++b) host_acc[static_cast<size_t>(2) * nb * p->tab.dd0 + b] = base_dd[b];
+  if (p->tab.plus0 >= 0)
+    for (int b = 0; b < 2 * nb; ++b) host_acc[static_cast<size_t>(2) * nb * p->tab.plus0 + b] = base_gg[b];
+
+  // ---- assembly (FP64, host) ----
+  const double kf = 2.0 * M_PI / cfg.box_size;
+  const double dn = static_cast<double>(cfg.dn_num) / cfg.dn_den;
+  for (int b = 0; b < nb; ++b) {
+    out->n_modes[b] = static_cast<int64_t>(llround(counts[b]));
+    out->k_eff[b] = counts[b] > 0 ? ksum[b] * kf / counts[b] : 0.0;
+    out->k_lo[b] = b * dn * kf;
+    out->k_hi[b] = (b + 1) * dn * kf;
+  }
+  const int ns = static_cast<int>(p->tab.series.size());
+  for (int i = 0; i < ns * nb; ++i) out->re[i] = out->im[i] = 0.0;
+  for (int a = 0; a < na; ++a) {
+    const int fam = p->tab.acc_series[a], Lm = p->tab.acc_L[a];
+    const int m = fam == FAM_GD ? 2 : (fam == FAM_MINUS ? 4 : 0);
+    const double pref = prefactor(m, Lm);
+    const int si = p->tab.series_of_acc[a];
+    for (int b = 0; b < nb; ++b) {
+      const double c = counts[b] > 0 ? counts[b] : 1.0;
+      double re = host_acc[static_cast<size_t>(2) * nb * a + b] * pref / (I * c);
+      const double im = host_acc[static_cast<size_t>(2) * nb * a + nb + b] * pref / (I * c);
+      if (a == p->tab.dd0) re -= out->shot_dd;
+      if (a == p->tab.plus0) re -= out->shot_plus;
+      out->re[si * nb + b] = re;
+      out->im[si * nb + b] = im;
+    }
+  }
+  // E/B: (P_+^(l) +- sum_L C_lL Re P_-^(L)) / 2
+  if ((cfg.spectra & LPP_PLUS) && (cfg.spectra & LPP_MINUS) && cfg.lmax >= 4) {
+    auto idx = [&](const std::string& name) {
+      for (int i = 0; i < ns; ++i)
+        if (p->tab.series[i] == name) return i;
+      return -1;
+    };
+    char nm[32];
+    for (int l = 0; l <= cfg.lmax; l += 2) {
+      std::snprintf(nm, sizeof nm, "PLUS_l%d", l);
+      const int ip = idx(nm);
+      std::snprintf(nm, sizeof nm, "EE_l%d", l);
+      const int ie = idx(nm);
+      std::snprintf(nm, sizeof nm, "BB_l%d", l);
+      const int ib = idx(nm);
+      for (int b = 0; b < nb; ++b) {
+        double mix = 0.0;
+        for (int Lm = 4; Lm <= cfg.lmax; Lm += 2) {
+          std::snprintf(nm, sizeof nm, "MINUS_L%d", Lm);
+          mix += cmap_minus_to_legendre(l, Lm) * out->re[idx(nm) * nb + b];
+        }
+        out->re[ie * nb + b] = 0.5 * (out->re[ip * nb + b] + mix);
+        out->re[ib * nb + b] = 0.5 * (out->re[ip * nb + b] - mix);
+      }
+    }
+  }
+  return LPP_OK;
+}
+
+template <typename T>
+lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* mesh) {
+  lpp_status s;
+  if ((s = check_catalog_args(c, false)) != LPP_OK) return s;
+  if (!mesh) return LPP_E_INVALID;
+  if ((s = ensure_tables(p)) != LPP_OK) return s;
+  if ((s = ensure_workspace(p, std::max<int64_t>(p->cap_gal, 1), std::max(p->cap_ran, c->n))) != LPP_OK) return s;
+  const Layout L = layout(p, p->cap_gal, p->cap_ran);
+  RawCat rc;
+  lpp_catalog cc = *c;
+  cc.g1 = cc.g2 = nullptr;  // only the weights are deposited
+  if ((s = stage(p, &cc, L.stage_ran, 5, rc)) != LPP_OK) return s;
+  double sums[16];
+  if ((s = catalog_sums(p, L, rc, nullptr, 1.0, sums)) != LPP_OK) return s;
+  if ((s = sums_status(sums)) != LPP_OK) return s;
+  ObjSet<T> setd = objset<T>(p, L, false, c->n);
+  const double ws[1] = {scale};
+  if ((s = sort_set<T>(p, L, &rc, ws, 1, false, setd)) != LPP_OK) return s;
+  LPP_TRY(launch_fill_zero(mesh, mesh_bytes(p), p->stream));
+  LPP_TRY(launch_deposit<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, tile_of_plan(p),
+                            make_spec(0, 0, 0, 0), 0, mesh, p->stream));
+  LPP_TRY(hipStreamSynchronize(p->stream));
+  return LPP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lpp_version(void) { return "liblpp 0.1 (gfx950)"; }
+
+const char* lpp_status_string(lpp_status s) {
+  switch (s) {
+    case LPP_OK:
+      return "ok";
+    case LPP_E_INVALID:
+      return "invalid argument or configuration";
+    case LPP_E_NONFINITE:
+      return "non-finite value in a catalog";
+    case LPP_E_OUT_OF_BOX:
+      return "object outside the box";
+    case LPP_E_AT_OBSERVER:
+      return "object at the observer position";
+    case LPP_E_NO_RANDOMS:
+      return "random catalog has zero total weight";
+    case LPP_E_WORKSPACE:
+      return "workspace too small";
+    case LPP_E_NOMEM:
+      return "out of memory";
+    case LPP_E_DEVICE:
+      return "HIP device error or no device";
+    case LPP_E_UNSUPPORTED:
+      return "unsupported request";
+  }
+  return "unknown status";
+}
+
+lpp_status lpp_plan_create(const lpp_config* cfg_in, lpp_plan* out) {
+  if (!cfg_in || !out) return LPP_E_INVALID;
+  *out = nullptr;
+  lpp_config cfg = *cfg_in;
+  const int N = cfg.mesh_n;
+  if (!is_pow2(N) || N < 16 || N > 1024) return LPP_E_INVALID;
+  if (!(cfg.box_size > 0.0) || !std::isfinite(cfg.box_size)) return LPP_E_INVALID;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(cfg.box_origin[i]) || !std::isfinite(cfg.observer[i])) return LPP_E_INVALID;
+  if (cfg.assignment < 1 || cfg.assignment > 3) return LPP_E_INVALID;
+  if ((cfg.interlacing != 0 && cfg.interlacing != 1) || (cfg.compensate != 0 && cfg.compensate != 1))
+    return LPP_E_INVALID;
+  if (cfg.precision != LPP_F32 && cfg.precision != LPP_F64) return LPP_E_INVALID;
+  if (cfg.lmax < 0 || cfg.lmax > 8 || cfg.lmax % 2) return LPP_E_INVALID;
+  if (cfg.spectra == 0 || (cfg.spectra & ~static_cast<uint32_t>(LPP_ALL))) return LPP_E_INVALID;
+  if (cfg.n_kbins < 1 || cfg.n_kbins > 512) return LPP_E_INVALID;
+  if (cfg.dn_num == 0 && cfg.dn_den == 0) {
+    int64_t a = N, b = 2 * static_cast<int64_t>(cfg.n_kbins);
+    const int64_t g = igcd(a, b);
+    cfg.dn_num = static_cast<int32_t>(a / g);
+    cfg.dn_den = static_cast<int32_t>(b / g);
+  }
+  if (cfg.dn_num <= 0 || cfg.dn_den <= 0) return LPP_E_INVALID;
+  // the last edge must not pass the Nyquist frequency: n_kbins * num / den <= N/2
+  if (static_cast<int64_t>(cfg.n_kbins) * cfg.dn_num * 2 > static_cast<int64_t>(N) * cfg.dn_den) return LPP_E_INVALID;
+  // a spectrum needs its multipoles: GD needs lmax >= 2, MINUS needs lmax >= 4
+  if ((cfg.spectra & LPP_GD) && cfg.lmax < 2) return LPP_E_INVALID;
+  if ((cfg.spectra & LPP_MINUS) && cfg.lmax < 4) return LPP_E_INVALID;
+  lpp_plan_s* p = new (std::nothrow) lpp_plan_s();
+  if (!p) return LPP_E_NOMEM;
+  p->cfg = cfg;
+  build_tables(cfg, p->tab);
+  p->geo.N = N;
+  p->geo.p = cfg.assignment;
+  p->geo.interlace = cfg.interlacing;
+  p->geo.H = cfg.box_size / N;
+  p->geo.box = cfg.box_size;
+  for (int i = 0; i < 3; ++i) {
+    p->geo.origin[i] = cfg.box_origin[i];
+    p->geo.rel[i] = cfg.box_origin[i] - cfg.observer[i];
+  }
+  *out = p;
+  return LPP_OK;
+}
+
+lpp_status lpp_plan_destroy(lpp_plan p) {
+  if (!p) return LPP_E_INVALID;
+  if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  if (p->tabs) (void)hipFree(p->tabs);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  delete p;
+  return LPP_OK;
+}
+
+lpp_status lpp_workspace_size(lpp_plan p, int64_t max_gal, int64_t max_ran, size_t* bytes) {
+  if (!p || !bytes || max_gal < 1 || max_ran < 1) return LPP_E_INVALID;
+  *bytes = layout(p, max_gal, max_ran).total;
+  return LPP_OK;
+}
+
+lpp_status lpp_set_workspace(lpp_plan p, void* ptr, size_t bytes) {
+  if (!p || !ptr || (reinterpret_cast<uintptr_t>(ptr) % kAlign) != 0) return LPP_E_INVALID;
+  if (p->own_ws && p->ws) (void)hipFree(p->ws);
+  p->ws = ptr;
+  p->ws_bytes = bytes;
+  p->own_ws = false;
+  p->cap_gal = p->cap_ran = 0;
+  return LPP_OK;
+}
+
+lpp_status lpp_set_stream(lpp_plan p, void* stream) {
+  if (!p) return LPP_E_INVALID;
+  p->stream = static_cast<hipStream_t>(stream);
+  return LPP_OK;
+}
+
+lpp_status lpp_result_layout(lpp_plan p, int32_t* n_series, int32_t* n_kbins) {
+  if (!p || !n_series || !n_kbins) return LPP_E_INVALID;
+  *n_series = static_cast<int32_t>(p->tab.series.size());
+  *n_kbins = p->cfg.n_kbins;
+  return LPP_OK;
+}
+
+const char* lpp_series_name(lpp_plan p, int32_t i) {
+  if (!p || i < 0 || i >= static_cast<int32_t>(p->tab.series.size())) return nullptr;
+  return p->tab.series[i].c_str();
+}
+
+lpp_status lpp_estimate(lpp_plan p, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out) {
+  if (!p) return LPP_E_INVALID;
+  try {
+    return p->cfg.precision == LPP_F64 ? run_estimate<double>(p, gal, ran, out) : run_estimate<float>(p, gal, ran, out);
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
+}
+
+lpp_status lpp_estimate_batch(lpp_plan p, int32_t n, const lpp_catalog* gals, const lpp_catalog* rans,
+                              lpp_result* outs, lpp_status* per) {
+  if (!p || n < 0 || (n > 0 && (!gals || !rans || !outs || !per))) return LPP_E_INVALID;
+  // size the workspace once for the largest catalog
+  int64_t mg = 1, mr = 1;
+  for (int i = 0; i < n; ++i) {
+    mg = std::max(mg, gals[i].n);
+    mr = std::max(mr, rans[i].n);
+  }
+  if (n > 0 && ensure_device(p) == LPP_OK) (void)ensure_workspace(p, mg, mr);
+  lpp_status first = LPP_OK;
+  for (int i = 0; i < n; ++i) {
+    per[i] = lpp_estimate(p, &gals[i], &rans[i], &outs[i]);
+    if (per[i] != LPP_OK && first == LPP_OK) first = per[i];
+  }
+  return first;
+}
+
+lpp_status lpp_deposit_weights(lpp_plan p, const lpp_catalog* cat, double scale, void* mesh) {
+  if (!p) return LPP_E_INVALID;
+  try {
+    return p->cfg.precision == LPP_F64 ? run_deposit<double>(p, cat, scale, mesh)
+                                       : run_deposit<float>(p, cat, scale, mesh);
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
+}
+
+lpp_status lpp_set_profiling(lpp_plan p, int32_t on) {
+  if (!p || (on != 0 && on != 1)) return LPP_E_INVALID;
+  p->prof_on = on != 0;
+  return LPP_OK;
+}
+
+lpp_status lpp_get_profile(lpp_plan p, double* ms, int64_t* launches, int32_t n) {
+  if (!p || !ms || !launches || n < 0) return LPP_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    ms[i] = i < LPP_N_STAGES ? p->prof_ms[i] : 0.0;
+    launches[i] = i < LPP_N_STAGES ? p->prof_launches[i] : 0;
+  }
+  return LPP_OK;
+}
+
+lpp_status lpp_reset_profile(lpp_plan p) {
+  if (!p) return LPP_E_INVALID;
+  for (int i = 0; i < LPP_N_STAGES; ++i) {
+    p->prof_ms[i] = 0.0;
+    p->prof_launches[i] = 0;
+  }
+  p->ev_used = 0;
+  return LPP_OK;
+}
+
+lpp_status lpp_fft3d(lpp_plan p, void* mesh) {
+  if (!p || !mesh) return LPP_E_INVALID;
+  lpp_status s = ensure_tables(p);
+  if (s != LPP_OK) return s;
+  const hipError_t e = p->cfg.precision == LPP_F64 ? launch_fft3d<double>(mesh, p->cfg.mesh_n, p->d_tw, p->stream)
+                                                   : launch_fft3d<float>(mesh, p->cfg.mesh_n, p->d_tw, p->stream);
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(hipStreamSynchronize(p->stream));
+}
+
+}  // extern "C"

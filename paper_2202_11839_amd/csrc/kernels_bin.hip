@@ -1,0 +1,386 @@
+// k-shell binning of the transformed fields.
+//
+// For every mode n the kernels form the compensated, interlaced transform
+//   F(k) = [F1(k) + exp(-i k.s) F2(k)] / (2 W_p(k))      (F1 alone without interlacing)
+// multiply it by the degree-L real harmonic h_a(khat) of the field and by the
+// base field (conj(B(k)) for delta-delta, plus and cross; B(-k) for minus),
+// and accumulate the real and imaginary parts per shell in FP64 (Sec. III.A,
+// eqs. lpp_dens_app, lpp_estimator_cross_Xiij, lpp_estimator_auto_+/-).
+//
+// Each thread walks runs of 8 consecutive x-modes (one 64-byte load per mesh
+// for float2), keeps a running FP64 sum while the shell index stays the same
+// and flushes it to an LDS accumulator on change; the block's accumulators go
+// to a per-block partial row that a second kernel reduces in block order.
+//
+// Density fields are real: their two interlaced copies are packed as the real
+// and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
+// with F1(k) = [P(k) + P*(-k)]/2, F2(k) = [P(k) - P*(-k)]/(2i).  Those kernels
+// walk half of k-space (z-index < N/2 with the usual tie-breaks on the
+// z = 0 and y = 0 planes) and count each mode pair (k, -k) twice.
+#include "lpp_internal.h"
+
+namespace lpp {
+
+namespace {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<float> {
+  using type = float2;
+};
+template <>
+struct V2<double> {
+  using type = double2;
+};
+
+template <typename T2>
+__device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+  return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T2>
+__device__ __forceinline__ T2 cmulc(T2 a, T2 b) {  // a * conj(b)
+  return T2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+constexpr int kBinThreads = 256;
+constexpr int kRun = 8;
+constexpr int kMaxBins = 512;
+
+template <typename T>
+struct KSpec {  // h_{L,M,cs}(khat) = Q_{LM}(khat_z) Re|Im (khat_x + i khat_y)^M
+  int M, cs, nq;
+  T q[9];
+};
+
+template <typename T>
+KSpec<T> kspec_of(const FieldSpec& f) {
+  KSpec<T> k{};
+  k.M = f.M;
+  k.cs = f.cs;
+  k.nq = f.nq[0];
+  for (int i = 0; i < 9; ++i) k.q[i] = static_cast<T>(f.q[0][i]);
+  return k;
+}
+
+template <typename T>
+__device__ __forceinline__ T harmonic(const KSpec<T>& h, T kx, T ky, T kz) {
+  T Q = 0;
+  for (int i = h.nq - 1; i >= 0; --i) Q = Q * kz + h.q[i];
+  T er = 1, ei = 0;
+  for (int m = 0; m < h.M; ++m) {
+    const T t = er * kx - ei * ky;
+    ei = er * ky + ei * kx;
+    er = t;
+  }
+  return Q * (h.cs ? ei : er);
+}
+
+__device__ __forceinline__ int sgn_mode(int i, int N) { return i < N / 2 ? i : i - N; }
+
+// Shell of |n|^2 = q (q > 0), or -1.  thr is in LDS.
+__device__ __forceinline__ int shell_of(int q, const int* thr, int nb, float inv_dn) {
+  if (q <= 0 || q >= thr[nb]) return -1;
+  int b = static_cast<int>(sqrtf(static_cast<float>(q)) * inv_dn);
+  b = b < 0 ? 0 : (b >= nb ? nb - 1 : b);
+  while (b + 1 < nb && thr[b + 1] <= q) ++b;
+  while (b > 0 && thr[b] > q) --b;
+  return b;
+}
+
+struct Acc {
+  int cur;
+  double re, im, cnt, ks;
+};
+
+template <bool COUNTS>
+__device__ __forceinline__ void acc_add(Acc& a, int b, double re, double im, double cnt, double ks, double* sre,
+                                        double* sim, double* scnt, double* sks) {
+  if (b != a.cur) {
+    if (a.cur >= 0) {
+      atomicAdd(&sre[a.cur], a.re);
+      atomicAdd(&sim[a.cur], a.im);
+      if (COUNTS) {
+        atomicAdd(&scnt[a.cur], a.cnt);
+        atomicAdd(&sks[a.cur], a.ks);
+      }
+    }
+    a.cur = b;
+    a.re = a.im = a.cnt = a.ks = 0.0;
+  }
+  a.re += re;
+  a.im += im;
+  if (COUNTS) {
+    a.cnt += cnt;
+    a.ks += ks;
+  }
+}
+
+template <bool COUNTS>
+__device__ __forceinline__ void acc_flush(Acc& a, double* sre, double* sim, double* scnt, double* sks) {
+  if (a.cur >= 0) {
+    atomicAdd(&sre[a.cur], a.re);
+    atomicAdd(&sim[a.cur], a.im);
+    if (COUNTS) {
+      atomicAdd(&scnt[a.cur], a.cnt);
+      atomicAdd(&sks[a.cur], a.ks);
+    }
+  }
+  a.cur = -1;
+}
+
+// shared-memory layout: thr[kMaxBins+1] ints, then 4*nb doubles
+struct Smem {
+  int thr[kMaxBins + 1];
+  double v[4 * kMaxBins];
+};
+
+__device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb) {
+  for (int i = threadIdx.x; i <= nb; i += blockDim.x) s.thr[i] = static_cast<int>(thr[i]);
+  for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) s.v[i] = 0.0;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void smem_store(const Smem& s, double* partial, int width) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(blockIdx.x) * width + i] = s.v[i];
+}
+
+// combined, compensated transform at mode (ix,iy,iz) from the two copies
+template <typename T, typename T2>
+__device__ __forceinline__ T2 combine(T2 f1, T2 f2, int interlace, const T2* phase, int phidx, T invw) {
+  if (interlace) {
+    const T2 ph = phase[phidx];
+    const T2 s = cmul(ph, f2);
+    return T2{static_cast<T>(0.5) * (f1.x + s.x) * invw, static_cast<T>(0.5) * (f1.y + s.y) * invw};
+  }
+  return T2{f1.x * invw, f1.y * invw};
+}
+
+// ---- density fields (packed pair of real copies), half k-space ----
+template <typename T, bool BASE>
+__global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T> h,
+                                                             const typename V2<T>::type* __restrict__ P,
+                                                             typename V2<T>::type* __restrict__ B) {
+  using T2 = typename V2<T>::type;
+  __shared__ Smem s;
+  const int N = a.N, nb = a.nb;
+  smem_init(s, a.thr, nb);
+  double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(s.thr[nb]));
+  const int mask = N - 1;
+  const int64_t runs_per_row = N / kRun;
+  const int64_t nruns = runs_per_row * N * (N / 2);
+  Acc acc{-1, 0, 0, 0, 0};
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x0 = static_cast<int>(r % runs_per_row) * kRun;
+    const int iy = static_cast<int>((r / runs_per_row) % N);
+    const int iz = static_cast<int>(r / (runs_per_row * N));
+    const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
+    if (iz == 0 && !(iy < N / 2)) continue;  // z=0 plane: y in [0, N/2)
+    const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
+    const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
+    const T wyz = invw[iy] * invw[iz];
+    T2 pv[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) pv[j] = P[row + x0 + j];
+    T2 bv[kRun];
+    if (!BASE) {
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) bv[j] = B[row + x0 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const int ix = x0 + j;
+      const int nx = sgn_mode(ix, N);
+      if (iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2)) continue;  // y=0 line: x in (0, N/2)
+      const int q = nx * nx + ny * ny + nz * nz;
+      const int b = shell_of(q, s.thr, nb, inv_dn);
+      const T2 pm = P[mrow + ((N - ix) & mask)];
+      // unpack the two real copies
+      const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
+      const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
+      const T2 F = combine<T, T2>(f1, f2, a.interlace, phase, nx + ny + nz + 3 * N / 2, wyz * invw[ix]);
+      if (BASE) {
+        if (q > 0) {
+          B[row + ix] = F;
+          B[mrow + ((N - ix) & mask)] = T2{F.x, -F.y};
+        }
+        if (b >= 0)
+          acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
+                        2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+      } else if (b >= 0) {
+        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+        const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
+        // 2 Re[h F conj(B)]
+        const double v = 2.0 * static_cast<double>(hk * (F.x * bv[j].x + F.y * bv[j].y));
+        acc_add<false>(acc, b, v, 0.0, 0.0, 0.0, sre, sim, scnt, sks);
+      }
+    }
+  }
+  if (BASE)
+    acc_flush<true>(acc, sre, sim, scnt, sks);
+  else
+    acc_flush<false>(acc, sre, sim, scnt, sks);
+  smem_store(s, a.partial, (BASE ? 4 : 2) * nb);
+}
+
+// ---- complex (shape) fields, full k-space ----
+// KIND 0: h G conj(B(k)); KIND 1: h G B(-k); KIND 2: base construction (B = G, |G|^2)
+template <typename T, int KIND>
+__global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T> h,
+                                                             const typename V2<T>::type* __restrict__ G1,
+                                                             const typename V2<T>::type* __restrict__ G2,
+                                                             typename V2<T>::type* __restrict__ B) {
+  using T2 = typename V2<T>::type;
+  __shared__ Smem s;
+  const int N = a.N, nb = a.nb;
+  smem_init(s, a.thr, nb);
+  double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(s.thr[nb]));
+  const int mask = N - 1;
+  const int64_t runs_per_row = N / kRun;
+  const int64_t nruns = runs_per_row * N * N;
+  Acc acc{-1, 0, 0, 0, 0};
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int x0 = static_cast<int>(r % runs_per_row) * kRun;
+    const int iy = static_cast<int>((r / runs_per_row) % N);
+    const int iz = static_cast<int>(r / (runs_per_row * N));
+    const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
+    const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
+    const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
+    const T wyz = invw[iy] * invw[iz];
+    T2 g1[kRun], g2[kRun], bv[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) g1[j] = G1[row + x0 + j];
+    if (a.interlace) {
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) g2[j] = G2[row + x0 + j];
+    }
+    if (KIND == 0) {
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) bv[j] = B[row + x0 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const int ix = x0 + j;
+      const int nx = sgn_mode(ix, N);
+      const int q = nx * nx + ny * ny + nz * nz;
+      const int b = shell_of(q, s.thr, nb, inv_dn);
+      const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, phase, nx + ny + nz + 3 * N / 2,
+                                  wyz * invw[ix]);
+      if (KIND == 2) {
+        B[row + ix] = F;
+        if (b >= 0)
+          acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
+                        sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+        continue;
+      }
+      if (b < 0) continue;
+      const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+      const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
+      T2 p;
+      if (KIND == 0) {
+        p = cmulc(F, bv[j]);
+      } else {
+        const T2 bm = B[mrow + ((N - ix) & mask)];
+        p = cmul(F, bm);
+      }
+      acc_add<false>(acc, b, static_cast<double>(hk * p.x), static_cast<double>(hk * p.y), 0.0, 0.0, sre, sim, scnt,
+                     sks);
+    }
+  }
+  if (KIND == 2)
+    acc_flush<true>(acc, sre, sim, scnt, sks);
+  else
+    acc_flush<false>(acc, sre, sim, scnt, sks);
+  smem_store(s, a.partial, (KIND == 2 ? 4 : 2) * nb);
+}
+
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, int nblocks, int width,
+                                       double* __restrict__ acc) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= width) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[static_cast<int64_t>(b) * width + w];
+  acc[w] += s;
+}
+
+}  // namespace
+
+int bin_blocks(int N) {
+  const int64_t runs = static_cast<int64_t>(N) * N * N / kRun;
+  int64_t want = (runs + kBinThreads - 1) / kBinThreads;
+  if (want > 2048) want = 2048;
+  if (want < 1) want = 1;
+  return static_cast<int>(want);
+}
+
+template <typename T>
+hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  if (a.nb > kMaxBins) return hipErrorInvalidValue;
+  KSpec<T> h{};
+  bin_dd_kernel<T, true><<<a.nblocks, kBinThreads, 0, st>>>(a, h, static_cast<const T2*>(packed),
+                                                              static_cast<T2*>(base));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  if (a.nb > kMaxBins) return hipErrorInvalidValue;
+  KSpec<T> h{};
+  bin_gg_kernel<T, 2><<<a.nblocks, kBinThreads, 0, st>>>(a, h, static_cast<const T2*>(g1),
+                                                          static_cast<const T2*>(g2), static_cast<T2*>(base));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
+                         hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  if (a.nb > kMaxBins) return hipErrorInvalidValue;
+  bin_dd_kernel<T, false><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(packed),
+                                                               const_cast<T2*>(static_cast<const T2*>(base)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
+                         int kind, hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  if (a.nb > kMaxBins) return hipErrorInvalidValue;
+  T2* b = const_cast<T2*>(static_cast<const T2*>(base));
+  if (kind == 0)
+    bin_gg_kernel<T, 0><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
+                                                            static_cast<const T2*>(g2), b);
+  else
+    bin_gg_kernel<T, 1><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
+                                                            static_cast<const T2*>(g2), b);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st) {
+  reduce_partials_kernel<<<(width + 127) / 128, 128, 0, st>>>(partial, nblocks, width, acc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_base_dd<float>(const BinArgs&, const void*, void*, hipStream_t);
+template hipError_t launch_base_dd<double>(const BinArgs&, const void*, void*, hipStream_t);
+template hipError_t launch_base_gg<float>(const BinArgs&, const void*, const void*, void*, hipStream_t);
+template hipError_t launch_base_gg<double>(const BinArgs&, const void*, const void*, void*, hipStream_t);
+template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
+template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
+template hipError_t launch_bin_gg<float>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*, int,
+                                         hipStream_t);
+template hipError_t launch_bin_gg<double>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*,
+                                          int, hipStream_t);
+
+}  // namespace lpp

@@ -1,0 +1,165 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of liblpp.  Nothing here crosses the C ABI (include/lpp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lpp.h"
+
+namespace lpp {
+
+// ---------------------------------------------------------------------------
+// Line-of-sight weights of one FFT field.
+//
+// The LPP kernels of the estimators are (k.m)^s d^s L_L/dmu^s (k.xhat) with
+// m = e_theta - i e_phi, i.e. exp(-i s phi_{k,x}) L^s_L(k.xhat) (Sec. III.A,
+// eqs. def_of_Xiij and def_of_Xiijkl; s = 0 for the Legendre moments).  By
+// the rotation identity of App. E (eq. spherical_harmonics_identity) this is,
+// as a function of khat, a degree-L spherical harmonic, and it factorises
+// exactly as
+//
+//   sum_a kappa_a h_a(khat) * s! [t^s] h_a(xhat + t m)
+//
+// over the 2L+1 real harmonic polynomials h_{L,M,cos|sin}(y) =
+// Q_{LM}(y_z) Re|Im (y_x + i y_y)^M with Q_{LM} = d^M L_L/dz^M, kappa_{L0} = 1,
+// kappa_{LM} = 2 (L-M)!/(L+M)! (the Legendre addition theorem, eq.
+// spherical_hamornics_hand), because y = xhat + t m stays on the complex unit
+// sphere y.y = 1.  The t-expansion has the closed form used by the deposit
+// kernel: with c = cos(theta), s = sin(theta),
+//   y_x + i y_y = e^{i phi} (s + t (1+c)),  y_x - i y_y = e^{-i phi} (s - t (1-c)),
+//   y_z = c - t s.
+// One FFT field per (s, L, M, cos|sin): 2L+1 fields per (s, L).
+struct FieldSpec {
+  int32_t s, L, M, cs;     // spin 0/2/4, degree, order, 0 = cos part, 1 = sin part
+  int32_t nq[5];           // number of coefficients in q[j]
+  double q[5][9];          // (-1)^j / j! d^{M+j} L_L / dz^{M+j}, power basis, j = 0..s
+  double binom[5];         // binom(M, s - j)
+  double scale;            // kappa_{LM} * s!
+};
+
+// Family of a field and the series it accumulates into.
+enum Family { FAM_DD = 0, FAM_GD = 1, FAM_PLUS = 2, FAM_MINUS = 3 };
+
+struct Field {
+  Family fam;
+  int series;              // index into the accumulator series
+  FieldSpec spec;
+};
+
+// Host tables built once per plan.
+struct Tables {
+  std::vector<std::string> series;   // output series names (incl. EE/BB)
+  std::vector<int> acc_series;       // for each accumulated series: family
+  std::vector<int> acc_L;            // and multipole
+  std::vector<int> series_of_acc;    // output index of each accumulated series
+  std::vector<Field> fields;         // all fields with L > 0 (bases are separate)
+  std::vector<int64_t> thr;          // thresholds T_0..T_nb
+  int dd0 = -1, plus0 = -1;          // accumulator index of DD_l0 and PLUS_l0
+};
+
+bool build_tables(const lpp_config& cfg, Tables& t);
+FieldSpec make_spec(int s, int L, int M, int cs);
+double prefactor(int m, int L);                 // (2L+1)(L-m)!/(L+m)!
+double cmap_minus_to_legendre(int l, int L);    // (2l+1) int dmu/2 L^4_L L_l
+
+// ---------------------------------------------------------------------------
+// Device-side object records (structure of arrays, sorted by tile).
+template <typename T>
+struct ObjSet {
+  uint32_t* key;           // packed cell: cx | cy << 10 | cz << 20
+  T* fx;                   // fractional position in the cell, [0, 1)
+  T* fy;
+  T* fz;
+  T* wr;                   // weight (density set) or w*g1 (shape set)
+  T* wi;                   // w*g2 (shape set), unused for the density set
+  int64_t n;
+};
+
+// Raw catalog columns on the device, in their own dtype.
+struct RawCat {
+  const void* x;
+  const void* y;
+  const void* z;
+  const void* w;
+  const void* nbar;
+  const void* g1;
+  const void* g2;
+  int64_t n;
+  int dtype;
+};
+
+struct Geometry {
+  int N;
+  int p;                   // assignment order
+  int interlace;
+  double H;
+  double origin[3];
+  double rel[3];           // origin - observer
+  double box;
+};
+
+// tile edge of the sorted deposit (cells)
+constexpr int kTileF32 = 16;
+constexpr int kTileF64 = 8;
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// FP64 sums over a catalog: [0] sum w, [1] sum w^2, [2] sum w^2 nbar, [3] sum w^2 |g|^2,
+// [4] count of non-finite, [5] out of box, [6] at observer (as doubles).
+hipError_t launch_catalog_sums(const RawCat& c, const Geometry& g, double nbar_default, double* partial,
+                               int nblocks, double* out, hipStream_t st);
+int catalog_sum_blocks();
+
+template <typename T>
+hipError_t launch_tile_count(const RawCat& c, const Geometry& g, int tile, uint32_t* counts, uint32_t* rank,
+                             uint32_t* tile_of, hipStream_t st);
+hipError_t launch_scan(const uint32_t* counts, uint32_t* starts, int n, hipStream_t st);
+template <typename T>
+hipError_t launch_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
+                          const uint32_t* rank, const uint32_t* tile_of, ObjSet<T> out, int64_t offset,
+                          hipStream_t st);
+
+// Deposit one field onto a complex mesh.  mode 0: packed real field (grid ->
+// real part, interlaced grid -> imaginary part); mode 1: complex field on the
+// grid; mode 2: complex field on the interlaced grid.
+template <typename T>
+hipError_t launch_deposit(const ObjSet<T>& o, const uint32_t* starts, const Geometry& g, int tile,
+                          const FieldSpec& f, int mode, void* mesh, hipStream_t st);
+
+template <typename T>
+hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st);
+// one axis (0: x, unit stride; 1: y; 2: z) of the 3D transform
+template <typename T>
+hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, hipStream_t st);
+
+// Binning.  Tables: twiddles (N complex, exp(-2 pi i m/N)), phase (3N+1
+// complex, exp(-i pi m/N) for m = -3N/2..3N/2), invw (N reals, 1/W_1(n)).
+struct BinArgs {
+  int N, nb, interlace, compensate;
+  const int64_t* thr;      // device thresholds [nb+1]
+  const void* phase;
+  const void* invw;
+  double* partial;         // [nblocks][width]
+  int nblocks;
+};
+int bin_blocks(int N);
+template <typename T>
+hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st);
+template <typename T>
+hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st);
+template <typename T>
+hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
+                         hipStream_t st);
+// kind 0: G conj(B(k)) (plus / cross), 1: G B(-k) (minus)
+template <typename T>
+hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
+                         int kind, hipStream_t st);
+// acc[0..width) += sum over blocks of partial (fixed order)
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st);
+
+}  // namespace lpp

@@ -1,0 +1,246 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 path <= 1e-9 of the per-bin scale; FP32 path <= 1e-4 of the
+per-bin scale, where the scale of a series is the auto power of the fields
+in its product before shot-noise subtraction (DD: P_dd^(0) + N_dd; PLUS,
+MINUS, EE, BB: P_+^(0) + N_+; GD: their geometric mean).  Mode counts are
+compared bit-exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import estimator as E, mesh as M
+from synth import Catalog, box_uniform
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lpp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2202_11839_amd as pkg
+    pkg.load()
+    return pkg
+
+
+def _cats(seed, ng, nr, origin, box, wfun=True, margin=0.0):
+    rng = np.random.default_rng(seed)
+    o = np.asarray(origin) + margin
+    gp = box_uniform(ng, rng, o, box - 2 * margin)
+    rp = box_uniform(nr, rng, o, box - 2 * margin)
+    w_g = rng.random(ng) + 0.5 if wfun else np.ones(ng)
+    w_r = rng.random(nr) + 0.5 if wfun else np.ones(nr)
+    g = Catalog(gp[:, 0], gp[:, 1], gp[:, 2], w_g, np.full(ng, 2e-3), 0.3 * rng.standard_normal(ng),
+                0.3 * rng.standard_normal(ng))
+    r = Catalog(rp[:, 0], rp[:, 1], rp[:, 2], w_r, np.full(nr, 2e-3))
+    return g, r
+
+
+def _scales(ref):
+    s = ref["series"]
+    dd = ref["re"][s.index("DD_l0")] + ref["shot_dd"] if "DD_l0" in s else None
+    pp = ref["re"][s.index("PLUS_l0")] + ref["shot_plus"] if "PLUS_l0" in s else None
+    out = []
+    for name in s:
+        if name.startswith("DD"):
+            out.append(np.abs(dd))
+        elif name.startswith("GD"):
+            out.append(np.sqrt(np.abs(dd * pp)))
+        else:
+            out.append(np.abs(pp))
+    return np.array(out)
+
+
+def _compare(got, ref, tol):
+    assert got["series"] == ref["series"]
+    assert list(got["n_modes"]) == list(ref["n_modes"]), (got["n_modes"], ref["n_modes"])
+    for k in ("alpha", "norm_I", "shot_dd", "shot_plus", "sum_w_gal", "sum_w_ran"):
+        assert abs(got[k] - ref[k]) <= 1e-10 * abs(ref[k]), k
+    np.testing.assert_allclose(got["k_lo"], ref["k_lo"], rtol=1e-13)
+    sel = ref["n_modes"] > 0
+    np.testing.assert_allclose(got["k_eff"][sel], ref["k_eff"][sel], rtol=1e-12)
+    sc = _scales(ref)
+    err_re = np.abs(got["re"] - ref["re"])[:, sel] / sc[:, sel]
+    err_im = np.abs(got["im"] - ref["im"])[:, sel] / sc[:, sel]
+    worst = max(err_re.max(), err_im.max())
+    if worst > tol:
+        i, b = np.unravel_index(np.argmax(np.maximum(err_re, err_im)), err_re.shape)
+        raise AssertionError(f"series {ref['series'][i]} bin {b}: rel err {worst:.3e} > {tol:.1e}")
+    return worst
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fft3d_matches_numpy(lpp, n, prec):
+    import torch
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, n, n)) + 1j * rng.standard_normal((n, n, n))
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    t = torch.tensor(a, dtype=dt, device="cuda").contiguous()
+    plan = lpp.Plan(n, 1.0, (0.0, 0.0, 0.0), (-1.0, -1.0, -1.0), precision=prec, n_kbins=1)
+    plan.fft3d(t)
+    want = np.fft.fftn(a)
+    got = t.cpu().numpy()
+    rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    assert rel < (1e-12 if prec == "f64" else 3e-6), rel
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("il", [0, 1])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_deposit_matches_oracle(lpp, p, il, prec):
+    import torch
+    n, box, origin = 32, 64.0, (-7.0, 3.0, 11.0)
+    g, _ = _cats(100 + p, 5000, 10, origin, box)
+    plan = lpp.Plan(n, box, origin, (-100.0, -100.0, -100.0), assignment=p, interlacing=il, precision=prec,
+                    n_kbins=4)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    mesh = torch.empty((n, n, n), dtype=dt, device="cuda")
+    plan.deposit_weights(g, -0.75, mesh)
+    got = mesh.cpu().numpy().transpose(2, 1, 0)  # [z, y, x] -> [x, y, z]
+    pos = g.pos()
+    want = M.deposit(pos, -0.75 * g.w, n, box, origin, p)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert np.max(np.abs(got.real - want)) <= tol * np.max(np.abs(want))
+    if il:
+        want2 = M.deposit(pos, -0.75 * g.w, n, box, origin, p, shift=0.5)
+        assert np.max(np.abs(got.imag - want2)) <= tol * np.max(np.abs(want2))
+    else:
+        assert np.all(got.imag == 0)
+
+
+# ---------------------------------------------------------------------------
+# the whole estimator
+
+CASES = [
+    # (mesh, box, origin, observer, p, il, comp, lmax, nb, ng, nr)
+    (16, 100.0, (300.0, 200.0, 250.0), (0.0, 0.0, 0.0), 3, 1, 1, 4, 6, 800, 3000),
+    (32, 150.0, (300.0, 200.0, 250.0), (0.0, 0.0, 0.0), 2, 0, 1, 4, 10, 3000, 9001),
+    (32, 80.0, (20.0, -30.0, 10.0), (0.0, 0.0, 0.0), 3, 1, 1, 4, 16, 2001, 7003),   # wide angle, near observer
+    (16, 60.0, (-30.0, -30.0, 5.0), (0.0, 0.0, 0.0), 1, 0, 0, 4, 8, 500, 1500),     # NGP, no compensation
+    (16, 60.0, (40.0, -70.0, -20.0), (0.0, 0.0, 0.0), 2, 1, 1, 8, 8, 700, 2100),    # lmax = 8
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_estimate_matches_oracle(lpp, case, prec):
+    n, box, origin, obs, p, il, comp, lmax, nb, ng, nr = CASES[case]
+    g, r = _cats(7 + case, ng, nr, origin, box)
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=obs, assignment=p, interlacing=il, compensate=comp,
+                   lmax=lmax, n_kbins=nb)
+    ref = E.mesh64(g, r, cfg)
+    plan = lpp.Plan(n, box, origin, obs, assignment=p, interlacing=il, compensate=comp, precision=prec, lmax=lmax,
+                    n_kbins=nb)
+    got = plan.estimate(g, r)
+    _compare(got, ref, 1e-9 if prec == "f64" else 1e-4)
+
+
+def test_estimate_spectra_subsets(lpp):
+    n, box, origin = 16, 90.0, (100.0, 50.0, -40.0)
+    g, r = _cats(55, 900, 2500, origin, box)
+    for fams, mask in ((("DD",), 1), (("GD",), 2), (("PLUS",), 4), (("PLUS", "MINUS"), 12), (("DD", "GD"), 3)):
+        cfg = E.Config(mesh=n, box=box, origin=origin, assignment=3, interlacing=1, lmax=4, n_kbins=6,
+                       families=fams)
+        ref = E.mesh64(g, r, cfg)
+        plan = lpp.Plan(n, box, origin, assignment=3, interlacing=1, precision="f64", lmax=4, n_kbins=6, spectra=mask)
+        got = plan.estimate(g, r)
+        assert got["series"] == ref["series"]
+        sel = ref["n_modes"] > 0
+        for i, s in enumerate(ref["series"]):
+            sc = np.abs(ref["re"][i][sel]).max() + 1e-300
+            assert np.max(np.abs(got["re"][i] - ref["re"][i])[sel]) <= 1e-9 * sc, (fams, s)
+
+
+def test_c1_workload_fp64_and_fp32(lpp):
+    """The 32^3 plain-estimator workload (5,000 galaxies from a GRF with tidal shapes,
+    50,000 randoms, CIC, l <= 4, 16 bins) against the oracle."""
+    from synth import WORKLOADS, make_catalogs
+    wl = WORKLOADS["c1"]
+    g, r = make_catalogs(wl, mock=0)
+    cfg = E.Config(mesh=wl["mesh"], box=wl["box"], origin=wl["origin"], observer=wl["observer"],
+                   assignment=wl["assignment"], interlacing=wl["interlacing"], lmax=4, n_kbins=wl["n_kbins"])
+    ref = E.mesh64(g, r, cfg)
+    for prec, tol in (("f64", 1e-9), ("f32", 1e-4)):
+        plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                        interlacing=wl["interlacing"], precision=prec, lmax=4, n_kbins=wl["n_kbins"])
+        got = plan.estimate(g, r)
+        worst = _compare(got, ref, tol)
+        print(f"c1 {prec}: worst rel err {worst:.2e}")
+
+
+def test_device_catalogs_and_reuse(lpp):
+    """Device-resident catalogs (torch tensors) give the same result as host ones, and a
+    plan can be reused for catalogs of different sizes (workspace regrowth)."""
+    import torch
+    n, box, origin = 32, 120.0, (200.0, 100.0, 300.0)
+    plan = lpp.Plan(n, box, origin, assignment=3, interlacing=1, precision="f32", lmax=4, n_kbins=8)
+    for seed, (ng, nr) in enumerate([(500, 1500), (4000, 20000), (1000, 3000)]):
+        g, r = _cats(200 + seed, ng, nr, origin, box)
+        host = plan.estimate(g, r)
+        to_dev = lambda c: Catalog(*[None if v is None else torch.tensor(v, dtype=torch.float32, device="cuda")
+                                     for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+        dev = plan.estimate(to_dev(g), to_dev(r))
+        sc = _scales(host)
+        sel = host["n_modes"] > 0
+        # float32 columns vs float64 columns: positions rounded to float32 on the device side
+        assert np.all(np.abs(dev["re"] - host["re"])[:, sel] <= 2e-4 * sc[:, sel])
+
+
+def test_error_paths_leave_plan_usable(lpp):
+    n, box, origin = 16, 50.0, (10.0, 10.0, 10.0)
+    plan = lpp.Plan(n, box, origin, (0.0, 0.0, 0.0), assignment=2, interlacing=0, precision="f64", lmax=4, n_kbins=4)
+    g, r = _cats(3, 300, 900, origin, box)
+
+    def bad(mut, code, which="g"):
+        gg, rr = _cats(3, 300, 900, origin, box)
+        mut(gg if which == "g" else rr)
+        with pytest.raises(lpp.LppError) as e:
+            plan.estimate(gg, rr)
+        assert e.value.status == code, (e.value, code)
+
+    def nan(c):
+        c.x[5] = np.nan
+
+    def outside(c):
+        c.y[7] = origin[1] + box + 1.0
+
+    def zero_w(c):
+        c.w[:] = 0.0
+
+    def nan_shape(c):
+        c.g2[3] = np.inf
+
+    bad(nan, 2)
+    bad(nan_shape, 2)
+    bad(outside, 3)
+    bad(outside, 3, which="r")
+    bad(zero_w, 5, which="r")
+    # an object at the observer (observer inside the box)
+    plan2 = lpp.Plan(n, box, origin, (30.0, 30.0, 30.0), assignment=2, interlacing=0, precision="f64", lmax=4,
+                     n_kbins=4)
+    g2, r2 = _cats(4, 300, 900, origin, box)
+    g2.x[0], g2.y[0], g2.z[0] = 30.0, 30.0, 30.0
+    with pytest.raises(lpp.LppError) as e:
+        plan2.estimate(g2, r2)
+    assert e.value.status == 4
+    # the plan still works
+    cfg = E.Config(mesh=n, box=box, origin=origin, assignment=2, interlacing=0, lmax=4, n_kbins=4)
+    ref = E.mesh64(g, r, cfg)
+    _compare(plan.estimate(g, r), ref, 1e-9)
+
+
+def test_batch_statuses(lpp):
+    n, box, origin = 16, 70.0, (100.0, 100.0, 100.0)
+    plan = lpp.Plan(n, box, origin, assignment=3, interlacing=1, precision="f64", lmax=4, n_kbins=5)
+    cats = [_cats(30 + i, 200 + 150 * i, 700 + 300 * i, origin, box) for i in range(4)]
+    cats[2][0].x[0] = np.nan
+    outs = plan.estimate_batch([c[0] for c in cats], [c[1] for c in cats])
+    assert isinstance(outs[2], lpp.LppError) and outs[2].status == 2
+    cfg = E.Config(mesh=n, box=box, origin=origin, assignment=3, interlacing=1, lmax=4, n_kbins=5)
+    for i in (0, 1, 3):
+        _compare(outs[i], E.mesh64(cats[i][0], cats[i][1], cfg), 1e-9)

@@ -1,0 +1,92 @@
+"""Host-side checks of the C-ABI library (no GPU): it loads, exports every
+function include/lpp.h declares, validates configurations, and its tables
+(series names, k-shell thresholds) agree with the oracle's definitions."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpp.h")
+
+
+def _lib():
+    import paper_2202_11839_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        pytest.skip("liblpp.so not built (run __graft_entry__.build())")
+    return pkg
+
+
+def test_exports_match_header():
+    pkg = _lib()
+    lib = pkg.load()
+    decl = re.findall(r"^(?:lpp_status|const char\*)\s+(lpp_\w+)\s*\(", open(HEADER).read(), re.M)
+    assert len(decl) >= 13
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(decl) == sorted(pkg.EXPORTS)
+    assert "gfx950" in pkg.version()
+
+
+def _cfg(**kw):
+    from paper_2202_11839_amd._lib import Config
+    c = Config()
+    c.mesh_n = kw.get("mesh_n", 32)
+    c.box_size = kw.get("box_size", 100.0)
+    c.box_origin = (C.c_double * 3)(0.0, 0.0, 0.0)
+    c.observer = (C.c_double * 3)(-10.0, -10.0, -10.0)
+    c.assignment = kw.get("assignment", 3)
+    c.interlacing = kw.get("interlacing", 1)
+    c.compensate = 1
+    c.precision = kw.get("precision", 0)
+    c.lmax = kw.get("lmax", 4)
+    c.spectra = kw.get("spectra", 15)
+    c.n_kbins = kw.get("n_kbins", 8)
+    c.dn_num, c.dn_den = kw.get("dn", (0, 0))
+    return c
+
+
+@pytest.mark.parametrize("bad", [dict(mesh_n=48), dict(mesh_n=8), dict(mesh_n=2048), dict(box_size=-1.0),
+                                 dict(assignment=4), dict(interlacing=2), dict(precision=3), dict(lmax=3),
+                                 dict(lmax=10), dict(spectra=0), dict(spectra=16), dict(n_kbins=0),
+                                 dict(dn=(17, 1), n_kbins=1), dict(dn=(-1, 2)), dict(lmax=2, spectra=8),
+                                 dict(lmax=0, spectra=2)])
+def test_plan_validation(bad):
+    pkg = _lib()
+    lib = pkg.load()
+    h = C.c_void_p()
+    st = lib.lpp_plan_create(C.byref(_cfg(**bad)), C.byref(h))
+    assert st == 1  # LPP_E_INVALID
+    assert not h.value
+
+
+def test_plan_tables_match_oracle():
+    pkg = _lib()
+    from oracle import estimator as E, mesh as M
+    for lmax in (0, 2, 4, 6, 8):
+        for fams, mask in ((("DD", "GD", "PLUS", "MINUS"), 15), (("DD",), 1), (("PLUS", "MINUS"), 12)):
+            if lmax < 4 and "MINUS" in fams or lmax < 2 and "GD" in fams:
+                continue
+            p = pkg.Plan(32, 100.0, (0.0, 0.0, 0.0), (-5.0, -5.0, -5.0), lmax=lmax, spectra=mask, n_kbins=7)
+            assert p.series == E.series_names(lmax, fams)
+    # null arguments and out-of-range names
+    lib = pkg.load()
+    assert lib.lpp_plan_create(None, None) == 1
+    p = pkg.Plan(64, 100.0, (0.0, 0.0, 0.0), n_kbins=10)
+    assert lib.lpp_series_name(p.handle, 99) is None
+    assert lib.lpp_series_name(p.handle, -1) is None
+    sz = C.c_size_t()
+    assert lib.lpp_workspace_size(p.handle, 1000, 5000, C.byref(sz)) == 0
+    assert sz.value > 4 * 64 ** 3 * 8  # at least the four complex meshes
+    assert lib.lpp_workspace_size(p.handle, 0, 5000, C.byref(sz)) == 1
+    assert pkg.load().lpp_status_string(6) == b"workspace too small"
+
+
+def test_workspace_too_small_is_reported():
+    pkg = _lib()
+    lib = pkg.load()
+    p = pkg.Plan(32, 100.0, (0.0, 0.0, 0.0), n_kbins=4)
+    # a misaligned pointer is rejected without touching a device
+    assert lib.lpp_set_workspace(p.handle, C.c_void_p(0x1001), 1 << 20) == 1
