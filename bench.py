@@ -1,0 +1,196 @@
+#!/usr/bin/env python
+"""Throughput of the LPP multipole estimator on one MI355X.
+
+One step = one full estimate (Sec. III.A): a galaxy catalog with shapes and
+its random catalog, already resident in HBM, in; every multipole series
+(DD l<=4, GD L=2,4, PLUS l<=4, MINUS L=4, EE/BB), the normalisation and the
+shot noise per k-shell out.  The default workload is the 512^3 single mock:
+wedge footprint RA 0-90 deg, Dec 0-40 deg, comoving distance 1000-1600 Mpc/h,
+1.5M galaxies drawn from a 512^3 Gaussian random field with tidal shapes,
+15M randoms, TSC with interlacing, 50 shells.
+
+Prints ONE JSON line (rank 0) with estimates/s, the roofline of the dominant
+kernel from live HIP-event timings, the FP64-path rate and the CPU oracle
+baseline timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def to_device(cat, torch):
+    from synth import Catalog
+    f = lambda a: None if a is None else torch.from_numpy(a).to("cuda", non_blocking=False).contiguous()
+    return Catalog(f(cat.x), f(cat.y), f(cat.z), f(cat.w), f(cat.nbar), f(cat.g1), f(cat.g2))
+
+
+def plan_for(lpp, wl, precision):
+    return lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision=precision, lmax=wl["lmax"], n_kbins=wl["n_kbins"])
+
+
+def time_steps(plan, gdev, rdev, steps, warmup, torch, profile=False):
+    for _ in range(warmup):
+        plan.estimate(gdev, rdev)
+    torch.cuda.synchronize()
+    plan.set_profiling(profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = plan.estimate(gdev, rdev)
+        log(f"step {i + 1}/{steps} done")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile() if profile else None
+    plan.set_profiling(False)
+    return (t1 - t0), res, prof
+
+
+def cpu_baseline(wl, gal, ran):
+    """The FP64 oracle timed on a bounded sample of the same workload.
+
+    Sample: one interlaced copy of the oracle's unit of work at the full mesh,
+    i.e. (a) the FP64 deposit of the density set (galaxies and randoms), (b)
+    one numpy 3D FFT of the mesh and (c) the complex deposit of the shape
+    set.  The oracle's FFT route does 2 copies x (23 density-set + 59
+    shape-set) such transforms per estimate (its Cartesian-tensor count at
+    l <= 4: 1 + 22 density, 1 + 22 + 21 + 15 shape), so
+    t_estimate = 2 (23 (a + b) + 59 (c + b)); shell sums are not included,
+    which makes the baseline an upper bound on the oracle's rate."""
+    import numpy as np
+    from oracle import mesh as M
+    n, box, origin, p = wl["mesh"], wl["box"], wl["origin"], wl["assignment"]
+    gpos, rpos = gal.pos(), ran.pos()
+    allpos = np.concatenate([gpos, rpos])
+    alpha = gal.w.sum() / ran.w.sum()
+    w = np.concatenate([gal.w, -alpha * ran.w])
+    t0 = time.perf_counter()
+    D = M.deposit(allpos, w, n, box, origin, p)
+    ta = time.perf_counter() - t0
+    log(f"cpu baseline: density deposit {ta:.1f} s")
+    t0 = time.perf_counter()
+    F = np.fft.fftn(D)
+    tb = time.perf_counter() - t0
+    del D, F
+    log(f"cpu baseline: fft {tb:.1f} s")
+    t0 = time.perf_counter()
+    G = M.deposit(gpos, gal.w * (gal.g1 + 1j * gal.g2), n, box, origin, p)
+    tc = time.perf_counter() - t0
+    del G
+    log(f"cpu baseline: shape deposit {tc:.1f} s")
+    t_est = 2 * (23 * (ta + tb) + 59 * (tc + tb))
+    return {"value": 1.0 / t_est, "unit": "estimates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one interlaced copy at {n}^3: FP64 deposit of {gal.n + ran.n} density objects "
+                       f"({ta:.1f} s), one numpy FFT ({tb:.1f} s), complex deposit of {gal.n} shape objects "
+                       f"({tc:.1f} s); scaled to 2 x (23 density + 59 shape) transforms per estimate; "
+                       "numpy FFT and bincount are single-threaded"),
+            "seconds_sampled": ta + tb + tc}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the field-parallel sharding is a design note, not code); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2202_11839_amd as lpp
+    from synth import WORKLOADS, make_catalogs
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    wl = dict(WORKLOADS[args.workload])
+    t0 = time.perf_counter()
+    gal, ran = make_catalogs(wl, mock=0)
+    log(f"catalogs generated in {time.perf_counter() - t0:.1f} s: {gal.n} galaxies, {ran.n} randoms")
+    gdev, rdev = to_device(gal, torch), to_device(ran, torch)
+    torch.cuda.synchronize()
+
+    plan = plan_for(lpp, wl, "f32")
+    dt, res, prof = time_steps(plan, gdev, rdev, args.steps, args.warmup, torch, profile=True)
+    ms = 1e3 * dt / args.steps
+    value = args.steps / dt
+    log(f"fp32: {ms:.1f} ms/estimate, {value:.3f} estimates/s")
+
+    # roofline of the dominant kernel (largest total time among the kernel stages)
+    n = wl["mesh"]
+    mesh_bytes = n ** 3 * 8  # complex float32
+    stages = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(("fft_yz", "fft_x", "deposit", "bin"), key=lambda k: stages.get(k, (0.0, 0))[0])
+    total_ms, launches = stages[dom]
+    avg_ms = total_ms / launches
+    if dom in ("fft_yz", "fft_x"):
+        alg_bytes = 2 * mesh_bytes            # one axis pass reads and writes the mesh once
+        kname = ("fft_axis_kernel<float, %d, %d, false> (y and z passes)" % (n, min(n, 8192 // n))
+                 if dom == "fft_yz" else "fft_axis_kernel<float, %d, %d, true> (x pass)" % (n, max(1, 256 // (n // 8))))
+    elif dom == "bin":
+        alg_bytes = 3 * mesh_bytes            # two field copies and the base
+        kname = "bin kernels"
+    else:
+        alg_bytes = mesh_bytes                # one mesh of atomic adds
+        kname = "deposit_kernel"
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+            "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()}}
+
+    extra = {}
+    if args.fp64_steps > 0:
+        del plan
+        torch.cuda.empty_cache()
+        plan64 = plan_for(lpp, wl, "f64")
+        dt64, _, _ = time_steps(plan64, gdev, rdev, args.fp64_steps, 1, torch)
+        extra["fp64"] = {"value": round(args.fp64_steps / dt64, 4), "ms_per_step": round(1e3 * dt64 / args.fp64_steps, 2)}
+        log(f"fp64: {1e3 * dt64 / args.fp64_steps:.1f} ms/estimate")
+        del plan64
+
+    cpu = None
+    if args.cpu_baseline:
+        cpu = cpu_baseline(wl, gal, ran)
+
+    out = {
+        "metric": "catalog multipole estimates/sec at 512^3 (FP32 vs FP64), %HBM peak; emulator speedup",
+        "value": round(value, 4), "unit": "estimates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("single mock, 512^3 mesh, wedge RA 0-90 Dec 0-40 r 1000-1600 Mpc/h, "
+                                "1.5M galaxies + 15M randoms, TSC + interlacing, l<=4, 50 shells")
+                   if args.workload == "c2" else args.workload,
+                   "mesh": n, "n_gal": gal.n, "n_ran": ran.n, "n_kbins": wl["n_kbins"],
+                   "series": len(res["series"]), "fft_fields": 53, "sums": "fp64"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

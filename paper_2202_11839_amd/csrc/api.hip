@@ -2,9 +2,9 @@
 // staging and the per-estimate pipeline
 //
 //   FP64 catalog sums (alpha, I, shot noise, input checks)
-//   -> counting sort of the density set (galaxies and randoms, weights w and
-//      -alpha w) and of the shape set (galaxies, weights w*gamma) by tile
-//   -> density base: deposit, FFT, unpack/combine -> B_delta, DD_l0 shells
+//   -> counting sort by mesh cell of the density set (galaxies and randoms,
+//      weights w and -alpha w) and of the shape set (galaxies, w*gamma)
+//   -> density base: gather deposit, FFT, unpack/combine -> B_delta, DD_l0
 //   -> shape base:   deposit (both grids), FFT, combine -> B_gamma, PLUS_l0
 //   -> every other field: deposit, FFT, multiply by its harmonic and by the
 //      base, FP64 shell sums
@@ -112,11 +112,6 @@ size_t mesh_bytes(const lpp_plan_s* p) {
   const size_t n = static_cast<size_t>(p->cfg.mesh_n);
   return n * n * n * 2 * real_size(p);
 }
-int tile_of_plan(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? kTileF64 : kTileF32; }
-int64_t ntiles(const lpp_plan_s* p) {
-  const int64_t nt = p->cfg.mesh_n / tile_of_plan(p);
-  return nt * nt * nt;
-}
 bool need_density(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_DD | LPP_GD)) != 0; }
 bool need_shape(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_GD | LPP_PLUS | LPP_MINUS)) != 0; }
 int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size()); }
@@ -126,7 +121,7 @@ struct Layout {
   size_t mesh[4];  // Bd, Bg, W0, W1
   size_t key_d, fx_d, fy_d, fz_d, wr_d;
   size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
-  size_t tile_of, rank, counts_d, starts_d, counts_g, starts_g;
+  size_t cell_of, rank, starts_d, starts_g, bsum;
   size_t stage_gal, stage_ran;
   size_t sums_partial, sums_out;
   size_t bin_partial, acc;
@@ -161,13 +156,12 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.fz_g = take(rs * gg);
   L.wr_g = take(rs * gg);
   L.wi_g = take(rs * gg);
-  L.tile_of = take(4 * nd);
+  L.cell_of = take(4 * nd);
   L.rank = take(4 * nd);
-  const size_t nt = static_cast<size_t>(ntiles(p));
-  L.counts_d = take(4 * nt);
-  L.starts_d = take(4 * (nt + 1));
-  L.counts_g = take(4 * nt);
-  L.starts_g = take(4 * (nt + 1));
+  const size_t ncell = static_cast<size_t>(p->cfg.mesh_n) * p->cfg.mesh_n * p->cfg.mesh_n;
+  L.starts_d = take(4 * (ncell + 1));  // also used by lpp_deposit_weights
+  L.starts_g = sh ? take(4 * (ncell + 1)) : 0;
+  L.bsum = take(4 * (static_cast<size_t>(scan_block_count(static_cast<int64_t>(ncell))) + 1));
   L.stage_gal = take(8 * 7 * gg);
   L.stage_ran = take(8 * 5 * static_cast<size_t>(nr));
   L.sums_partial = take(8 * 8 * static_cast<size_t>(catalog_sum_blocks()));
@@ -326,8 +320,8 @@ lpp_status check_catalog_args(const lpp_catalog* c, bool shapes) {
 }
 
 template <typename T>
-ObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
-  ObjSet<T> o{};
+GObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
+  GObjSet<T> o{};
   if (shape_set) {
     o.key = reinterpret_cast<uint32_t*>(wsp(p, L.key_g));
     o.fx = reinterpret_cast<T*>(wsp(p, L.fx_g));
@@ -347,31 +341,31 @@ ObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
   return o;
 }
 
-// sort the catalogs (cats[0..k)) into one set; wscale per catalog
+// Counting sort of the catalogs (cats[0..k), weight scale per catalog) by mesh
+// cell into one object set; cell_start (N^3 + 1 entries) receives the offsets.
 template <typename T>
 lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const double* wscale, int k, bool shape,
-                    ObjSet<T> out) {
-  const int64_t nt = ntiles(p);
-  uint32_t* counts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.counts_g : L.counts_d));
+                    GObjSet<T> out) {
+  const int64_t ncell = static_cast<int64_t>(p->cfg.mesh_n) * p->cfg.mesh_n * p->cfg.mesh_n;
   uint32_t* starts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.starts_g : L.starts_d));
-  uint32_t* tile_of = reinterpret_cast<uint32_t*>(wsp(p, L.tile_of));
+  uint32_t* cell_of = reinterpret_cast<uint32_t*>(wsp(p, L.cell_of));
   uint32_t* rank = reinterpret_cast<uint32_t*>(wsp(p, L.rank));
-  const int tile = tile_of_plan(p);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(wsp(p, L.bsum));
   LPP_TRY(prof_begin(p));
-  LPP_TRY(launch_fill_zero(counts, 4 * static_cast<size_t>(nt), p->stream));
+  LPP_TRY(launch_fill_zero(starts, 4 * static_cast<size_t>(ncell + 1), p->stream));
   int64_t off = 0;
   for (int i = 0; i < k; ++i) {
-    LPP_TRY(launch_tile_count<T>(cats[i], p->geo, tile, counts, rank + off, tile_of + off, p->stream));
+    LPP_TRY(launch_cell_count(cats[i], p->geo, starts, rank + off, cell_of + off, p->stream));
     off += cats[i].n;
   }
-  LPP_TRY(launch_scan(counts, starts, static_cast<int>(nt), p->stream));
+  LPP_TRY(launch_big_scan(starts, ncell, bsum, starts, p->stream));
   off = 0;
   for (int i = 0; i < k; ++i) {
-    LPP_TRY(launch_scatter<T>(cats[i], p->geo, wscale[i], shape ? 1 : 0, starts, rank + off, tile_of + off, out, 0,
-                              p->stream));
+    LPP_TRY(launch_cell_scatter<T>(cats[i], p->geo, wscale[i], shape ? 1 : 0, starts, rank + off, cell_of + off, out,
+                                   p->stream));
     off += cats[i].n;
   }
-  LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2 + 2 * k));
+  LPP_TRY(prof_end(p, LPP_STAGE_SORT, 4 + 2 * k));
   return LPP_OK;
 }
 
@@ -439,11 +433,10 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   void* Bg = wsp(p, L.mesh[1]);
   void* W0 = wsp(p, L.mesh[2]);
   void* W1 = wsp(p, L.mesh[3]);
-  const int tile = tile_of_plan(p);
   const bool il = cfg.interlacing != 0;
 
-  ObjSet<T> setd = objset<T>(p, L, false, gal->n + ran->n);
-  ObjSet<T> setg = objset<T>(p, L, true, gal->n);
+  GObjSet<T> setd = objset<T>(p, L, false, gal->n + ran->n);
+  GObjSet<T> setg = objset<T>(p, L, true, gal->n);
   const uint32_t* starts_d = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d));
   const uint32_t* starts_g = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_g));
   if (need_density(p)) {
@@ -479,16 +472,10 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   // the host, which places the monopoles and keeps the mode counts.
   double* tmp4 = acc + static_cast<size_t>(2) * nb * scratch;
   // kernel groups, each timed as one stage when profiling is on
-  auto zero = [&](void* m) -> hipError_t {
-    hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fill_zero(m, M, st);
-    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_OTHER, 1);
-    return e;
-  };
-  auto deposit = [&](const ObjSet<T>& set, const uint32_t* starts, const FieldSpec& f, int mode,
+  auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec& f, int mode,
                      void* m) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_deposit<T>(set, starts, p->geo, tile, f, mode, m, st);
+    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, f, mode, m, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
@@ -524,7 +511,6 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
     return LPP_OK;
   };
   if (need_density(p)) {
-    LPP_TRY(zero(W0));
     LPP_TRY(deposit(setd, starts_d, s0, 0, W0));
     LPP_TRY(fft(W0));
     LPP_TRY(prof_begin(p));
@@ -533,11 +519,9 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
     if ((s = fetch_base(base_dd)) != LPP_OK) return s;
   }
   if (need_shape(p)) {
-    LPP_TRY(zero(W0));
     LPP_TRY(deposit(setg, starts_g, s0, 1, W0));
     LPP_TRY(fft(W0));
     if (il) {
-      LPP_TRY(zero(W1));
       LPP_TRY(deposit(setg, starts_g, s0, 2, W1));
       LPP_TRY(fft(W1));
     }
@@ -552,18 +536,15 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   for (const Field& f : p->tab.fields) {
     double* slot = acc + static_cast<size_t>(2) * nb * f.series;
     if (f.fam == FAM_DD) {
-      LPP_TRY(zero(W0));
       LPP_TRY(deposit(setd, starts_d, f.spec, 0, W0));
       LPP_TRY(fft(W0));
       LPP_TRY(prof_begin(p));
       LPP_TRY(launch_bin_dd<T>(ba, f.spec, W0, Bd, st));
       LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
     } else {
-      LPP_TRY(zero(W0));
       LPP_TRY(deposit(setg, starts_g, f.spec, 1, W0));
       LPP_TRY(fft(W0));
       if (il) {
-        LPP_TRY(zero(W1));
         LPP_TRY(deposit(setg, starts_g, f.spec, 2, W1));
         LPP_TRY(fft(W1));
       }
@@ -656,12 +637,11 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   double sums[16];
   if ((s = catalog_sums(p, L, rc, nullptr, 1.0, sums)) != LPP_OK) return s;
   if ((s = sums_status(sums)) != LPP_OK) return s;
-  ObjSet<T> setd = objset<T>(p, L, false, c->n);
+  GObjSet<T> setd = objset<T>(p, L, false, c->n);
   const double ws[1] = {scale};
   if ((s = sort_set<T>(p, L, &rc, ws, 1, false, setd)) != LPP_OK) return s;
-  LPP_TRY(launch_fill_zero(mesh, mesh_bytes(p), p->stream));
-  LPP_TRY(launch_deposit<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, tile_of_plan(p),
-                            make_spec(0, 0, 0, 0), 0, mesh, p->stream));
+  LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, make_spec(0, 0, 0, 0),
+                           0, mesh, p->stream));
   LPP_TRY(hipStreamSynchronize(p->stream));
   return LPP_OK;
 }

@@ -141,9 +141,10 @@ __device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb) {
   __syncthreads();
 }
 
+// partial rows are stored column-major, [width][gridDim.x], for a coalesced reduction
 __device__ __forceinline__ void smem_store(const Smem& s, double* partial, int width) {
   __syncthreads();
-  for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(blockIdx.x) * width + i] = s.v[i];
+  for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = s.v[i];
 }
 
 // combined, compensated transform at mode (ix,iy,iz) from the two copies
@@ -303,13 +304,22 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
   smem_store(s, a.partial, (KIND == 2 ? 4 : 2) * nb);
 }
 
-__global__ void reduce_partials_kernel(const double* __restrict__ partial, int nblocks, int width,
-                                       double* __restrict__ acc) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= width) return;
+// one block per column: strided partial sums, then a fixed-shape tree (deterministic)
+constexpr int kRedThreads = 256;
+__global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const double* __restrict__ partial, int nblocks,
+                                                                      double* __restrict__ acc) {
+  __shared__ double sh[kRedThreads];
+  const int w = blockIdx.x;
+  const double* col = partial + static_cast<int64_t>(w) * nblocks;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[static_cast<int64_t>(b) * width + w];
-  acc[w] += s;
+  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += col[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[w] += sh[0];
 }
 
 }  // namespace
@@ -368,7 +378,7 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, c
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st) {
-  reduce_partials_kernel<<<(width + 127) / 128, 128, 0, st>>>(partial, nblocks, width, acc);
+  reduce_partials_kernel<<<width, kRedThreads, 0, st>>>(partial, nblocks, acc);
   return hipGetLastError();
 }
 

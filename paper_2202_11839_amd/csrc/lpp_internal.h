@@ -67,10 +67,10 @@ double prefactor(int m, int L);                 // (2L+1)(L-m)!/(L+m)!
 double cmap_minus_to_legendre(int l, int L);    // (2l+1) int dmu/2 L^4_L L_l
 
 // ---------------------------------------------------------------------------
-// Device-side object records (structure of arrays, sorted by tile).
+// Cell-sorted object records for the gather deposit (structure of arrays).
 template <typename T>
-struct ObjSet {
-  uint32_t* key;           // packed cell: cx | cy << 10 | cz << 20
+struct GObjSet {
+  uint32_t* key;           // cell index cx + N (cy + N cz)
   T* fx;                   // fractional position in the cell, [0, 1)
   T* fy;
   T* fz;
@@ -102,10 +102,6 @@ struct Geometry {
   double box;
 };
 
-// tile edge of the sorted deposit (cells)
-constexpr int kTileF32 = 16;
-constexpr int kTileF64 = 8;
-
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
@@ -115,21 +111,22 @@ hipError_t launch_catalog_sums(const RawCat& c, const Geometry& g, double nbar_d
                                int nblocks, double* out, hipStream_t st);
 int catalog_sum_blocks();
 
+// Counting sort by mesh cell and the gather deposit (kernels_gather.hip).
+int64_t scan_block_count(int64_t n);
+hipError_t launch_cell_count(const RawCat& c, const Geometry& g, uint32_t* counts, uint32_t* rank,
+                             uint32_t* cell_of_obj, hipStream_t st);
+// exclusive scan of n counts into starts[0..n]; bsum needs scan_block_count(n)+1 entries;
+// counts and starts may alias
+hipError_t launch_big_scan(const uint32_t* counts, int64_t n, uint32_t* bsum, uint32_t* starts, hipStream_t st);
 template <typename T>
-hipError_t launch_tile_count(const RawCat& c, const Geometry& g, int tile, uint32_t* counts, uint32_t* rank,
-                             uint32_t* tile_of, hipStream_t st);
-hipError_t launch_scan(const uint32_t* counts, uint32_t* starts, int n, hipStream_t st);
+hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
+                               const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, hipStream_t st);
+// Writes every node of the mesh (no clearing needed).  mode 0: packed real field
+// (grid -> real part, interlaced grid -> imaginary part); mode 1: complex field
+// on the grid; mode 2: complex field on the interlaced grid.
 template <typename T>
-hipError_t launch_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
-                          const uint32_t* rank, const uint32_t* tile_of, ObjSet<T> out, int64_t offset,
-                          hipStream_t st);
-
-// Deposit one field onto a complex mesh.  mode 0: packed real field (grid ->
-// real part, interlaced grid -> imaginary part); mode 1: complex field on the
-// grid; mode 2: complex field on the interlaced grid.
-template <typename T>
-hipError_t launch_deposit(const ObjSet<T>& o, const uint32_t* starts, const Geometry& g, int tile,
-                          const FieldSpec& f, int mode, void* mesh, hipStream_t st);
+hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec& f,
+                         int mode, void* mesh, hipStream_t st);
 
 template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st);
@@ -159,7 +156,7 @@ hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packe
 template <typename T>
 hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
                          int kind, hipStream_t st);
-// acc[0..width) += sum over blocks of partial (fixed order)
+// acc[0..width) += sum over blocks of partial, laid out [width][nblocks] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st);
 
 }  // namespace lpp
