@@ -153,8 +153,8 @@ def main():
         alg_bytes = 3 * mesh_bytes            # two field copies and the base
         kname = "bin kernels"
     else:
-        alg_bytes = mesh_bytes                # one mesh of atomic adds
-        kname = "deposit_kernel"
+        alg_bytes = mesh_bytes                # output meshes of one gather pass (lower bound)
+        kname = "gather_kernel"
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,

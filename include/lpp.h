@@ -91,7 +91,7 @@ typedef struct {
   int32_t lmax;            /* even, 0..8; DD/PLUS l = 0..lmax, GD L = 2..lmax,
                               MINUS L = 4..lmax                                    */
   uint32_t spectra;        /* bitmask of LPP_DD | LPP_GD | LPP_PLUS | LPP_MINUS    */
-  int32_t n_kbins;         /* number of k-shells, >= 1                             */
+  int32_t n_kbins;         /* number of k-shells, 1..256                           */
   int32_t dn_num, dn_den;  /* bin width dn_num/dn_den in units of kf; both 0 for
                               the default N/(2 n_kbins)                            */
 } lpp_config;
@@ -176,7 +176,7 @@ enum {
   LPP_STAGE_FFT_X = 2,   /* unit-stride FFT pass                               */
   LPP_STAGE_FFT_YZ = 3,  /* strided FFT passes (y and z, same kernel)          */
   LPP_STAGE_BIN = 4,     /* base construction and shell binning kernels        */
-  LPP_STAGE_OTHER = 5,   /* mesh clears and partial-sum reductions             */
+  LPP_STAGE_OTHER = 5,   /* clears and partial-sum reductions                  */
   LPP_N_STAGES = 6
 };
 lpp_status lpp_set_profiling(lpp_plan plan, int32_t on);

@@ -116,15 +116,28 @@ bool need_density(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_DD | LPP_
 bool need_shape(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_GD | LPP_PLUS | LPP_MINUS)) != 0; }
 int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size()); }
 
+// Work meshes: one gather pass deposits up to kGatherMaxReal density fields
+// (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per grid).
+constexpr int kWork = 4;
+static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
+int work_meshes(const lpp_plan_s* p, bool dn, bool sh, bool il) {
+  int n = 1;
+  if (dn) n = std::max(n, std::min<int>(kGatherMaxReal, 1 + static_cast<int>(p->tab.fields.size())));
+  if (sh) n = std::max(n, (il ? 2 : 1) * kGatherMaxComplex);
+  return n;
+}
+
 // Workspace layout (offsets in bytes), computed for capacities (ng, nr).
 struct Layout {
-  size_t mesh[4];  // Bd, Bg, W0, W1
+  size_t mesh[2];  // Bd, Bg
+  size_t work[kWork];
   size_t key_d, fx_d, fy_d, fz_d, wr_d;
   size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
   size_t cell_of, rank, starts_d, starts_g, bsum;
   size_t stage_gal, stage_ran;
   size_t sums_partial, sums_out;
   size_t bin_partial, acc;
+  size_t fp[2];  // footprints of the density and the shape set: row N^2, tile (N/8)^2, plane N bytes
   size_t total;
 };
 
@@ -141,8 +154,8 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   const bool il = p->cfg.interlacing != 0;
   L.mesh[0] = dn ? take(M) : 0;
   L.mesh[1] = sh ? take(M) : 0;
-  L.mesh[2] = take(M);
-  L.mesh[3] = (sh && il) ? take(M) : 0;
+  const int nw = work_meshes(p, dn, sh, il);
+  for (int i = 0; i < kWork; ++i) L.work[i] = i < nw ? take(M) : 0;
   const size_t nd = static_cast<size_t>(ng + nr);
   const size_t gg = static_cast<size_t>(ng);
   L.key_d = take(4 * nd);
@@ -168,12 +181,20 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.sums_out = take(8 * 16);
   const int nb = p->cfg.n_kbins;
   L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * bin_blocks(p->cfg.mesh_n));
-  L.acc = take(8 * (2 * static_cast<size_t>(nb) * (n_acc(p) + 1) + 2 * static_cast<size_t>(nb)));
+  L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
+  const size_t nn = static_cast<size_t>(p->cfg.mesh_n), nt = nn / kTile;
+  for (int i = 0; i < 2; ++i) L.fp[i] = take(nn * nn + nt * nt + nn);
   L.total = off;
   return L;
 }
 
 char* wsp(lpp_plan_s* p, size_t off) { return static_cast<char*>(p->ws) + off; }
+
+Footprint footprint_at(lpp_plan_s* p, size_t off) {
+  const size_t nn = static_cast<size_t>(p->cfg.mesh_n), nt = nn / kTile;
+  uint8_t* b = reinterpret_cast<uint8_t*>(wsp(p, off));
+  return Footprint{b, b + nn * nn, b + nn * nn + nt * nt};
+}
 
 lpp_status hip_status(hipError_t e) {
   if (e == hipSuccess) return LPP_OK;
@@ -431,29 +452,37 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   const size_t M = mesh_bytes(p);
   void* Bd = wsp(p, L.mesh[0]);
   void* Bg = wsp(p, L.mesh[1]);
-  void* W0 = wsp(p, L.mesh[2]);
-  void* W1 = wsp(p, L.mesh[3]);
+  void* W[kWork];
+  for (int i = 0; i < kWork; ++i) W[i] = L.work[i] ? wsp(p, L.work[i]) : nullptr;
   const bool il = cfg.interlacing != 0;
 
   GObjSet<T> setd = objset<T>(p, L, false, gal->n + ran->n);
   GObjSet<T> setg = objset<T>(p, L, true, gal->n);
   const uint32_t* starts_d = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d));
   const uint32_t* starts_g = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_g));
+  const Footprint fpd = footprint_at(p, L.fp[0]), fpg = footprint_at(p, L.fp[1]);
   if (need_density(p)) {
     const RawCat cs[2] = {rg, rr};
     const double ws[2] = {1.0, -alpha};
     if ((s = sort_set<T>(p, L, cs, ws, 2, false, setd)) != LPP_OK) return s;
+    LPP_TRY(prof_begin(p));
+    LPP_TRY(launch_footprint(starts_d, N, fpd, st));
+    LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2));
   }
   if (need_shape(p)) {
     const double ws[1] = {1.0};
     if ((s = sort_set<T>(p, L, &rg, ws, 1, true, setg)) != LPP_OK) return s;
+    LPP_TRY(prof_begin(p));
+    LPP_TRY(launch_footprint(starts_g, N, fpg, st));
+    LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2));
   }
 
   const int na = n_acc(p);
-  double* acc = reinterpret_cast<double*>(wsp(p, L.acc));  // [na+1][2nb] then counts[nb], ksum[nb]
-  const int scratch = na;                                    // slot for unrequested monopoles
+  // [na][2nb] series rows, then the two bases as [re, im, counts, ksum] rows of width 4nb
+  double* acc = reinterpret_cast<double*>(wsp(p, L.acc));
   double* partial = reinterpret_cast<double*>(wsp(p, L.bin_partial));
-  LPP_TRY(launch_fill_zero(acc, 8 * (2 * static_cast<size_t>(nb) * (na + 1) + 2 * static_cast<size_t>(nb)), st));
+  const size_t acc_len = 2 * static_cast<size_t>(nb) * na + 8 * static_cast<size_t>(nb);
+  LPP_TRY(launch_fill_zero(acc, 8 * acc_len, st));
   BinArgs ba{};
   ba.N = N;
   ba.nb = nb;
@@ -465,107 +494,95 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   ba.partial = partial;
   ba.nblocks = bin_blocks(N);
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
-  bool counted = false;
-
-  // The base kernels write rows [re, im, cnt, ksum] of width 4*nb; they are
-  // reduced into the scratch slot (followed by the counts slot) and copied to
-  // the host, which places the monopoles and keeps the mode counts.
-  double* tmp4 = acc + static_cast<size_t>(2) * nb * scratch;
+  // The base kernels write rows [re, im, cnt, ksum] of width 4nb; they are
+  // reduced into their own rows after the series rows.
+  double* base_rows[2] = {acc + static_cast<size_t>(2) * nb * na, acc + static_cast<size_t>(2) * nb * na + 4 * nb};
   // kernel groups, each timed as one stage when profiling is on
-  auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec& f, int mode,
-                     void* m) -> hipError_t {
+  auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
+                     const Footprint& fp) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, f, mode, m, st);
+    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.tile, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
-  auto fft = [&](void* m) -> hipError_t {
+  // the binning reads modes inside the last shell only
+  const int qmax = static_cast<int>(p->tab.thr[nb]);
+  auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
+    const FftPrune pr{fp.row, fp.plane, qmax};
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, pr, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, st);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, pr, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, pr, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
     return e;
   };
-  std::vector<double> host_acc;
-  // ---- bases ----
-  // Because the reduce kernel adds full rows, run the bases first into the
-  // scratch slot and copy their re/im parts to the requested slots on the host.
-  std::vector<double> base_dd(2 * nb, 0.0), base_gg(2 * nb, 0.0), counts(nb, 0.0), ksum(nb, 0.0);
-  std::vector<double> tmp(4 * nb);
-  auto fetch_base = [&](std::vector<double>& reim) -> lpp_status {
-    LPP_TRY(launch_fill_zero(tmp4, 8 * 4 * static_cast<size_t>(nb), st));
-    LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 4 * nb, tmp4, st));
-    LPP_TRY(hipMemcpyAsync(tmp.data(), tmp4, 8 * 4 * nb, hipMemcpyDeviceToHost, st));
-    LPP_TRY(hipStreamSynchronize(st));
-    for (int b = 0; b < 2 * nb; ++b) reim[b] = tmp[b];
-    if (!counted) {
-      for (int b = 0; b < nb; ++b) {
-        counts[b] = tmp[2 * nb + b];
-        ksum[b] = tmp[3 * nb + b];
+  // Fields in gather order: each set's base first (its spectrum is the
+  // reference the other fields of the set are binned against), then the
+  // set's other fields; the density set goes first since GD bins against B_delta.
+  struct Job {
+    FieldSpec spec;
+    int fam, series;  // series < 0: base of the set
+  };
+  std::vector<Job> dens, shape;
+  if (need_density(p)) dens.push_back(Job{s0, FAM_DD, -1});
+  if (cfg.spectra & (LPP_PLUS | LPP_MINUS)) shape.push_back(Job{s0, FAM_PLUS, -1});
+  for (const Field& f : p->tab.fields) (f.fam == FAM_DD ? dens : shape).push_back(Job{f.spec, f.fam, f.series});
+  const int copies = il ? 2 : 1;
+  auto run_set = [&](const std::vector<Job>& jobs, const GObjSet<T>& set, const uint32_t* starts, int cplx,
+                     const Footprint& fp) -> lpp_status {
+    const int per = cplx ? kGatherMaxComplex : kGatherMaxReal;
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
+      const int nf = static_cast<int>(std::min<size_t>(per, jobs.size() - j0));
+      FieldSpec specs[kWork];
+      for (int q = 0; q < nf; ++q) specs[q] = jobs[j0 + q].spec;
+      LPP_TRY(deposit(set, starts, specs, nf, cplx, fp));
+      for (int m = 0; m < nf * (cplx ? copies : 1); ++m) LPP_TRY(fft(W[m], fp));
+      for (int q = 0; q < nf; ++q) {
+        const Job& jb = jobs[j0 + q];
+        const int m0 = cplx ? q * copies : q;
+        void* g1 = W[m0];
+        void* g2 = (cplx && il) ? W[m0 + 1] : nullptr;
+        LPP_TRY(prof_begin(p));
+        if (jb.series < 0) {
+          if (cplx) LPP_TRY(launch_base_gg<T>(ba, g1, g2, Bg, st));
+          else LPP_TRY(launch_base_dd<T>(ba, g1, Bd, st));
+          LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+          LPP_TRY(prof_begin(p));
+          LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 4 * nb, base_rows[cplx], st));
+          LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
+          continue;
+        }
+        if (!cplx) {
+          LPP_TRY(launch_bin_dd<T>(ba, jb.spec, g1, Bd, st));
+        } else {
+          const void* base = (jb.fam == FAM_GD) ? Bd : Bg;
+          const int kind = (jb.fam == FAM_MINUS) ? 1 : 0;
+          LPP_TRY(launch_bin_gg<T>(ba, jb.spec, g1, g2, base, kind, st));
+        }
+        LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
+        LPP_TRY(prof_begin(p));
+        LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 2 * nb, acc + static_cast<size_t>(2) * nb * jb.series, st));
+        LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
       }
-      counted = true;
     }
     return LPP_OK;
   };
-  if (need_density(p)) {
-    LPP_TRY(deposit(setd, starts_d, s0, 0, W0));
-    LPP_TRY(fft(W0));
-    LPP_TRY(prof_begin(p));
-    LPP_TRY(launch_base_dd<T>(ba, W0, Bd, st));
-    LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
-    if ((s = fetch_base(base_dd)) != LPP_OK) return s;
-  }
-  if (need_shape(p)) {
-    LPP_TRY(deposit(setg, starts_g, s0, 1, W0));
-    LPP_TRY(fft(W0));
-    if (il) {
-      LPP_TRY(deposit(setg, starts_g, s0, 2, W1));
-      LPP_TRY(fft(W1));
-    }
-    LPP_TRY(prof_begin(p));
-    LPP_TRY(launch_base_gg<T>(ba, W0, il ? W1 : nullptr, Bg, st));
-    LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
-    if ((s = fetch_base(base_gg)) != LPP_OK) return s;
-  }
-  LPP_TRY(launch_fill_zero(acc, 8 * 2 * static_cast<size_t>(nb) * (na + 1), st));
-
-  // ---- all other fields ----
-  for (const Field& f : p->tab.fields) {
-    double* slot = acc + static_cast<size_t>(2) * nb * f.series;
-    if (f.fam == FAM_DD) {
-      LPP_TRY(deposit(setd, starts_d, f.spec, 0, W0));
-      LPP_TRY(fft(W0));
-      LPP_TRY(prof_begin(p));
-      LPP_TRY(launch_bin_dd<T>(ba, f.spec, W0, Bd, st));
-      LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
-    } else {
-      LPP_TRY(deposit(setg, starts_g, f.spec, 1, W0));
-      LPP_TRY(fft(W0));
-      if (il) {
-        LPP_TRY(deposit(setg, starts_g, f.spec, 2, W1));
-        LPP_TRY(fft(W1));
-      }
-      const void* base = (f.fam == FAM_GD) ? Bd : Bg;
-      const int kind = (f.fam == FAM_MINUS) ? 1 : 0;
-      LPP_TRY(prof_begin(p));
-      LPP_TRY(launch_bin_gg<T>(ba, f.spec, W0, il ? W1 : nullptr, base, kind, st));
-      LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
-    }
-    LPP_TRY(prof_begin(p));
-    LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 2 * nb, slot, st));
-    LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
-  }
-  host_acc.assign(static_cast<size_t>(2) * nb * (na + 1), 0.0);
-  LPP_TRY(hipMemcpyAsync(host_acc.data(), acc, 8 * host_acc.size(), hipMemcpyDeviceToHost, st));
+  if ((s = run_set(dens, setd, starts_d, 0, fpd)) != LPP_OK) return s;
+  if ((s = run_set(shape, setg, starts_g, 1, fpg)) != LPP_OK) return s;
+  std::vector<double> host_acc(acc_len);
+  LPP_TRY(hipMemcpyAsync(host_acc.data(), acc, 8 * acc_len, hipMemcpyDeviceToHost, st));
   LPP_TRY(hipStreamSynchronize(st));
   prof_collect(p);
+  // the mode counts come from whichever base was computed (both give the same)
+  const double* brow = host_acc.data() + static_cast<size_t>(2) * nb * na + (need_density(p) ? 0 : 4 * nb);
+  std::vector<double> counts(brow + 2 * nb, brow + 3 * nb), ksum(brow + 3 * nb, brow + 4 * nb);
   if (p->tab.dd0 >= 0)
-    for (int b = 0; b < 2 * nb; ++b) host_acc[static_cast<size_t>(2) * nb * p->tab.dd0 + b] = base_dd[b];
+    for (int b = 0; b < 2 * nb; ++b) host_acc[static_cast<size_t>(2) * nb * p->tab.dd0 + b] = host_acc[2 * nb * na + b];
   if (p->tab.plus0 >= 0)
-    for (int b = 0; b < 2 * nb; ++b) host_acc[static_cast<size_t>(2) * nb * p->tab.plus0 + b] = base_gg[b];
+    for (int b = 0; b < 2 * nb; ++b)
+      host_acc[static_cast<size_t>(2) * nb * p->tab.plus0 + b] = host_acc[2 * nb * na + 4 * nb + b];
 
   // ---- assembly (FP64, host) ----
   const double kf = 2.0 * M_PI / cfg.box_size;
@@ -640,8 +657,10 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   GObjSet<T> setd = objset<T>(p, L, false, c->n);
   const double ws[1] = {scale};
   if ((s = sort_set<T>(p, L, &rc, ws, 1, false, setd)) != LPP_OK) return s;
-  LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, make_spec(0, 0, 0, 0),
-                           0, mesh, p->stream));
+  const FieldSpec s0 = make_spec(0, 0, 0, 0);
+  void* meshes[1] = {mesh};
+  LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, &s0, 1, 0, meshes,
+                           nullptr, p->stream));
   LPP_TRY(hipStreamSynchronize(p->stream));
   return LPP_OK;
 }
@@ -693,7 +712,7 @@ lpp_status lpp_plan_create(const lpp_config* cfg_in, lpp_plan* out) {
   if (cfg.precision != LPP_F32 && cfg.precision != LPP_F64) return LPP_E_INVALID;
   if (cfg.lmax < 0 || cfg.lmax > 8 || cfg.lmax % 2) return LPP_E_INVALID;
   if (cfg.spectra == 0 || (cfg.spectra & ~static_cast<uint32_t>(LPP_ALL))) return LPP_E_INVALID;
-  if (cfg.n_kbins < 1 || cfg.n_kbins > 512) return LPP_E_INVALID;
+  if (cfg.n_kbins < 1 || cfg.n_kbins > kMaxShells) return LPP_E_INVALID;
   if (cfg.dn_num == 0 && cfg.dn_den == 0) {
     int64_t a = N, b = 2 * static_cast<int64_t>(cfg.n_kbins);
     const int64_t g = igcd(a, b);

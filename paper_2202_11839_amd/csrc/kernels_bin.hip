@@ -17,76 +17,25 @@
 // with F1(k) = [P(k) + P*(-k)]/2, F2(k) = [P(k) - P*(-k)]/(2i).  Those kernels
 // walk half of k-space (z-index < N/2 with the usual tie-breaks on the
 // z = 0 and y = 0 planes) and count each mode pair (k, -k) twice.
-#include "lpp_internal.h"
+#include "device_common.h"
 
 namespace lpp {
 
 namespace {
 
-template <typename T>
-struct V2;
-template <>
-struct V2<float> {
-  using type = float2;
-};
-template <>
-struct V2<double> {
-  using type = double2;
-};
-
-template <typename T2>
-__device__ __forceinline__ T2 cmul(T2 a, T2 b) {
-  return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T2>
-__device__ __forceinline__ T2 cmulc(T2 a, T2 b) {  // a * conj(b)
-  return T2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
-}
+using dev::cmul;
+using dev::cmulc;
+using dev::combine;
+using dev::harmonic;
+using dev::KSpec;
+using dev::kspec_of;
+using dev::sgn_mode;
+using dev::shell_of;
+using dev::V2;
 
 constexpr int kBinThreads = 256;
 constexpr int kRun = 8;
 constexpr int kMaxBins = 512;
-
-template <typename T>
-struct KSpec {  // h_{L,M,cs}(khat) = Q_{LM}(khat_z) Re|Im (khat_x + i khat_y)^M
-  int M, cs, nq;
-  T q[9];
-};
-
-template <typename T>
-KSpec<T> kspec_of(const FieldSpec& f) {
-  KSpec<T> k{};
-  k.M = f.M;
-  k.cs = f.cs;
-  k.nq = f.nq[0];
-  for (int i = 0; i < 9; ++i) k.q[i] = static_cast<T>(f.q[0][i]);
-  return k;
-}
-
-template <typename T>
-__device__ __forceinline__ T harmonic(const KSpec<T>& h, T kx, T ky, T kz) {
-  T Q = 0;
-  for (int i = h.nq - 1; i >= 0; --i) Q = Q * kz + h.q[i];
-  T er = 1, ei = 0;
-  for (int m = 0; m < h.M; ++m) {
-    const T t = er * kx - ei * ky;
-    ei = er * ky + ei * kx;
-    er = t;
-  }
-  return Q * (h.cs ? ei : er);
-}
-
-__device__ __forceinline__ int sgn_mode(int i, int N) { return i < N / 2 ? i : i - N; }
-
-// Shell of |n|^2 = q (q > 0), or -1.  thr is in LDS.
-__device__ __forceinline__ int shell_of(int q, const int* thr, int nb, float inv_dn) {
-  if (q <= 0 || q >= thr[nb]) return -1;
-  int b = static_cast<int>(sqrtf(static_cast<float>(q)) * inv_dn);
-  b = b < 0 ? 0 : (b >= nb ? nb - 1 : b);
-  while (b + 1 < nb && thr[b + 1] <= q) ++b;
-  while (b > 0 && thr[b] > q) --b;
-  return b;
-}
 
 struct Acc {
   int cur;
@@ -129,6 +78,14 @@ __device__ __forceinline__ void acc_flush(Acc& a, double* sre, double* sim, doub
   a.cur = -1;
 }
 
+// Does the run of kRun x-modes starting at x0 reach inside the last shell,
+// given qyz = ny^2 + nz^2?  (N/2 is a multiple of kRun, so a run is all
+// non-negative or all negative modes.)
+__device__ __forceinline__ bool run_live(int x0, int N, int qyz, int qmax) {
+  const int mx = x0 < N / 2 ? x0 : N - x0 - (kRun - 1);  // smallest |nx| of the run
+  return mx * mx + qyz < qmax;
+}
+
 // shared-memory layout: thr[kMaxBins+1] ints, then 4*nb doubles
 struct Smem {
   int thr[kMaxBins + 1];
@@ -147,17 +104,6 @@ __device__ __forceinline__ void smem_store(const Smem& s, double* partial, int w
   for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = s.v[i];
 }
 
-// combined, compensated transform at mode (ix,iy,iz) from the two copies
-template <typename T, typename T2>
-__device__ __forceinline__ T2 combine(T2 f1, T2 f2, int interlace, const T2* phase, int phidx, T invw) {
-  if (interlace) {
-    const T2 ph = phase[phidx];
-    const T2 s = cmul(ph, f2);
-    return T2{static_cast<T>(0.5) * (f1.x + s.x) * invw, static_cast<T>(0.5) * (f1.y + s.y) * invw};
-  }
-  return T2{f1.x * invw, f1.y * invw};
-}
-
 // ---- density fields (packed pair of real copies), half k-space ----
 template <typename T, bool BASE>
 __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T> h,
@@ -170,7 +116,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(s.thr[nb]));
+  const int qmax = s.thr[nb];
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
   const int64_t runs_per_row = N / kRun;
   const int64_t nruns = runs_per_row * N * (N / 2);
@@ -182,6 +129,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
     const int iz = static_cast<int>(r / (runs_per_row * N));
     const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
     if (iz == 0 && !(iy < N / 2)) continue;  // z=0 plane: y in [0, N/2)
+    if (!run_live(x0, N, ny * ny + nz * nz, qmax)) continue;
     const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
     const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
     const T wyz = invw[iy] * invw[iz];
@@ -200,20 +148,18 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
       if (iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2)) continue;  // y=0 line: x in (0, N/2)
       const int q = nx * nx + ny * ny + nz * nz;
       const int b = shell_of(q, s.thr, nb, inv_dn);
+      if (b < 0) continue;
       const T2 pm = P[mrow + ((N - ix) & mask)];
       // unpack the two real copies
       const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
       const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
       const T2 F = combine<T, T2>(f1, f2, a.interlace, phase, nx + ny + nz + 3 * N / 2, wyz * invw[ix]);
       if (BASE) {
-        if (q > 0) {
-          B[row + ix] = F;
-          B[mrow + ((N - ix) & mask)] = T2{F.x, -F.y};
-        }
-        if (b >= 0)
-          acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
-                        2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
-      } else if (b >= 0) {
+        B[row + ix] = F;
+        B[mrow + ((N - ix) & mask)] = T2{F.x, -F.y};
+        acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
+                      2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+      } else {
         const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
         const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
         // 2 Re[h F conj(B)]
@@ -243,7 +189,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(s.thr[nb]));
+  const int qmax = s.thr[nb];
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
   const int64_t runs_per_row = N / kRun;
   const int64_t nruns = runs_per_row * N * N;
@@ -254,6 +201,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
     const int iy = static_cast<int>((r / runs_per_row) % N);
     const int iz = static_cast<int>(r / (runs_per_row * N));
     const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
+    if (!run_live(x0, N, ny * ny + nz * nz, qmax)) continue;
     const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
     const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
     const T wyz = invw[iy] * invw[iz];
@@ -274,16 +222,15 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
       const int nx = sgn_mode(ix, N);
       const int q = nx * nx + ny * ny + nz * nz;
       const int b = shell_of(q, s.thr, nb, inv_dn);
+      if (b < 0) continue;
       const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, phase, nx + ny + nz + 3 * N / 2,
                                   wyz * invw[ix]);
       if (KIND == 2) {
         B[row + ix] = F;
-        if (b >= 0)
-          acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
-                        sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+        acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
+                      sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
         continue;
       }
-      if (b < 0) continue;
       const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
       const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
       T2 p;
@@ -386,11 +333,11 @@ template hipError_t launch_base_dd<float>(const BinArgs&, const void*, void*, hi
 template hipError_t launch_base_dd<double>(const BinArgs&, const void*, void*, hipStream_t);
 template hipError_t launch_base_gg<float>(const BinArgs&, const void*, const void*, void*, hipStream_t);
 template hipError_t launch_base_gg<double>(const BinArgs&, const void*, const void*, void*, hipStream_t);
-template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
-template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
 template hipError_t launch_bin_gg<float>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*, int,
                                          hipStream_t);
 template hipError_t launch_bin_gg<double>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*,
                                           int, hipStream_t);
+template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
+template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
 
 }  // namespace lpp

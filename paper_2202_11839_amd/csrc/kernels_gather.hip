@@ -94,30 +94,55 @@ __device__ __forceinline__ void los_weight(const SpecT<T>& f, T ct, T st, T cp, 
   gi = f.scale * acci;
 }
 
-// 1D assignment window W_p(x), x = (object - node) in cells.
+// 1D assignment window W_p(x), x = (object - node) in cells, written without
+// branches (the inner gather loop evaluates it for every node of a row):
+//   NGP: 1 on [-1/2, 1/2);  CIC: max(0, 1-|x|);
+//   TSC: 3/4 - x^2 for |x| < 1/2, (1/2) max(0, 3/2 - |x|)^2 otherwise.
 template <typename T, int P>
 __device__ __forceinline__ T window(T x) {
-  if (P == 1) return (x >= static_cast<T>(-0.5) && x < static_cast<T>(0.5)) ? static_cast<T>(1) : static_cast<T>(0);
-  const T ax = x < 0 ? -x : x;
-  if (P == 2) return ax < 1 ? 1 - ax : static_cast<T>(0);
-  if (ax < static_cast<T>(0.5)) return static_cast<T>(0.75) - ax * ax;
-  if (ax < static_cast<T>(1.5)) {
-    const T d = static_cast<T>(1.5) - ax;
-    return static_cast<T>(0.5) * d * d;
+  if (P == 1) {
+    const bool in = (x >= static_cast<T>(-0.5)) & (x < static_cast<T>(0.5));
+    return in ? static_cast<T>(1) : static_cast<T>(0);
   }
-  return static_cast<T>(0);
+  const T ax = fabs(x);
+  if (P == 2) return fmax(static_cast<T>(0), static_cast<T>(1) - ax);
+  const T inner = static_cast<T>(0.75) - ax * ax;
+  const T d = fmax(static_cast<T>(0), static_cast<T>(1.5) - ax);
+  const T outer = static_cast<T>(0.5) * d * d;
+  return ax < static_cast<T>(0.5) ? inner : outer;
 }
 
 constexpr int TT = 8;          // tile edge (nodes)
 constexpr int R = TT + 3;      // region edge (cells t0-2 .. t0+TT)
-constexpr int R3 = R * R * R;
+constexpr int R2 = R * R;      // region rows (y, z)
 constexpr int kRows = TT * TT;          // x-rows of the tile
-constexpr int kParts = 4;               // threads sharing one row's objects
+constexpr int kParts = 4;               // threads per row: one z-offset of the stencil range each
 constexpr int kThreads = kRows * kParts;
+constexpr int kMaxMeshes = 8;
+
+template <typename T, int NF>
+struct SpecSet {
+  SpecT<T> f[NF];
+};
 
 template <typename T>
+struct MeshSet {
+  typename V2<T>::type* m[kMaxMeshes];
+};
+
+// staged object values per field and component, plus three positions
+template <typename T, int K, int NF>
+constexpr int rows_of() {
+  return 3 + K * NF;
+}
+
+template <typename T, int K, int NF>
 constexpr int cap_of() {
-  return sizeof(T) == 4 ? 1024 : 832;
+  // the staging buffer must also hold the cross-part reduction rounds and the output rows
+  constexpr int need = (kParts - 1) * kRows * (16 + 1) + 2 * (TT + 1) * kRows;
+  constexpr int base = sizeof(T) == 4 ? 1024 : 640;
+  constexpr int rows = rows_of<T, K, NF>();
+  return base * rows >= need ? base : (need + rows - 1) / rows;
 }
 
 // inclusive scan of one value per lane across a 64-wide wavefront
@@ -131,31 +156,38 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
   return v;
 }
 
-constexpr int R2 = R * R;  // region rows (y, z)
-
-// MODE 0: packed real field (grid -> .x, interlaced grid -> .y); 1: complex on the
-// grid; 2: complex on the interlaced grid.
-template <typename T, int P, int MODE>
+// K = 1: NF real (density) fields, each written packed: grid -> .x, interlaced
+//        grid -> .y of mesh f (.y is zero without interlacing).
+// K = 2: NF complex (shape) fields; with interlacing grid -> mesh 2f and
+//        interlaced grid -> mesh 2f+1, without it grid -> mesh f.
+template <typename T, int P, int K, int NF>
 __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
                                                           int N, int lgN, int interlace, T H, T relx, T rely, T relz,
-                                                          SpecT<T> f, typename V2<T>::type* __restrict__ mesh) {
+                                                          SpecSet<T, NF> fs, MeshSet<T> out,
+                                                          const uint8_t* __restrict__ tile_flags) {
   using T2 = typename V2<T>::type;
-  constexpr int CAP = cap_of<T>();
+  constexpr int CAP = cap_of<T, K, NF>();
+  constexpr int ROWS = rows_of<T, K, NF>();
+  constexpr int NACC = NF * 2 * K * TT;  // accumulators per thread: [f][copy][component][x]
+  static_assert(NACC % 16 == 0, "reduction rounds of 16");
   // each region row (cells x in [t0x-2, t0x+TT] at fixed y, z) is at most two
   // contiguous ranges of the cell-sorted objects (two when the row wraps)
   __shared__ uint32_t seg_beg[R2][2];
   __shared__ uint32_t seg_cnt[R2];   // objects in the first range
   __shared__ uint32_t roff[R2 + 1];  // offsets of the rows in staging order
-  __shared__ T su[5][CAP];           // [0..2] region-local positions, [3..4] values (re, im)
-  static_assert(5 * CAP >= 2 * TT * kRows * (kParts - 1), "row reduction reuses the staging buffers");
+  __shared__ __align__(16) T su[ROWS][CAP];  // [0..2] region-local positions, then the values
   static_assert(R2 <= 2 * 64, "row scan uses two values per lane of one wavefront");
+  const int copies = (K == 2 && interlace) ? 2 : 1;
+  const int nmesh = NF * copies;
 
   const int nt = N / TT;
+  const int mask = N - 1;
+  const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
   const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
-  const int mask = N - 1;
-  const int tid = threadIdx.x;
+  // outside the footprint: every node of the tile-row is zero and is never read
+  if (tile_flags != nullptr && tile_flags[ty + nt * tz] == 0) return;
 
   if (tid < 64) {
     uint32_t cnt[2];
@@ -197,12 +229,24 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   __syncthreads();
   const uint32_t total = roff[R2];
 
-  // this thread's row: nodes (t0x + k, t0y + ny, t0z + nz), k = 0..TT-1; `part` strides the objects
+  // empty region: the tile is zero in every output mesh
+  if (total == 0) {
+    for (int i = tid; i < kRows * TT; i += kThreads) {
+      const int kx = i % TT, r = i / TT;
+      const int64_t idx = t0x + kx + static_cast<int64_t>(N) * ((t0y + r % TT) + static_cast<int64_t>(N) * (t0z + r / TT));
+      for (int m = 0; m < nmesh; ++m) out.m[m][idx] = T2{0, 0};
+    }
+    return;
+  }
+
+  // this thread's node row: (t0x + k, t0y + ny, t0z + nz), k = 0..TT-1.  The kParts threads of a
+  // row take one z-offset dz each: region rows y in [ny, ny+3] at z = nz + dz are contiguous.
   const int rowid = tid % kRows, part = tid / kRows;
   const int ny = rowid % TT, nz = rowid / TT;
-  T a1[TT], a2[TT];
+  static_assert(kParts == 4, "one thread per z-offset of the stencil range");
+  T acc[NACC];
 #pragma unroll
-  for (int k = 0; k < TT; ++k) a1[k] = a2[k] = 0;
+  for (int i = 0; i < NACC; ++i) acc[i] = 0;
 
   for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
     const uint32_t c1 = min(total, c0 + static_cast<uint32_t>(CAP));
@@ -222,99 +266,114 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
       const int cz = static_cast<int>(key >> (2 * lgN));
       const int lx = (cx - t0x + 2) & mask, ly = r % R, lz = r / R;
       const T fx = o.fx[src], fy = o.fy[src], fz = o.fz[src];
-      T gr = 1, gi = 0;
-      if (f.L > 0 || f.s > 0) {
-        const T px = relx + (static_cast<T>(cx) + fx) * H;
-        const T py = rely + (static_cast<T>(cy) + fy) * H;
-        const T pz = relz + (static_cast<T>(cz) + fz) * H;
-        const T rinv = static_cast<T>(1) / sqrt(px * px + py * py + pz * pz);
-        const T xx = px * rinv, xy = py * rinv, xz = pz * rinv;
-        const T st = sqrt(xx * xx + xy * xy);
-        const T cp = st > 0 ? xx / st : static_cast<T>(1);
-        const T sp = st > 0 ? xy / st : static_cast<T>(0);
-        los_weight(f, xz, st, cp, sp, gr, gi);
-      }
       const uint32_t d = k - c0;
       su[0][d] = static_cast<T>(lx) + fx;
       su[1][d] = static_cast<T>(ly) + fy;
       su[2][d] = static_cast<T>(lz) + fz;
-      if (MODE == 0) {
-        su[3][d] = o.wr[src] * gr;
-      } else {
-        const T ar = o.wr[src], ai = o.wi[src];
-        su[3][d] = ar * gr - ai * gi;
-        su[4][d] = ar * gi + ai * gr;
+      // line of sight of the object
+      const T px = relx + (static_cast<T>(cx) + fx) * H;
+      const T py = rely + (static_cast<T>(cy) + fy) * H;
+      const T pz = relz + (static_cast<T>(cz) + fz) * H;
+      const T rinv = static_cast<T>(1) / sqrt(px * px + py * py + pz * pz);
+      const T xx = px * rinv, xy = py * rinv, xz = pz * rinv;
+      const T st = sqrt(xx * xx + xy * xy);
+      const T cp = st > 0 ? xx / st : static_cast<T>(1);
+      const T sp = st > 0 ? xy / st : static_cast<T>(0);
+      const T ar = o.wr[src];
+      const T ai = K == 2 ? o.wi[src] : static_cast<T>(0);
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        T gr = 1, gi = 0;
+        if (fs.f[q].L > 0 || fs.f[q].s > 0) los_weight(fs.f[q], xz, st, cp, sp, gr, gi);
+        if (K == 1) {
+          su[3 + q][d] = ar * gr;
+        } else {
+          su[3 + 2 * q][d] = ar * gr - ai * gi;
+          su[4 + 2 * q][d] = ar * gi + ai * gr;
+        }
       }
     }
     __syncthreads();
-    // gather: rows that can reach this node row are y in [ny, ny+3], z in [nz, nz+3] (region coordinates)
-    const T nyc = static_cast<T>(ny + 2), nzc = static_cast<T>(nz + 2);
-    for (int dz = 0; dz < 4; ++dz) {
-      for (int dy = 0; dy < 4; ++dy) {
-        const int row = (ny + dy) + (nz + dz) * R;
-        const uint32_t lo = max(roff[row], c0), hi = min(roff[row + 1], c1);
-        for (uint32_t k = lo + part; k < hi; k += kParts) {
-          const uint32_t d = k - c0;
-          const T ux = su[0][d], uy = su[1][d], uz = su[2][d];
-          if (MODE == 0) {
-            const T v = su[3][d];
-            const T w1 = v * window<T, P>(uy - nyc) * window<T, P>(uz - nzc);
-            const T w2 = interlace ? v * window<T, P>(uy - nyc - static_cast<T>(0.5)) *
-                                         window<T, P>(uz - nzc - static_cast<T>(0.5))
-                                   : static_cast<T>(0);
+    {
+      const T nyc = static_cast<T>(ny + 2), nzc = static_cast<T>(nz + 2);
+      const int row = ny + (nz + part) * R;  // rows y = ny..ny+3 at z = nz + part are contiguous
+      const uint32_t lo = max(roff[row], c0), hi = min(roff[row + 4], c1);
+      const T half = static_cast<T>(0.5);
+      for (uint32_t k = lo; k < hi; ++k) {
+        const uint32_t d = k - c0;
+        const T ux = su[0][d], uy = su[1][d], uz = su[2][d];
+        const T w0 = window<T, P>(uy - nyc) * window<T, P>(uz - nzc);
+        const T w1 = interlace ? window<T, P>(uy - nyc - half) * window<T, P>(uz - nzc - half) : static_cast<T>(0);
+        T val[K * NF];
 #pragma unroll
-            for (int kx = 0; kx < TT; ++kx) {
-              const T xk = ux - static_cast<T>(kx + 2);
-              a1[kx] += w1 * window<T, P>(xk);
-              a2[kx] += w2 * window<T, P>(xk - static_cast<T>(0.5));
-            }
-          } else {
-            const T sh = (MODE == 2) ? static_cast<T>(0.5) : static_cast<T>(0);
-            const T wyz = window<T, P>(uy - nyc - sh) * window<T, P>(uz - nzc - sh);
-            const T vr = su[3][d] * wyz, vi = su[4][d] * wyz;
+        for (int q = 0; q < K * NF; ++q) val[q] = su[3 + q][d];
 #pragma unroll
-            for (int kx = 0; kx < TT; ++kx) {
-              const T wx = window<T, P>(ux - static_cast<T>(kx + 2) - sh);
-              a1[kx] += vr * wx;
-              a2[kx] += vi * wx;
+        for (int kx = 0; kx < TT; ++kx) {
+          const T xk = ux - static_cast<T>(kx + 2);
+          const T wx0 = w0 * window<T, P>(xk);
+          const T wx1 = w1 * window<T, P>(xk - half);
+#pragma unroll
+          for (int q = 0; q < NF; ++q)
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+              acc[((q * 2 + 0) * K + c) * TT + kx] += val[q * K + c] * wx0;
+              acc[((q * 2 + 1) * K + c) * TT + kx] += val[q * K + c] * wx1;
             }
-          }
         }
       }
     }
     __syncthreads();
   }
-  // combine the kParts partial rows in a fixed order (the staging buffers are free now)
+  // combine the kParts partial rows in a fixed order, 16 accumulators per round
+  constexpr int RS = 16 + 1;  // padded against LDS bank conflicts
   T* red = &su[0][0];
-  if (part > 0) {
 #pragma unroll
-    for (int kx = 0; kx < TT; ++kx) {
-      red[((part - 1) * kRows + rowid) * 2 * TT + kx] = a1[kx];
-      red[((part - 1) * kRows + rowid) * 2 * TT + TT + kx] = a2[kx];
+  for (int r0 = 0; r0 < NACC; r0 += 16) {
+    if (part > 0) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) red[((part - 1) * kRows + rowid) * RS + i] = acc[r0 + i];
     }
+    __syncthreads();
+    if (part == 0) {
+#pragma unroll
+      for (int q = 1; q < kParts; ++q)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[r0 + i] += red[((q - 1) * kRows + rowid) * RS + i];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  T2* out = reinterpret_cast<T2*>(&su[0][0]) + (kParts - 1) * kRows * TT;  // after the partial rows
-  static_assert(5 * CAP >= 2 * TT * kRows * kParts, "output staging fits after the partial rows");
-  if (part == 0) {
+  // store each output mesh through LDS: consecutive lanes write consecutive nodes of an x-row
+  T2* stage = reinterpret_cast<T2*>(red);
+  static_assert(ROWS * CAP >= 2 * (TT + 1) * kRows, "output staging fits");
+  // (the loops over fields and copies are unrolled: acc[] is only ever indexed
+  // with compile-time constants, which keeps it in registers)
 #pragma unroll
-    for (int q = 1; q < kParts; ++q)
+  for (int q = 0; q < NF; ++q) {
 #pragma unroll
-      for (int kx = 0; kx < TT; ++kx) {
-        a1[kx] += red[((q - 1) * kRows + rowid) * 2 * TT + kx];
-        a2[kx] += red[((q - 1) * kRows + rowid) * 2 * TT + TT + kx];
+    for (int cpy = 0; cpy < K; ++cpy) {
+      if (K == 2 && cpy >= copies) continue;
+      const int m = K == 1 ? q : q * copies + cpy;
+      if (part == 0) {
+#pragma unroll
+        for (int kx = 0; kx < TT; ++kx) {
+          T2 v;
+          if (K == 1)  // field q: (grid, interlaced grid)
+            v = T2{acc[(q * 2 + 0) * TT + kx], acc[(q * 2 + 1) * TT + kx]};
+          else         // field q, copy cpy: (re, im)
+            v = T2{acc[((q * 2 + cpy) * K + 0) * TT + kx], acc[((q * 2 + cpy) * K + 1) * TT + kx]};
+          stage[rowid * (TT + 1) + kx] = v;
+        }
       }
-#pragma unroll
-    for (int kx = 0; kx < TT; ++kx) out[rowid * TT + kx] = T2{a1[kx], a2[kx]};
-  }
-  __syncthreads();
-  // coalesced store of the tile: each lane writes two adjacent nodes of one x-row
-  for (int i = tid; i < kRows * TT / 2; i += kThreads) {
-    const int r = i / (TT / 2), kx = 2 * (i % (TT / 2));
-    const int yy = r % TT, zz = r / TT;
-    const int64_t base = t0x + kx + static_cast<int64_t>(N) * ((t0y + yy) + static_cast<int64_t>(N) * (t0z + zz));
-    mesh[base] = out[r * TT + kx];
-    mesh[base + 1] = out[r * TT + kx + 1];
+      __syncthreads();
+      T2* __restrict__ dst = out.m[m];
+      for (int i = tid; i < kRows * TT; i += kThreads) {
+        const int kx = i % TT, r = i / TT;
+        const int64_t idx =
+            t0x + kx + static_cast<int64_t>(N) * ((t0y + r % TT) + static_cast<int64_t>(N) * (t0z + r / TT));
+        dst[idx] = stage[r * (TT + 1) + kx];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -433,27 +492,67 @@ __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, 
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
 }
 
-template <typename T, int MODE>
+template <typename T, int K, int NF>
 hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
-                    const SpecT<T>& f, void* mesh, hipStream_t st) {
-  using T2 = typename V2<T>::type;
+                    const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, hipStream_t st) {
   const T H = static_cast<T>(g.H), rx = static_cast<T>(g.rel[0]), ry = static_cast<T>(g.rel[1]),
           rz = static_cast<T>(g.rel[2]);
-  T2* m = static_cast<T2*>(mesh);
+  SpecSet<T, NF> fs;
+  for (int q = 0; q < NF; ++q) fs.f[q] = to_spec<T>(specs[q]);
+  MeshSet<T> ms{};
+  const int nm = (K == 2 && g.interlace) ? 2 * NF : NF;
+  for (int m = 0; m < nm; ++m) ms.m[m] = static_cast<typename V2<T>::type*>(meshes[m]);
   int lg = 0;
   while ((1 << lg) < g.N) ++lg;
   switch (p) {
     case 1:
-      gather_kernel<T, 1, MODE><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, f, m);
+      gather_kernel<T, 1, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
       break;
     case 2:
-      gather_kernel<T, 2, MODE><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, f, m);
+      gather_kernel<T, 2, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
       break;
     default:
-      gather_kernel<T, 3, MODE><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, f, m);
+      gather_kernel<T, 3, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
       break;
   }
   return hipGetLastError();
+}
+
+// ---- footprint of a cell-sorted set ----
+
+// One thread per node row (y, z): flagged when a cell row (y + dy, z + dz),
+// dy, dz in -2..1, holds an object (cell rows are contiguous in the sorted order).
+__global__ void footprint_rows_kernel(const uint32_t* __restrict__ cell_start, int N, uint8_t* __restrict__ row) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= static_cast<int64_t>(N) * N) return;
+  const int y = static_cast<int>(i % N), z = static_cast<int>(i / N);
+  const int mask = N - 1;
+  uint32_t any = 0;
+  for (int dz = -2; dz <= 1; ++dz)
+    for (int dy = -2; dy <= 1; ++dy) {
+      const int64_t r = static_cast<int64_t>(N) * (((y + dy) & mask) + static_cast<int64_t>(N) * ((z + dz) & mask));
+      any |= cell_start[r + N] - cell_start[r];
+    }
+  row[i] = any != 0 ? 1 : 0;
+}
+
+// Threads [0, nt^2): tile-row flags; threads [nt^2, nt^2 + N): plane flags.
+__global__ void footprint_reduce_kernel(int N, Footprint fp) {
+  const int nt = N / kTile;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nt * nt) {
+    const int ty = i % nt, tz = i / nt;
+    uint8_t any = 0;
+    for (int dz = 0; dz < kTile; ++dz)
+      for (int dy = 0; dy < kTile; ++dy)
+        any |= fp.row[(ty * kTile + dy) + static_cast<int64_t>(N) * (tz * kTile + dz)];
+    fp.tile[i] = any;
+  } else if (i < nt * nt + N) {
+    const int z = i - nt * nt;
+    uint8_t any = 0;
+    for (int y = 0; y < N; ++y) any |= fp.row[y + static_cast<int64_t>(N) * z];
+    fp.plane[z] = any;
+  }
 }
 
 }  // namespace
@@ -485,29 +584,54 @@ hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale
 }
 
 template <typename T>
-hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec& f,
-                         int mode, void* mesh, hipStream_t st) {
+hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
+                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags,
+                         hipStream_t st) {
+  static_assert(TT == kTile, "footprint tiles are gather tiles");
   if (g.N % TT != 0) return hipErrorInvalidValue;
   const int nt = g.N / TT;
   dim3 grid(static_cast<unsigned>(nt) * nt * nt);
-  const SpecT<T> sp = to_spec<T>(f);
-  switch (mode) {
-    case 0:
-      return dispatch<T, 0>(g.p, grid, o, cell_start, g, sp, mesh, st);
-    case 1:
-      return dispatch<T, 1>(g.p, grid, o, cell_start, g, sp, mesh, st);
-    default:
-      return dispatch<T, 2>(g.p, grid, o, cell_start, g, sp, mesh, st);
+  if (!complex_fields) {
+    switch (nf) {
+      case 1:
+        return dispatch<T, 1, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      case 2:
+        return dispatch<T, 1, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      case 3:
+        return dispatch<T, 1, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      case 4:
+        return dispatch<T, 1, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      default:
+        return hipErrorInvalidValue;
+    }
   }
+  switch (nf) {
+    case 1:
+      return dispatch<T, 2, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+    case 2:
+      return dispatch<T, 2, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st) {
+  if (N % kTile != 0) return hipErrorInvalidValue;
+  const int64_t rows = static_cast<int64_t>(N) * N;
+  footprint_rows_kernel<<<static_cast<unsigned>((rows + 255) / 256), 256, 0, st>>>(cell_start, N, fp.row);
+  const int nt = N / kTile;
+  const int nred = nt * nt + N;
+  footprint_reduce_kernel<<<(nred + 255) / 256, 256, 0, st>>>(N, fp);
+  return hipGetLastError();
 }
 
 template hipError_t launch_cell_scatter<float>(const RawCat&, const Geometry&, double, int, const uint32_t*,
                                                const uint32_t*, const uint32_t*, GObjSet<float>, hipStream_t);
 template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, double, int, const uint32_t*,
                                                 const uint32_t*, const uint32_t*, GObjSet<double>, hipStream_t);
-template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec&,
-                                         int, void*, hipStream_t);
-template hipError_t launch_gather<double>(const GObjSet<double>&, const uint32_t*, const Geometry&,
-                                          const FieldSpec&, int, void*, hipStream_t);
+template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec*,
+                                         int, int, void* const*, const uint8_t*, hipStream_t);
+template hipError_t launch_gather<double>(const GObjSet<double>&, const uint32_t*, const Geometry&, const FieldSpec*,
+                                          int, int, void* const*, const uint8_t*, hipStream_t);
 
 }  // namespace lpp

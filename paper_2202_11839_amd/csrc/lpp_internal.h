@@ -121,41 +121,79 @@ hipError_t launch_big_scan(const uint32_t* counts, int64_t n, uint32_t* bsum, ui
 template <typename T>
 hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
                                const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, hipStream_t st);
-// Writes every node of the mesh (no clearing needed).  mode 0: packed real field
-// (grid -> real part, interlaced grid -> imaginary part); mode 1: complex field
-// on the grid; mode 2: complex field on the interlaced grid.
+// Footprint of a cell-sorted object set, as 0/1 byte flags (nt = N / kTile):
+//   row[y + N z]      node row (y, z) can receive weight: some object lies in
+//                     cells y-2..y+1, z-2..z+1 (the reach of every window
+//                     on both grids), any x;
+//   tile[ty + nt tz]  some node row of the kTile x kTile tile-row is flagged;
+//   plane[z]          some node row of plane z is flagged.
+// Node rows that are not flagged are zero in every field of the set.
+constexpr int kTile = 8;
+struct Footprint {
+  uint8_t* row;
+  uint8_t* tile;
+  uint8_t* plane;
+};
+hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st);
+
+// Deposits nf fields of one object set in one pass and writes every node of
+// each output mesh (no clearing needed).  With tile_flags (the footprint's
+// tile flags) the tile-rows that are not flagged are skipped and left
+// unwritten.  Real fields (complex_fields = 0,
+// nf <= kGatherMaxReal): mesh q holds field q packed (grid -> real part,
+// interlaced grid -> imaginary part).  Complex fields (nf <= kGatherMaxComplex):
+// with interlacing mesh 2q holds field q on the grid and mesh 2q+1 on the
+// interlaced grid, without it mesh q holds field q.
+constexpr int kGatherMaxReal = 4;
+constexpr int kGatherMaxComplex = 2;
 template <typename T>
-hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec& f,
-                         int mode, void* mesh, hipStream_t st);
+hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
+                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, hipStream_t st);
 
 template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st);
+// Pruning of the 3D transform of a field with a known footprint, keeping only
+// the modes the binning reads.  row/plane: footprint flags (nullable); input
+// rows that are not flagged are taken as zero and never read.  The x pass
+// leaves unflagged rows unwritten, the y pass unflagged planes, and the z pass
+// the columns with nx^2 + ny^2 >= qmax: the result is exact at every mode with
+// nx^2 + ny^2 < qmax and undefined elsewhere.
+struct FftPrune {
+  const uint8_t* row;
+  const uint8_t* plane;
+  int qmax;
+};
 // one axis (0: x, unit stride; 1: y; 2: z) of the 3D transform
 template <typename T>
-hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, hipStream_t st);
+hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, const FftPrune& pr, hipStream_t st);
 
 // Binning.  Tables: twiddles (N complex, exp(-2 pi i m/N)), phase (3N+1
 // complex, exp(-i pi m/N) for m = -3N/2..3N/2), invw (N reals, 1/W_1(n)).
+// largest number of k-shells a plan may ask for
+constexpr int kMaxShells = 256;
+
 struct BinArgs {
   int N, nb, interlace, compensate;
   const int64_t* thr;      // device thresholds [nb+1]
   const void* phase;
   const void* invw;
-  double* partial;         // [nblocks][width]
+  double* partial;         // column-major [width][nblocks]
   int nblocks;
 };
+// The binning kernels read the transformed fields only at modes inside the
+// last shell, |n|^2 < T_nb, and the base kernels write the base only there.
 int bin_blocks(int N);
 template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st);
 template <typename T>
 hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st);
-template <typename T>
-hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
-                         hipStream_t st);
 // kind 0: G conj(B(k)) (plus / cross), 1: G B(-k) (minus)
 template <typename T>
 hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
                          int kind, hipStream_t st);
+template <typename T>
+hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
+                         hipStream_t st);
 // acc[0..width) += sum over blocks of partial, laid out [width][nblocks] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st);
 

@@ -140,6 +140,55 @@ def test_estimate_matches_oracle(lpp, case, prec):
     _compare(got, ref, 1e-9 if prec == "f64" else 1e-4)
 
 
+def _footprint_cats(seed, ng, nr, pts):
+    rng = np.random.default_rng(seed)
+    gp, rp = pts(ng, rng), pts(nr, rng)
+    g = Catalog(gp[:, 0], gp[:, 1], gp[:, 2], rng.random(ng) + 0.5, np.full(ng, 2e-3), 0.3 * rng.standard_normal(ng),
+                0.3 * rng.standard_normal(ng))
+    r = Catalog(rp[:, 0], rp[:, 1], rp[:, 2], rng.random(nr) + 0.5, np.full(nr, 2e-3))
+    return g, r
+
+
+_FOOTPRINT_REF = {}
+
+
+def _footprint_case(layout):
+    """(catalogs, plan arguments, oracle result) of a compact-footprint case, cached."""
+    from synth import wedge_uniform
+    if layout not in _FOOTPRINT_REF:
+        if layout == "wedge":
+            n, box, origin, p, il = 64, 400.0, (20.0, 20.0, 0.0), 3, 1
+            pts = lambda k, rng: wedge_uniform(k, rng, (10.0, 60.0), (5.0, 35.0), (300.0, 420.0))
+        else:
+            n, box, origin, p, il = 32, 200.0, (300.0, 100.0, 150.0), 2, 1
+
+            def pts(k, rng):
+                u = box_uniform(k, rng, (0.0, 0.0, 0.0), 1.0)
+                y = np.where(u[:, 1] < 0.5, 2.0 * u[:, 1] * 9.0, box - 2.0 * (u[:, 1] - 0.5) * 9.0 - 1e-9)
+                return np.stack([origin[0] + 20.0 + 60.0 * u[:, 0], origin[1] + y,
+                                 origin[2] + 40.0 + 100.0 * u[:, 2]], axis=1)
+        g, r = _footprint_cats(11, 2500, 9000, pts)
+        cfg = E.Config(mesh=n, box=box, origin=origin, assignment=p, interlacing=il, lmax=4, n_kbins=12)
+        _FOOTPRINT_REF[layout] = (g, r, dict(mesh_n=n, box_size=box, box_origin=origin, assignment=p,
+                                             interlacing=il, lmax=4, n_kbins=12), E.mesh64(g, r, cfg))
+    return _FOOTPRINT_REF[layout]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["wedge", "wrapped_slabs"])
+def test_estimate_compact_footprint(lpp, layout, prec):
+    """Catalogs that cover a small part of the box, so that most node rows,
+    tile-rows and planes are outside the footprint and skipped by the
+    deposit and the transforms: a survey wedge (RA 10-60, Dec 5-35 deg,
+    r 300-420) in a 64^3 box, and two thin slabs at both ends of the y range
+    whose stencils wrap around the periodic boundary."""
+    g, r, kw, ref = _footprint_case(layout)
+    plan = lpp.Plan(precision=prec, **kw)
+    got = plan.estimate(g, r)
+    worst = _compare(got, ref, 1e-9 if prec == "f64" else 1e-4)
+    print(f"{layout} {prec}: worst rel err {worst:.2e}")
+
+
 def test_estimate_spectra_subsets(lpp):
     n, box, origin = 16, 90.0, (100.0, 50.0, -40.0)
     g, r = _cats(55, 900, 2500, origin, box)
