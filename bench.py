@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -120,6 +123,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB done")
+        return
 
     import paper_2202_11839_amd as lpp
     from synth import WORKLOADS, make_catalogs

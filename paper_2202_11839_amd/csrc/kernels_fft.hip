@@ -44,16 +44,16 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   int64_t base, stride;
   bool live = true;            // this column is read and written
   const uint8_t* lflag = nullptr;  // per-element load flags along the line (nullable)
-  int64_t lflag_stride = 0;
   if constexpr (ALONG) {  // the x axis
     const int64_t line = static_cast<int64_t>(blockIdx.x) * NCOL + col;  // y + N z
     base = line * N;
     stride = 1;
     if (pr.row) {
       // the rows of a block are consecutive: skip the block when none is flagged
-      bool any = false;
+      int any = 0;
       const int64_t l0 = static_cast<int64_t>(blockIdx.x) * NCOL;
-      for (int c = 0; c < NCOL; ++c) any |= pr.row[l0 + c] != 0;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) any |= pr.row[l0 + c];
       if (!any) return;
       live = pr.row[line] != 0;
     }
@@ -69,7 +69,6 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
       stride = N;
       if (pr.row) {
         lflag = pr.row + static_cast<int64_t>(N) * other;
-        lflag_stride = 1;
       }
     } else {  // other = y index (ky after the y pass), x = kx
       base = x + static_cast<int64_t>(N) * other;
@@ -77,15 +76,26 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
       const int nx = dev::sgn_mode(x, N), ny = dev::sgn_mode(other, N);
       live = nx * nx + ny * ny < pr.qmax;
       lflag = pr.plane;
-      lflag_stride = 1;
     }
   }
-  T2 v[8];  // pass-0 inputs of this thread: elements t + j*N/8
+  // pass-0 inputs of this thread: elements t + j*N/8.  The flags are loaded
+  // first, all together, so that the predicated data loads are then in flight
+  // together too.
+  bool rd[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) rd[j] = live;
+  if (lflag != nullptr) {
+    uint8_t f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = lflag[t + j * TL];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rd[j] = rd[j] && f[j] != 0;
+  }
+  T2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int e = t + j * TL;
-    const bool rd = live && (lflag == nullptr || lflag[e * lflag_stride] != 0);
-    v[j] = rd ? data[base + static_cast<int64_t>(e) * stride] : T2{0, 0};
+    v[j] = T2{0, 0};
+    if (rd[j]) v[j] = data[base + static_cast<int64_t>(t + j * TL) * stride];
   }
   dev::fft_column_regs<T, N>(tw, sm, col, t, v);
   if (!live) return;

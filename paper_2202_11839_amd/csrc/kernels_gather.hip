@@ -119,6 +119,7 @@ constexpr int kRows = TT * TT;          // x-rows of the tile
 constexpr int kParts = 4;               // threads per row: one z-offset of the stencil range each
 constexpr int kThreads = kRows * kParts;
 constexpr int kMaxMeshes = 8;
+constexpr int kXcds = 8;  // accelerator complex dies of the device
 
 template <typename T, int NF>
 struct SpecSet {
@@ -183,7 +184,15 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   const int nt = N / TT;
   const int mask = N - 1;
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
+  // Workgroups are dispatched round-robin over the XCDs, each with its own L2.
+  // Deal whole x tile-rows to the XCDs in turn (tile-row r to XCD r % kXcds),
+  // so that x-neighbouring tiles, which read overlapping cell_start rows and
+  // objects, run on the same XCD and share its L2, while every XCD still
+  // gets an even share of the footprint (plain order when nt^2 is not a
+  // multiple of kXcds, i.e. N = 16).
+  const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const int tile = (nt * nt) % kXcds == 0 ? ((local / nt) * kXcds + xcd) * nt + local % nt
+                                           : static_cast<int>(blockIdx.x);
   const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
   const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
   // outside the footprint: every node of the tile-row is zero and is never read
