@@ -12,9 +12,10 @@
 // NCOL-element row segment (LDS-staged transpose).
 //
 // With a footprint (FftPrune) the passes skip what is known to be zero or
-// never read: the x pass skips unflagged rows, the y pass unflagged planes and
-// reads flagged rows only, the z pass reads flagged planes only and skips the
-// (kx, ky) columns that lie outside the last k-shell for every kz.
+// never read: the x pass skips unflagged rows; the y pass skips unflagged
+// planes, reads flagged rows only and stores the (kx, ky) inside the last
+// k-shell only; the z pass reads flagged planes only, skips the (kx, ky)
+// columns outside the last k-shell and stores the modes inside it only.
 #include <climits>
 
 #include "device_common.h"
@@ -32,6 +33,8 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   using T2 = typename V2<T>::type;
   constexpr int TL = N / 8;
   __shared__ T2 sm[NCOL * N];
+  __shared__ T2 stw[N];  // twiddles: reading them from LDS instead of global memory
+                         // keeps them out of the path of the strided data accesses
   const int tid = threadIdx.x;
   int col, t;
   if constexpr (ALONG) {
@@ -43,6 +46,9 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   }
   int64_t base, stride;
   bool live = true;            // this column is read and written
+  // outputs are stored where qline + m^2 < qstore, m the output's signed mode:
+  // the y pass keeps nx^2 + ny^2 < qmax and the z pass |n|^2 < qmax
+  int qline = 0, qstore = INT_MAX;
   const uint8_t* lflag = nullptr;  // per-element load flags along the line (nullable)
   if constexpr (ALONG) {  // the x axis
     const int64_t line = static_cast<int64_t>(blockIdx.x) * NCOL + col;  // y + N z
@@ -70,12 +76,17 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
       if (pr.row) {
         lflag = pr.row + static_cast<int64_t>(N) * other;
       }
+      const int nx = dev::sgn_mode(x, N);
+      qline = nx * nx;
+      qstore = pr.qmax;
     } else {  // other = y index (ky after the y pass), x = kx
       base = x + static_cast<int64_t>(N) * other;
       stride = static_cast<int64_t>(N) * N;
       const int nx = dev::sgn_mode(x, N), ny = dev::sgn_mode(other, N);
       live = nx * nx + ny * ny < pr.qmax;
       lflag = pr.plane;
+      qline = nx * nx + ny * ny;
+      qstore = pr.qmax;
     }
   }
   // pass-0 inputs of this thread: elements t + j*N/8.  The flags are loaded
@@ -97,12 +108,17 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
     v[j] = T2{0, 0};
     if (rd[j]) v[j] = data[base + static_cast<int64_t>(t + j * TL) * stride];
   }
-  dev::fft_column_regs<T, N>(tw, sm, col, t, v);
+  // (fft_column_regs has a barrier after its first exchange, before the first twiddle is read)
+  for (int i = tid; i < N; i += NCOL * TL) stw[i] = tw[i];
+  dev::fft_column_regs<T, N>(stw, sm, col, t, v);
   if (!live) return;
   int row[8];
   dev::fft_rows<N>(t, row);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) data[base + static_cast<int64_t>(row[q]) * stride] = v[q];
+  for (int q = 0; q < 8; ++q) {
+    const int m = dev::sgn_mode(row[q], N);
+    if (qline + m * m < qstore) data[base + static_cast<int64_t>(row[q]) * stride] = v[q];
+  }
 }
 
 template <typename T, int N>

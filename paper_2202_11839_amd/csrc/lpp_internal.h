@@ -155,9 +155,10 @@ hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st)
 // Pruning of the 3D transform of a field with a known footprint, keeping only
 // the modes the binning reads.  row/plane: footprint flags (nullable); input
 // rows that are not flagged are taken as zero and never read.  The x pass
-// leaves unflagged rows unwritten, the y pass unflagged planes, and the z pass
-// the columns with nx^2 + ny^2 >= qmax: the result is exact at every mode with
-// nx^2 + ny^2 < qmax and undefined elsewhere.
+// leaves unflagged rows unwritten, the y pass unflagged planes and the
+// (kx, ky) with nx^2 + ny^2 >= qmax, and the z pass the modes with
+// |n|^2 >= qmax: the result is exact at every mode with |n|^2 < qmax and
+// undefined elsewhere (without pruning, qmax = INT_MAX, everywhere exact).
 struct FftPrune {
   const uint8_t* row;
   const uint8_t* plane;
