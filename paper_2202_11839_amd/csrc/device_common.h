@@ -232,11 +232,11 @@ __device__ __forceinline__ int shell_of(int q, const int* thr, int nb, float inv
   return b;
 }
 
-// combined, compensated transform from the two interlaced copies
+// combined, compensated transform from the two interlaced copies; ph is
+// exp(-i k.s) of the mode (unused without interlacing)
 template <typename T, typename T2>
-__device__ __forceinline__ T2 combine(T2 f1, T2 f2, int interlace, const T2* phase, int phidx, T invw) {
+__device__ __forceinline__ T2 combine(T2 f1, T2 f2, int interlace, T2 ph, T invw) {
   if (interlace) {
-    const T2 ph = phase[phidx];
     const T2 s = cmul(ph, f2);
     return T2{static_cast<T>(0.5) * (f1.x + s.x) * invw, static_cast<T>(0.5) * (f1.y + s.y) * invw};
   }

@@ -92,6 +92,24 @@ struct Smem {
   double v[4 * kMaxBins];
 };
 
+// Per-x tables staged in dynamic LDS (bytes: tables_bytes<T>(N)): the
+// interlacing phase factor along x, exp(-i pi nx/N) at nx + N/2, and 1/W(x).
+// The full phase is that factor times the row's exp(-i pi (ny+nz)/N).
+template <typename T>
+constexpr size_t tables_bytes(int N) {
+  return static_cast<size_t>(N) * (sizeof(typename V2<T>::type) + sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void tables_init(const BinArgs& a, typename V2<T>::type* px, T* iw) {
+  using T2 = typename V2<T>::type;
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  for (int i = threadIdx.x; i < a.N; i += blockDim.x) {
+    px[i] = phase[i + a.N];  // nx = i - N/2 sits at nx + 3N/2 of the phase table
+    iw[i] = invw[i];
+  }
+}
+
 __device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb) {
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) s.thr[i] = static_cast<int>(thr[i]);
   for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) s.v[i] = 0.0;
@@ -111,8 +129,12 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
                                                              typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
   __shared__ Smem s;
+  extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
-  smem_init(s, a.thr, nb);
+  T2* px = reinterpret_cast<T2*>(dyn);
+  T* iw = reinterpret_cast<T*>(px + N);
+  tables_init<T>(a, px, iw);
+  smem_init(s, a.thr, nb);  // (ends with a barrier)
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
@@ -133,6 +155,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
     const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
     const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
     const T wyz = invw[iy] * invw[iz];
+    const T2 pyz = phase[ny + nz + 3 * N / 2];
     T2 pv[kRun];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) pv[j] = P[row + x0 + j];
@@ -153,7 +176,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
       // unpack the two real copies
       const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
       const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
-      const T2 F = combine<T, T2>(f1, f2, a.interlace, phase, nx + ny + nz + 3 * N / 2, wyz * invw[ix]);
+      const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pyz, px[nx + N / 2]), wyz * iw[ix]);
       if (BASE) {
         B[row + ix] = F;
         B[mrow + ((N - ix) & mask)] = T2{F.x, -F.y};
@@ -184,8 +207,12 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
                                                              typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
   __shared__ Smem s;
+  extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
-  smem_init(s, a.thr, nb);
+  T2* px = reinterpret_cast<T2*>(dyn);
+  T* iw = reinterpret_cast<T*>(px + N);
+  tables_init<T>(a, px, iw);
+  smem_init(s, a.thr, nb);  // (ends with a barrier)
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
@@ -205,6 +232,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
     const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
     const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
     const T wyz = invw[iy] * invw[iz];
+    const T2 pyz = phase[ny + nz + 3 * N / 2];
     T2 g1[kRun], g2[kRun], bv[kRun];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) g1[j] = G1[row + x0 + j];
@@ -223,8 +251,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
       const int q = nx * nx + ny * ny + nz * nz;
       const int b = shell_of(q, s.thr, nb, inv_dn);
       if (b < 0) continue;
-      const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, phase, nx + ny + nz + 3 * N / 2,
-                                  wyz * invw[ix]);
+      const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pyz, px[nx + N / 2]),
+                                  wyz * iw[ix]);
       if (KIND == 2) {
         B[row + ix] = F;
         acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
@@ -284,7 +312,7 @@ hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipS
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
   KSpec<T> h{};
-  bin_dd_kernel<T, true><<<a.nblocks, kBinThreads, 0, st>>>(a, h, static_cast<const T2*>(packed),
+  bin_dd_kernel<T, true><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, h, static_cast<const T2*>(packed),
                                                               static_cast<T2*>(base));
   return hipGetLastError();
 }
@@ -294,7 +322,7 @@ hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
   KSpec<T> h{};
-  bin_gg_kernel<T, 2><<<a.nblocks, kBinThreads, 0, st>>>(a, h, static_cast<const T2*>(g1),
+  bin_gg_kernel<T, 2><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, h, static_cast<const T2*>(g1),
                                                           static_cast<const T2*>(g2), static_cast<T2*>(base));
   return hipGetLastError();
 }
@@ -304,7 +332,7 @@ hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packe
                          hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  bin_dd_kernel<T, false><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(packed),
+  bin_dd_kernel<T, false><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(packed),
                                                                const_cast<T2*>(static_cast<const T2*>(base)));
   return hipGetLastError();
 }
@@ -316,10 +344,10 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, c
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
   T2* b = const_cast<T2*>(static_cast<const T2*>(base));
   if (kind == 0)
-    bin_gg_kernel<T, 0><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
+    bin_gg_kernel<T, 0><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
                                                             static_cast<const T2*>(g2), b);
   else
-    bin_gg_kernel<T, 1><<<a.nblocks, kBinThreads, 0, st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
+    bin_gg_kernel<T, 1><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
                                                             static_cast<const T2*>(g2), b);
   return hipGetLastError();
 }
