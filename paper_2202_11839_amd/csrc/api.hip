@@ -137,7 +137,7 @@ struct Layout {
   size_t stage_gal, stage_ran;
   size_t sums_partial, sums_out;
   size_t bin_partial, acc;
-  size_t fp[2];  // footprints of the density and the shape set: row N^2, tile (N/8)^2, plane N bytes
+  size_t fp[2];  // footprints of the density and the shape set (footprint_bytes)
   size_t total;
 };
 
@@ -183,7 +183,7 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * bin_blocks(p->cfg.mesh_n));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
   const size_t nn = static_cast<size_t>(p->cfg.mesh_n), nt = nn / kTile;
-  for (int i = 0; i < 2; ++i) L.fp[i] = take(nn * nn + nt * nt + nn);
+  for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
   L.total = off;
   return L;
 }
@@ -193,7 +193,7 @@ char* wsp(lpp_plan_s* p, size_t off) { return static_cast<char*>(p->ws) + off; }
 Footprint footprint_at(lpp_plan_s* p, size_t off) {
   const size_t nn = static_cast<size_t>(p->cfg.mesh_n), nt = nn / kTile;
   uint8_t* b = reinterpret_cast<uint8_t*>(wsp(p, off));
-  return Footprint{b, b + nn * nn, b + nn * nn + nt * nt};
+  return Footprint{b, b + nn * nn, b + nn * nn + nt * nt, b + nn * nn + nt * nt + nn};
 }
 
 lpp_status hip_status(hipError_t e) {
@@ -501,14 +501,14 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
                      const Footprint& fp) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.tile, st);
+    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
   // the binning reads modes inside the last shell only
   const int qmax = static_cast<int>(p->tab.thr[nb]);
   auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
-    const FftPrune pr{fp.row, fp.plane, qmax};
+    const FftPrune pr{fp.row, fp.plane, fp.cube, qmax};
     hipError_t e = prof_begin(p);
     if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, pr, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);

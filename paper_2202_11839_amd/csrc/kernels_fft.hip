@@ -12,7 +12,8 @@
 // NCOL-element row segment (LDS-staged transpose).
 //
 // With a footprint (FftPrune) the passes skip what is known to be zero or
-// never read: the x pass skips unflagged rows; the y pass skips unflagged
+// never read: the x pass skips unflagged rows and reads the segments of
+// flagged cubes only; the y pass skips unflagged
 // planes, reads flagged rows only and stores the (kx, ky) inside the last
 // k-shell only; the z pass reads flagged planes only, skips the (kx, ky)
 // columns outside the last k-shell and stores the modes inside it only.
@@ -49,7 +50,8 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   // outputs are stored where qline + m^2 < qstore, m the output's signed mode:
   // the y pass keeps nx^2 + ny^2 < qmax and the z pass |n|^2 < qmax
   int qline = 0, qstore = INT_MAX;
-  const uint8_t* lflag = nullptr;  // per-element load flags along the line (nullable)
+  const uint8_t* lflag = nullptr;  // load flags along the line (nullable): element e reads lflag[e >> lshift]
+  int lshift = 0;
   if constexpr (ALONG) {  // the x axis
     const int64_t line = static_cast<int64_t>(blockIdx.x) * NCOL + col;  // y + N z
     base = line * N;
@@ -62,6 +64,13 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
       for (int c = 0; c < NCOL; ++c) any |= pr.row[l0 + c];
       if (!any) return;
       live = pr.row[line] != 0;
+    }
+    if (pr.cube) {
+      const int64_t y = line % N, z = line / N;
+      const int nt = N / kTile;
+      lflag = pr.cube + nt * ((y / kTile) + nt * (z / kTile));
+      lshift = 3;
+      static_assert(kTile == 8, "segment flags by x >> 3");
     }
   } else {
     static_assert(NCOL <= N, "column blocks within one line of the other axis");
@@ -80,6 +89,11 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
       qline = nx * nx;
       qstore = pr.qmax;
     } else {  // other = y index (ky after the y pass), x = kx
+      // the whole block of columns outside the last k-shell: nothing to do
+      const int c0 = chunk * NCOL;  // NCOL | N/2, so the chunk's modes share a sign
+      const int mx = c0 < N / 2 ? c0 : N - c0 - (NCOL - 1);
+      const int nyb = dev::sgn_mode(other, N);
+      if (mx * mx + nyb * nyb >= pr.qmax) return;
       base = x + static_cast<int64_t>(N) * other;
       stride = static_cast<int64_t>(N) * N;
       const int nx = dev::sgn_mode(x, N), ny = dev::sgn_mode(other, N);
@@ -98,7 +112,7 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   if (lflag != nullptr) {
     uint8_t f[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) f[j] = lflag[t + j * TL];
+    for (int j = 0; j < 8; ++j) f[j] = lflag[(t + j * TL) >> lshift];
 #pragma unroll
     for (int j = 0; j < 8; ++j) rd[j] = rd[j] && f[j] != 0;
   }
@@ -166,7 +180,7 @@ hipError_t launch_fft_axis(void* mesh, int N, const void* tw, int axis, const Ff
 
 template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* tw, hipStream_t st) {
-  const FftPrune full{nullptr, nullptr, INT_MAX};
+  const FftPrune full{nullptr, nullptr, nullptr, INT_MAX};
   for (int axis = 0; axis < 3; ++axis) {
     const hipError_t e = launch_fft_axis<T>(mesh, N, tw, axis, full, st);
     if (e != hipSuccess) return e;

@@ -195,8 +195,8 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
                                            : static_cast<int>(blockIdx.x);
   const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
   const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
-  // outside the footprint: every node of the tile-row is zero and is never read
-  if (tile_flags != nullptr && tile_flags[ty + nt * tz] == 0) return;
+  // outside the footprint: every node of the tile is zero and is never read
+  if (tile_flags != nullptr && tile_flags[tile] == 0) return;
 
   if (tid < 64) {
     uint32_t cnt[2];
@@ -545,6 +545,33 @@ __global__ void footprint_rows_kernel(const uint32_t* __restrict__ cell_start, i
   row[i] = any != 0 ? 1 : 0;
 }
 
+// One thread per tile: flagged when one of the 11 x 11 cell rows of its
+// region holds an object in cells x = t0x-2 .. t0x+8 (with wrap-around).
+__global__ void footprint_cubes_kernel(const uint32_t* __restrict__ cell_start, int N, uint8_t* __restrict__ cube) {
+  const int nt = N / kTile;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= static_cast<int64_t>(nt) * nt * nt) return;
+  const int tx = static_cast<int>(i % nt), ty = static_cast<int>((i / nt) % nt), tz = static_cast<int>(i / (nt * nt));
+  const int mask = N - 1;
+  const int xa = tx * kTile - 2, xb = tx * kTile + kTile;  // inclusive cell range
+  uint32_t any = 0;
+  for (int dz = -2; dz <= kTile; ++dz)
+    for (int dy = -2; dy <= kTile; ++dy) {
+      const int64_t r = static_cast<int64_t>(N) * (((ty * kTile + dy) & mask) +
+                                                   static_cast<int64_t>(N) * ((tz * kTile + dz) & mask));
+      if (xa < 0) {
+        any |= cell_start[r + N] - cell_start[r + N + xa];
+        any |= cell_start[r + xb + 1] - cell_start[r];
+      } else if (xb >= N) {
+        any |= cell_start[r + N] - cell_start[r + xa];
+        any |= cell_start[r + xb - N + 1] - cell_start[r];
+      } else {
+        any |= cell_start[r + xb + 1] - cell_start[r + xa];
+      }
+    }
+  cube[i] = any != 0 ? 1 : 0;
+}
+
 // Threads [0, nt^2): tile-row flags; threads [nt^2, nt^2 + N): plane flags.
 __global__ void footprint_reduce_kernel(int N, Footprint fp) {
   const int nt = N / kTile;
@@ -631,6 +658,8 @@ hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hip
   const int nt = N / kTile;
   const int nred = nt * nt + N;
   footprint_reduce_kernel<<<(nred + 255) / 256, 256, 0, st>>>(N, fp);
+  const int64_t ncube = static_cast<int64_t>(nt) * nt * nt;
+  footprint_cubes_kernel<<<static_cast<unsigned>((ncube + 255) / 256), 256, 0, st>>>(cell_start, N, fp.cube);
   return hipGetLastError();
 }
 

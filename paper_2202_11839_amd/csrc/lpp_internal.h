@@ -126,20 +126,26 @@ hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale
 //                     cells y-2..y+1, z-2..z+1 (the reach of every window
 //                     on both grids), any x;
 //   tile[ty + nt tz]  some node row of the kTile x kTile tile-row is flagged;
-//   plane[z]          some node row of plane z is flagged.
-// Node rows that are not flagged are zero in every field of the set.
+//   plane[z]          some node row of plane z is flagged;
+//   cube[tx + nt (ty + nt tz)]  the kTile^3 tile can receive weight: some
+//                     object lies in its cells t0-2 .. t0+kTile on every axis.
+// Nodes outside the flagged rows or cubes are zero in every field of the set.
 constexpr int kTile = 8;
 struct Footprint {
   uint8_t* row;
   uint8_t* tile;
   uint8_t* plane;
+  uint8_t* cube;
 };
+inline size_t footprint_bytes(int N) {
+  const size_t n = static_cast<size_t>(N), nt = n / kTile;
+  return n * n + nt * nt + n + nt * nt * nt;
+}
 hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st);
 
 // Deposits nf fields of one object set in one pass and writes every node of
 // each output mesh (no clearing needed).  With tile_flags (the footprint's
-// tile flags) the tile-rows that are not flagged are skipped and left
-// unwritten.  Real fields (complex_fields = 0,
+// cube flags) the tiles that are not flagged are skipped and left unwritten.  Real fields (complex_fields = 0,
 // nf <= kGatherMaxReal): mesh q holds field q packed (grid -> real part,
 // interlaced grid -> imaginary part).  Complex fields (nf <= kGatherMaxComplex):
 // with interlacing mesh 2q holds field q on the grid and mesh 2q+1 on the
@@ -162,6 +168,7 @@ hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st)
 struct FftPrune {
   const uint8_t* row;
   const uint8_t* plane;
+  const uint8_t* cube;  // x pass: kTile-node segments of a row outside the flagged cubes are zero
   int qmax;
 };
 // one axis (0: x, unit stride; 1: y; 2: z) of the 3D transform
