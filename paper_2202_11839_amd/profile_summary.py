@@ -1,0 +1,125 @@
+"""Short text summaries of rocprofv3 output for the profiles/ folder.
+
+``kernels DB [--title T] [--command C]``
+    Per-kernel launch count, average and total duration from a
+    ``--kernel-trace`` SQLite database (rocprofv3's ``*_results.db``).
+
+``traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB [--kernel PATTERN]``
+    HBM bytes per launch of the kernels whose name contains PATTERN, from a
+    ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the same program.
+    Both counters are scaled by what they read for a plain device copy of
+    known size (``bench.py --copy-calibration``: 1 GiB read and 1 GiB written
+    per ``__amd_rocclr_copyBuffer`` launch), and the SHA-256 of the kernel
+    source is recorded so that a stale figure can be recognised.  Without
+    --kernel: a table of read and written bytes per launch of every kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import statistics
+
+COPY_BYTES = 1 << 30  # bytes read and bytes written by one calibration copy
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _short(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    name = name.replace("lpp::dev::V2<float>::type", "float2").replace("lpp::dev::V2<double>::type", "double2")
+    return re.sub(r"\(.*", "", name).strip()
+
+
+def kernel_table(db: str) -> list[tuple[str, int, float, float]]:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(end - start), sum(end - start) from kernels group by name").fetchall()
+    out = [(_short(n), c, a / 1e6, s / 1e6) for n, c, a, s in rows]
+    return sorted(out, key=lambda r: -r[3])
+
+
+def counter(db: str, name: str) -> dict[str, list[float]]:
+    con = sqlite3.connect(db)
+    per: dict[str, list[float]] = {}
+    for kname, value in con.execute("select name, counter_value from pmc_events where counter_name = ?", (name,)):
+        per.setdefault(kname, []).append(float(value))
+    return per
+
+
+def scale(db: str, name: str) -> float:
+    """Bytes per counter unit, from the calibration copies (first copy skipped)."""
+    vals = [v for k, vs in counter(db, name).items() if "copyBuffer" in k for v in vs]
+    if not vals:
+        raise SystemExit(f"no copy kernel in {db}")
+    vals = vals[1:] if len(vals) > 1 else vals
+    return COPY_BYTES / statistics.mean(vals)
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    k.add_argument("--title", default="")
+    k.add_argument("--command", default="")
+    k.add_argument("--top", type=int, default=25)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_db")
+    t.add_argument("write_db")
+    t.add_argument("copy_fetch_db")
+    t.add_argument("copy_write_db")
+    t.add_argument("--kernel", default="")
+    t.add_argument("--source", default=os.path.join(HERE, "csrc", "kernels_fft.hip"))
+    t.add_argument("--command", default="")
+    args = ap.parse_args()
+
+    if args.mode == "kernels":
+        rows = kernel_table(args.db)
+        if args.title:
+            print(f"# {args.title}")
+        if args.command:
+            print(f"# command: {args.command}")
+        total = sum(r[3] for r in rows)
+        print(f"{'kernel':70s} {'calls':>6s} {'avg ms':>9s} {'total ms':>10s} {'share':>6s}")
+        for name, calls, avg, tot in rows[: args.top]:
+            print(f"{name[:70]:70s} {calls:6d} {avg:9.4f} {tot:10.2f} {100 * tot / total:5.1f}%")
+        print(f"{'all kernels':70s} {sum(r[1] for r in rows):6d} {'':9s} {total:10.2f}")
+        return
+
+    fs, ws = scale(args.copy_fetch_db, "FETCH_SIZE"), scale(args.copy_write_db, "WRITE_SIZE")
+    if not args.kernel:
+        fetch_all, write_all = counter(args.fetch_db, "FETCH_SIZE"), counter(args.write_db, "WRITE_SIZE")
+        dur = {}
+        con = sqlite3.connect(args.fetch_db)
+        for kname, d in con.execute("select name, duration from pmc_events where counter_name = 'FETCH_SIZE'"):
+            dur.setdefault(kname, []).append(d / 1e6)
+        if args.command:
+            print(f"# command: {args.command}")
+        print(f"# counters scaled by the calibration copy: FETCH_SIZE x {fs:.1f} B, WRITE_SIZE x {ws:.1f} B")
+        print(f"{'kernel':60s} {'calls':>6s} {'read GB':>9s} {'write GB':>9s} {'ms (pmc run)':>13s}")
+        rows = []
+        for kname, vals in fetch_all.items():
+            wv = write_all.get(kname, [0.0])
+            rows.append((_short(kname), len(vals), statistics.mean(vals) * fs / 1e9, statistics.mean(wv) * ws / 1e9,
+                         statistics.mean(dur.get(kname, [0.0]))))
+        for r in sorted(rows, key=lambda r: -r[1] * r[4])[:25]:
+            print(f"{r[0][:60]:60s} {r[1]:6d} {r[2]:9.3f} {r[3]:9.3f} {r[4]:13.4f}")
+        return
+    fetch = [v for n, vs in counter(args.fetch_db, "FETCH_SIZE").items() if args.kernel in n for v in vs]
+    write = [v for n, vs in counter(args.write_db, "WRITE_SIZE").items() if args.kernel in n for v in vs]
+    if not fetch or not write:
+        raise SystemExit(f"no launches of {args.kernel!r}")
+    with open(args.source, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    rd, wr = statistics.mean(fetch) * fs, statistics.mean(write) * ws
+    rec = {"kernel": args.kernel, "launches": len(fetch), "read_bytes_per_launch": round(rd),
+           "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
+           "fetch_scale_bytes_per_unit": fs, "write_scale_bytes_per_unit": ws,
+           "kernels_fft_sha256": digest, "command": args.command}
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main()
