@@ -148,11 +148,21 @@ const char* lpp_series_name(lpp_plan plan, int32_t i);
  * noise out (Sec. III.A).  Synchronises the plan's stream before returning. */
 lpp_status lpp_estimate(lpp_plan plan, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out);
 
-/* n independent estimates (mock catalogs of any sizes) through the same plan;
+/* n independent estimates (mock catalogs of any sizes) through the same plan
+ * (the batch of mocks of Sec. IV, each one estimate of Sec. III.A);
  * per_catalog_status[i] receives each one's status, and the call returns
- * LPP_OK if all succeeded, otherwise the first failure's status. */
+ * LPP_OK if all succeeded, otherwise the first failure's status.  Every
+ * catalog is validated first.  When every catalog is device-resident, the
+ * device work of the valid ones is captured into one HIP graph on a capture
+ * stream owned by the plan and launched on the plan's stream; a later call
+ * with the same catalog pointers and sizes (and the same workspace) replays
+ * that graph without capturing again (new contents of the same buffers are
+ * fine).  Host-resident batches run catalog by catalog.  Synchronises the
+ * plan's stream before returning.  Stage timing does not cover graph work. */
 lpp_status lpp_estimate_batch(lpp_plan plan, int32_t n, const lpp_catalog* gals, const lpp_catalog* rans,
                               lpp_result* outs, lpp_status* per_catalog_status);
+/* Graphs captured and launched by lpp_estimate_batch over the plan's life. */
+lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 
 /* Building blocks, exposed for testing and for callers with their own meshes.
  * All meshes are complex, index x + N*(y + N*z), interleaved (re, im), of the

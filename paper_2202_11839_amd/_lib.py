@@ -25,7 +25,7 @@ STATUS = ["LPP_OK", "LPP_E_INVALID", "LPP_E_NONFINITE", "LPP_E_OUT_OF_BOX", "LPP
 EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace", "lpp_set_stream",
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
-           "lpp_reset_profile"]
+           "lpp_reset_profile", "lpp_batch_stats"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
 
@@ -240,6 +240,12 @@ class Plan:
             else:
                 outs.append(self._pack(res[i][0], RS[i], self.series))
         return outs
+
+    def batch_stats(self) -> tuple:
+        """(graphs captured, graph launches) of estimate_batch over the plan's life."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(self.lib.lpp_batch_stats(self.handle, C.byref(a), C.byref(b)), "lpp_batch_stats")
+        return a.value, b.value
 
     def deposit_weights(self, cat, scale: float, mesh) -> None:
         """Mass-assign cat.w * scale onto ``mesh`` (torch complex tensor N^3 on the device)."""

@@ -67,6 +67,16 @@ struct lpp_plan_s {
   size_t ev_used = 0;             // pairs recorded since the last collection
   double prof_ms[LPP_N_STAGES] = {0};
   int64_t prof_launches[LPP_N_STAGES] = {0};
+  // batch executor: the device pipelines of a batch of device-resident
+  // catalogs captured into one HIP graph, replayed while the batch's
+  // pointers and sizes stay the same
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+  double* d_batch = nullptr;  // alpha[n], then n rows of acc_doubles
+  size_t d_batch_cap = 0;     // doubles
+  int64_t graph_captures = 0, graph_replays = 0;
 };
 
 namespace {
@@ -182,7 +192,6 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   const int nb = p->cfg.n_kbins;
   L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * bin_blocks(p->cfg.mesh_n));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
-  const size_t nn = static_cast<size_t>(p->cfg.mesh_n), nt = nn / kTile;
   for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
   L.total = off;
   return L;
@@ -365,25 +374,25 @@ GObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
 // Counting sort of the catalogs (cats[0..k), weight scale per catalog) by mesh
 // cell into one object set; cell_start (N^3 + 1 entries) receives the offsets.
 template <typename T>
-lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const double* wscale, int k, bool shape,
-                    GObjSet<T> out) {
+lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const double* wscale,
+                    const double* const* wscale_dev, int k, bool shape, GObjSet<T> out, hipStream_t st) {
   const int64_t ncell = static_cast<int64_t>(p->cfg.mesh_n) * p->cfg.mesh_n * p->cfg.mesh_n;
   uint32_t* starts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.starts_g : L.starts_d));
   uint32_t* cell_of = reinterpret_cast<uint32_t*>(wsp(p, L.cell_of));
   uint32_t* rank = reinterpret_cast<uint32_t*>(wsp(p, L.rank));
   uint32_t* bsum = reinterpret_cast<uint32_t*>(wsp(p, L.bsum));
   LPP_TRY(prof_begin(p));
-  LPP_TRY(launch_fill_zero(starts, 4 * static_cast<size_t>(ncell + 1), p->stream));
+  LPP_TRY(launch_fill_zero(starts, 4 * static_cast<size_t>(ncell + 1), st));
   int64_t off = 0;
   for (int i = 0; i < k; ++i) {
-    LPP_TRY(launch_cell_count(cats[i], p->geo, starts, rank + off, cell_of + off, p->stream));
+    LPP_TRY(launch_cell_count(cats[i], p->geo, starts, rank + off, cell_of + off, st));
     off += cats[i].n;
   }
-  LPP_TRY(launch_big_scan(starts, ncell, bsum, starts, p->stream));
+  LPP_TRY(launch_big_scan(starts, ncell, bsum, starts, st));
   off = 0;
   for (int i = 0; i < k; ++i) {
-    LPP_TRY(launch_cell_scatter<T>(cats[i], p->geo, wscale[i], shape ? 1 : 0, starts, rank + off, cell_of + off, out,
-                                   p->stream));
+    LPP_TRY(launch_cell_scatter<T>(cats[i], p->geo, wscale[i], wscale_dev[i], shape ? 1 : 0, starts, rank + off,
+                                   cell_of + off, out, st));
     off += cats[i].n;
   }
   LPP_TRY(prof_end(p, LPP_STAGE_SORT, 4 + 2 * k));
@@ -409,20 +418,19 @@ lpp_status sums_status(const double* s) {
   return LPP_OK;
 }
 
-template <typename T>
-lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out) {
-  const lpp_config& cfg = p->cfg;
-  lpp_status s;
-  if ((s = check_catalog_args(gal, need_shape(p))) != LPP_OK) return s;
-  if ((s = check_catalog_args(ran, false)) != LPP_OK) return s;
-  if (!out || !out->re || !out->im || !out->n_modes || !out->k_eff || !out->k_lo || !out->k_hi) return LPP_E_INVALID;
-  if ((s = ensure_tables(p)) != LPP_OK) return s;
-  if ((s = ensure_workspace(p, gal->n, ran->n)) != LPP_OK) return s;
-  const Layout L = layout(p, p->cap_gal, p->cap_ran);
-  const int N = cfg.mesh_n, nb = cfg.n_kbins;
-  const double vol = cfg.box_size * cfg.box_size * cfg.box_size;
+// Host-side scalars of one estimate (Sec. III.A normalisation and shot noise).
+struct Scalars {
+  double alpha, I, shot_dd, shot_plus, swg, swr;
+};
 
-  RawCat rg, rr;
+// Validation, staging and the FP64 catalog sums of one estimate: the part
+// that needs the host (one synchronisation).  rg / rr point at the caller's
+// device columns, or at the staged copies of host columns.
+lpp_status prepare(lpp_plan_s* p, const Layout& L, const lpp_catalog* gal, const lpp_catalog* ran, RawCat& rg,
+                   RawCat& rr, Scalars& sc) {
+  lpp_status s;
+  const lpp_config& cfg = p->cfg;
+  const double vol = cfg.box_size * cfg.box_size * cfg.box_size;
   lpp_catalog gcat = *gal, rcat = *ran;
   rcat.g1 = rcat.g2 = nullptr;  // shapes of randoms are ignored
   if (!need_shape(p)) gcat.g1 = gcat.g2 = nullptr;
@@ -436,42 +444,58 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   const double nbar_default = sums[0] / vol;
   if ((s = catalog_sums(p, L, rg, &rr, nbar_default, sums)) != LPP_OK) return s;
   if ((s = sums_status(sums + 8)) != LPP_OK) return s;
-  const double swg = sums[0], swr = sums[8];
-  if (!(swr != 0.0)) return LPP_E_NO_RANDOMS;
-  const double alpha = swg / swr;
-  const double I = alpha * sums[10];
-  if (!(I > 0.0) || !std::isfinite(I)) return LPP_E_NO_RANDOMS;
-  out->alpha = alpha;
-  out->norm_I = I;
-  out->shot_dd = (sums[1] + alpha * alpha * sums[9]) / I;
-  out->shot_plus = sums[3] / I;
-  out->sum_w_gal = swg;
-  out->sum_w_ran = swr;
+  sc.swg = sums[0];
+  sc.swr = sums[8];
+  if (!(sc.swr != 0.0)) return LPP_E_NO_RANDOMS;
+  sc.alpha = sc.swg / sc.swr;
+  sc.I = sc.alpha * sums[10];
+  if (!(sc.I > 0.0) || !std::isfinite(sc.I)) return LPP_E_NO_RANDOMS;
+  sc.shot_dd = (sums[1] + sc.alpha * sc.alpha * sums[9]) / sc.I;
+  sc.shot_plus = sums[3] / sc.I;
+  return LPP_OK;
+}
 
-  const hipStream_t st = p->stream;
-  const size_t M = mesh_bytes(p);
+size_t acc_doubles(const lpp_plan_s* p) {
+  const size_t nb = static_cast<size_t>(p->cfg.n_kbins);
+  return 2 * nb * static_cast<size_t>(n_acc(p)) + 8 * nb;
+}
+
+// The device part of one estimate: counting sort, footprint, gathers, 3D
+// transforms and shell sums into acc (acc_doubles(p) FP64 values: the series
+// rows [na][2nb], then the two bases as [re, im, counts, ksum] rows of width
+// 4nb).  No host synchronisation and no host-side reads, so that it can be
+// captured into a graph.  The randoms enter the density set with weight
+// -alpha w, alpha = alpha_host * (*alpha_dev) (alpha_dev nullable).
+template <typename T>
+lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, const RawCat& rr, double alpha_host,
+                           const double* alpha_dev, double* acc, hipStream_t st) {
+  lpp_status s;
+  const lpp_config& cfg = p->cfg;
+  const int N = cfg.mesh_n, nb = cfg.n_kbins;
   void* Bd = wsp(p, L.mesh[0]);
   void* Bg = wsp(p, L.mesh[1]);
   void* W[kWork];
   for (int i = 0; i < kWork; ++i) W[i] = L.work[i] ? wsp(p, L.work[i]) : nullptr;
   const bool il = cfg.interlacing != 0;
 
-  GObjSet<T> setd = objset<T>(p, L, false, gal->n + ran->n);
-  GObjSet<T> setg = objset<T>(p, L, true, gal->n);
+  GObjSet<T> setd = objset<T>(p, L, false, rg.n + rr.n);
+  GObjSet<T> setg = objset<T>(p, L, true, rg.n);
   const uint32_t* starts_d = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d));
   const uint32_t* starts_g = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_g));
   const Footprint fpd = footprint_at(p, L.fp[0]), fpg = footprint_at(p, L.fp[1]);
   if (need_density(p)) {
     const RawCat cs[2] = {rg, rr};
-    const double ws[2] = {1.0, -alpha};
-    if ((s = sort_set<T>(p, L, cs, ws, 2, false, setd)) != LPP_OK) return s;
+    const double ws[2] = {1.0, -alpha_host};
+    const double* wd[2] = {nullptr, alpha_dev};
+    if ((s = sort_set<T>(p, L, cs, ws, wd, 2, false, setd, st)) != LPP_OK) return s;
     LPP_TRY(prof_begin(p));
     LPP_TRY(launch_footprint(starts_d, N, fpd, st));
     LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2));
   }
   if (need_shape(p)) {
     const double ws[1] = {1.0};
-    if ((s = sort_set<T>(p, L, &rg, ws, 1, true, setg)) != LPP_OK) return s;
+    const double* wd[1] = {nullptr};
+    if ((s = sort_set<T>(p, L, &rg, ws, wd, 1, true, setg, st)) != LPP_OK) return s;
     LPP_TRY(prof_begin(p));
     LPP_TRY(launch_footprint(starts_g, N, fpg, st));
     LPP_TRY(prof_end(p, LPP_STAGE_SORT, 2));
@@ -479,9 +503,8 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
 
   const int na = n_acc(p);
   // [na][2nb] series rows, then the two bases as [re, im, counts, ksum] rows of width 4nb
-  double* acc = reinterpret_cast<double*>(wsp(p, L.acc));
   double* partial = reinterpret_cast<double*>(wsp(p, L.bin_partial));
-  const size_t acc_len = 2 * static_cast<size_t>(nb) * na + 8 * static_cast<size_t>(nb);
+  const size_t acc_len = acc_doubles(p);
   LPP_TRY(launch_fill_zero(acc, 8 * acc_len, st));
   BinArgs ba{};
   ba.N = N;
@@ -571,10 +594,21 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   };
   if ((s = run_set(dens, setd, starts_d, 0, fpd)) != LPP_OK) return s;
   if ((s = run_set(shape, setg, starts_g, 1, fpg)) != LPP_OK) return s;
-  std::vector<double> host_acc(acc_len);
-  LPP_TRY(hipMemcpyAsync(host_acc.data(), acc, 8 * acc_len, hipMemcpyDeviceToHost, st));
-  LPP_TRY(hipStreamSynchronize(st));
-  prof_collect(p);
+  return LPP_OK;
+}
+
+// FP64 assembly on the host from the shell sums: prefactors, normalisation,
+// shot noise (monopoles only) and the truncated E/B map.
+void assemble(const lpp_plan_s* p, const Scalars& sc, std::vector<double>& host_acc, lpp_result* out) {
+  const lpp_config& cfg = p->cfg;
+  const int nb = cfg.n_kbins, na = n_acc(p);
+  const double I = sc.I;
+  out->alpha = sc.alpha;
+  out->norm_I = sc.I;
+  out->shot_dd = sc.shot_dd;
+  out->shot_plus = sc.shot_plus;
+  out->sum_w_gal = sc.swg;
+  out->sum_w_ran = sc.swr;
   // the mode counts come from whichever base was computed (both give the same)
   const double* brow = host_acc.data() + static_cast<size_t>(2) * nb * na + (need_density(p) ? 0 : 4 * nb);
   std::vector<double> counts(brow + 2 * nb, brow + 3 * nb), ksum(brow + 3 * nb, brow + 4 * nb);
@@ -636,6 +670,27 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
       }
     }
   }
+}
+
+template <typename T>
+lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog* ran, lpp_result* out) {
+  lpp_status s;
+  if ((s = check_catalog_args(gal, need_shape(p))) != LPP_OK) return s;
+  if ((s = check_catalog_args(ran, false)) != LPP_OK) return s;
+  if (!out || !out->re || !out->im || !out->n_modes || !out->k_eff || !out->k_lo || !out->k_hi) return LPP_E_INVALID;
+  if ((s = ensure_tables(p)) != LPP_OK) return s;
+  if ((s = ensure_workspace(p, gal->n, ran->n)) != LPP_OK) return s;
+  const Layout L = layout(p, p->cap_gal, p->cap_ran);
+  RawCat rg, rr;
+  Scalars sc{};
+  if ((s = prepare(p, L, gal, ran, rg, rr, sc)) != LPP_OK) return s;
+  double* acc = reinterpret_cast<double*>(wsp(p, L.acc));
+  if ((s = device_pipeline<T>(p, L, rg, rr, sc.alpha, nullptr, acc, p->stream)) != LPP_OK) return s;
+  std::vector<double> host_acc(acc_doubles(p));
+  LPP_TRY(hipMemcpyAsync(host_acc.data(), acc, 8 * host_acc.size(), hipMemcpyDeviceToHost, p->stream));
+  LPP_TRY(hipStreamSynchronize(p->stream));
+  prof_collect(p);
+  assemble(p, sc, host_acc, out);
   return LPP_OK;
 }
 
@@ -656,13 +711,140 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   if ((s = sums_status(sums)) != LPP_OK) return s;
   GObjSet<T> setd = objset<T>(p, L, false, c->n);
   const double ws[1] = {scale};
-  if ((s = sort_set<T>(p, L, &rc, ws, 1, false, setd)) != LPP_OK) return s;
+  const double* wd[1] = {nullptr};
+  if ((s = sort_set<T>(p, L, &rc, ws, wd, 1, false, setd, p->stream)) != LPP_OK) return s;
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
   void* meshes[1] = {mesh};
   LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, &s0, 1, 0, meshes,
                            nullptr, p->stream));
   LPP_TRY(hipStreamSynchronize(p->stream));
   return LPP_OK;
+}
+
+void drop_graph(lpp_plan_s* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->gkey.clear();
+}
+
+uint64_t key_of(const void* ptr) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(ptr)); }
+
+// A batch of catalogs.  Every catalog is validated and its scalars computed
+// first (one synchronisation each).  When all catalogs are device-resident,
+// the device pipelines of the valid ones are captured into one HIP graph
+// (on a capture stream of the plan) and the graph is launched on the plan's
+// stream; a later call with the same pointers, sizes and workspace replays
+// it without capturing again.  The randoms' -alpha weight of catalog i is
+// read from a device table, so the graph does not depend on the scalars.
+// Catalogs on the host go through lpp_estimate one by one.
+template <typename T>
+lpp_status run_batch(lpp_plan_s* p, int32_t n, const lpp_catalog* gals, const lpp_catalog* rans, lpp_result* outs,
+                     lpp_status* per) {
+  lpp_status s;
+  int64_t mg = 1, mr = 1;
+  bool device = true;
+  for (int i = 0; i < n; ++i) {
+    mg = std::max(mg, gals[i].n);
+    mr = std::max(mr, rans[i].n);
+    device = device && gals[i].on_device && rans[i].on_device;
+  }
+  if (n == 0) return LPP_OK;
+  if ((s = ensure_tables(p)) != LPP_OK) return s;
+  if ((s = ensure_workspace(p, mg, mr)) != LPP_OK) return s;
+  lpp_status first = LPP_OK;
+  if (!device) {
+    for (int i = 0; i < n; ++i) {
+      per[i] = lpp_estimate(p, &gals[i], &rans[i], &outs[i]);
+      if (per[i] != LPP_OK && first == LPP_OK) first = per[i];
+    }
+    return first;
+  }
+  const Layout L = layout(p, p->cap_gal, p->cap_ran);
+  std::vector<RawCat> rg(n), rr(n);
+  std::vector<Scalars> sc(n);
+  std::vector<int> valid;
+  for (int i = 0; i < n; ++i) {
+    per[i] = check_catalog_args(&gals[i], need_shape(p));
+    if (per[i] == LPP_OK) per[i] = check_catalog_args(&rans[i], false);
+    const lpp_result* o = &outs[i];
+    if (per[i] == LPP_OK && (!o->re || !o->im || !o->n_modes || !o->k_eff || !o->k_lo || !o->k_hi))
+      per[i] = LPP_E_INVALID;
+    if (per[i] == LPP_OK) per[i] = prepare(p, L, &gals[i], &rans[i], rg[i], rr[i], sc[i]);
+    if (per[i] == LPP_OK)
+      valid.push_back(i);
+    else if (first == LPP_OK)
+      first = per[i];
+  }
+  if (valid.empty()) return first;
+  const size_t nv = valid.size(), acc_len = acc_doubles(p);
+  const size_t need = nv * (1 + acc_len);
+  if (need > p->d_batch_cap) {
+    drop_graph(p);
+    if (p->d_batch) (void)hipFree(p->d_batch);
+    p->d_batch = nullptr;
+    p->d_batch_cap = 0;
+    if (hipMalloc(&p->d_batch, 8 * need) != hipSuccess) {
+      (void)hipGetLastError();
+      return LPP_E_NOMEM;
+    }
+    p->d_batch_cap = need;
+  }
+  double* d_alpha = p->d_batch;
+  double* d_rows = p->d_batch + nv;
+  std::vector<double> alpha(nv);
+  for (size_t j = 0; j < nv; ++j) alpha[j] = sc[valid[j]].alpha;
+  LPP_TRY(hipMemcpyAsync(d_alpha, alpha.data(), 8 * nv, hipMemcpyHostToDevice, p->stream));
+
+  // what the graph depends on: workspace, tables, batch buffers and every catalog column
+  std::vector<uint64_t> key = {key_of(p->ws), key_of(p->d_batch), static_cast<uint64_t>(p->cap_gal),
+                               static_cast<uint64_t>(p->cap_ran), nv};
+  for (int i : valid)
+    for (const RawCat* c : {&rg[i], &rr[i]}) {
+      for (const void* q : {c->x, c->y, c->z, c->w, c->nbar, c->g1, c->g2}) key.push_back(key_of(q));
+      key.push_back(static_cast<uint64_t>(c->n));
+      key.push_back(static_cast<uint64_t>(c->dtype));
+    }
+  if (!p->gexec || key != p->gkey) {
+    drop_graph(p);
+    if (!p->cap_stream) LPP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    const bool prof = p->prof_on;
+    p->prof_on = false;  // no timing events inside the graph
+    LPP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    lpp_status cs = LPP_OK;
+    for (size_t j = 0; j < nv && cs == LPP_OK; ++j) {
+      const int i = valid[j];
+      cs = device_pipeline<T>(p, L, rg[i], rr[i], 1.0, d_alpha + j, d_rows + j * acc_len, p->cap_stream);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+    p->prof_on = prof;
+    if (cs != LPP_OK || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return cs != LPP_OK ? cs : hip_status(ce);
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_status(ie);
+    }
+    p->graph = g;
+    p->gexec = ge;
+    p->gkey = key;
+    ++p->graph_captures;
+  }
+  LPP_TRY(hipGraphLaunch(p->gexec, p->stream));
+  ++p->graph_replays;
+  std::vector<double> rows(nv * acc_len);
+  LPP_TRY(hipMemcpyAsync(rows.data(), d_rows, 8 * rows.size(), hipMemcpyDeviceToHost, p->stream));
+  LPP_TRY(hipStreamSynchronize(p->stream));
+  for (size_t j = 0; j < nv; ++j) {
+    std::vector<double> h(rows.begin() + j * acc_len, rows.begin() + (j + 1) * acc_len);
+    assemble(p, sc[valid[j]], h, &outs[valid[j]]);
+  }
+  return first;
 }
 
 }  // namespace
@@ -747,6 +929,10 @@ lpp_status lpp_plan_destroy(lpp_plan p) {
   if (p->own_ws && p->ws) (void)hipFree(p->ws);
   if (p->tabs) (void)hipFree(p->tabs);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_batch) (void)hipFree(p->d_batch);
   delete p;
   return LPP_OK;
 }
@@ -797,19 +983,19 @@ lpp_status lpp_estimate(lpp_plan p, const lpp_catalog* gal, const lpp_catalog* r
 lpp_status lpp_estimate_batch(lpp_plan p, int32_t n, const lpp_catalog* gals, const lpp_catalog* rans,
                               lpp_result* outs, lpp_status* per) {
   if (!p || n < 0 || (n > 0 && (!gals || !rans || !outs || !per))) return LPP_E_INVALID;
-  // size the workspace once for the largest catalog
-  int64_t mg = 1, mr = 1;
-  for (int i = 0; i < n; ++i) {
-    mg = std::max(mg, gals[i].n);
-    mr = std::max(mr, rans[i].n);
+  try {
+    return p->cfg.precision == LPP_F64 ? run_batch<double>(p, n, gals, rans, outs, per)
+                                       : run_batch<float>(p, n, gals, rans, outs, per);
+  } catch (...) {
+    return LPP_E_NOMEM;
   }
-  if (n > 0 && ensure_device(p) == LPP_OK) (void)ensure_workspace(p, mg, mr);
-  lpp_status first = LPP_OK;
-  for (int i = 0; i < n; ++i) {
-    per[i] = lpp_estimate(p, &gals[i], &rans[i], &outs[i]);
-    if (per[i] != LPP_OK && first == LPP_OK) first = per[i];
-  }
-  return first;
+}
+
+lpp_status lpp_batch_stats(lpp_plan p, int64_t* captures, int64_t* replays) {
+  if (!p || !captures || !replays) return LPP_E_INVALID;
+  *captures = p->graph_captures;
+  *replays = p->graph_replays;
+  return LPP_OK;
 }
 
 lpp_status lpp_deposit_weights(lpp_plan p, const lpp_catalog* cat, double scale, void* mesh) {

@@ -410,10 +410,12 @@ __global__ void cell_count_kernel(RawCat c, Geometry g, uint32_t* counts, uint32
 }
 
 template <typename T>
-__global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, int shape, const uint32_t* starts,
-                                    const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out) {
+__global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const double* __restrict__ wscale_dev,
+                                    int shape, const uint32_t* starts, const uint32_t* rank,
+                                    const uint32_t* cell_of_obj, GObjSet<T> out) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= c.n) return;
+  if (wscale_dev != nullptr) wscale *= *wscale_dev;
   const int N = g.N;
   const double ux = (ldc(c.x, i, c.dtype) - g.origin[0]) / g.H;
   const double uy = (ldc(c.y, i, c.dtype) - g.origin[1]) / g.H;
@@ -611,11 +613,11 @@ hipError_t launch_big_scan(const uint32_t* counts, int64_t n, uint32_t* bsum, ui
 }
 
 template <typename T>
-hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
+hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, const double* wscale_dev, int shape, const uint32_t* starts,
                                const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, hipStream_t st) {
   if (c.n == 0) return hipSuccess;
-  cell_scatter_kernel<T><<<static_cast<unsigned>((c.n + 255) / 256), 256, 0, st>>>(c, g, wscale, shape, starts, rank,
-                                                                                    cell_of_obj, out);
+  cell_scatter_kernel<T><<<static_cast<unsigned>((c.n + 255) / 256), 256, 0, st>>>(c, g, wscale, wscale_dev, shape,
+                                                                                    starts, rank, cell_of_obj, out);
   return hipGetLastError();
 }
 
@@ -663,9 +665,9 @@ hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hip
   return hipGetLastError();
 }
 
-template hipError_t launch_cell_scatter<float>(const RawCat&, const Geometry&, double, int, const uint32_t*,
+template hipError_t launch_cell_scatter<float>(const RawCat&, const Geometry&, double, const double*, int, const uint32_t*,
                                                const uint32_t*, const uint32_t*, GObjSet<float>, hipStream_t);
-template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, double, int, const uint32_t*,
+template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, double, const double*, int, const uint32_t*,
                                                 const uint32_t*, const uint32_t*, GObjSet<double>, hipStream_t);
 template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec*,
                                          int, int, void* const*, const uint8_t*, hipStream_t);

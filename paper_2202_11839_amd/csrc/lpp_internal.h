@@ -119,8 +119,10 @@ hipError_t launch_cell_count(const RawCat& c, const Geometry& g, uint32_t* count
 // counts and starts may alias
 hipError_t launch_big_scan(const uint32_t* counts, int64_t n, uint32_t* bsum, uint32_t* starts, hipStream_t st);
 template <typename T>
-hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, int shape, const uint32_t* starts,
-                               const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, hipStream_t st);
+// The density weight of each object is w * wscale * (*wscale_dev) (wscale_dev nullable).
+hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, const double* wscale_dev, int shape,
+                               const uint32_t* starts, const uint32_t* rank, const uint32_t* cell_of_obj,
+                               GObjSet<T> out, hipStream_t st);
 // Footprint of a cell-sorted object set, as 0/1 byte flags (nt = N / kTile):
 //   row[y + N z]      node row (y, z) can receive weight: some object lies in
 //                     cells y-2..y+1, z-2..z+1 (the reach of every window

@@ -293,3 +293,53 @@ def test_batch_statuses(lpp):
     cfg = E.Config(mesh=n, box=box, origin=origin, assignment=3, interlacing=1, lmax=4, n_kbins=5)
     for i in (0, 1, 3):
         _compare(outs[i], E.mesh64(cats[i][0], cats[i][1], cfg), 1e-9)
+
+
+def _to_dev(c, dtype):
+    import torch
+    return Catalog(*[None if v is None else torch.tensor(v, dtype=dtype, device="cuda")
+                     for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_graph_matches_oracle_and_replays(lpp, prec):
+    """A batch of device-resident mocks of different sizes goes through one
+    captured graph; every catalog matches the oracle; a second call on the
+    same buffers replays the graph (no new capture), also after the buffers
+    were refilled with other mocks of the same sizes, with eager estimates in
+    between; an invalid catalog gets its own status and leaves the rest
+    alone."""
+    import torch
+    n, box, origin = 32, 150.0, (300.0, 200.0, 250.0)
+    tol = 1e-9 if prec == "f64" else 1e-4
+    plan = lpp.Plan(n, box, origin, assignment=3, interlacing=1, precision=prec, lmax=4, n_kbins=10)
+    cfg = E.Config(mesh=n, box=box, origin=origin, assignment=3, interlacing=1, lmax=4, n_kbins=10)
+    sizes = [(700, 2500), (2000, 9000), (400, 5000)]
+    cats = [_cats(500 + i, ng, nr, origin, box) for i, (ng, nr) in enumerate(sizes)]
+    dev = [(_to_dev(g, torch.float64), _to_dev(r, torch.float64)) for g, r in cats]
+    outs = plan.estimate_batch([d[0] for d in dev], [d[1] for d in dev])
+    assert plan.batch_stats() == (1, 1)
+    for (g, r), o in zip(cats, outs):
+        _compare(o, E.mesh64(g, r, cfg), tol)
+    # eager work in between, then the same buffers refilled with other mocks
+    single = plan.estimate(*cats[1])
+    _compare(single, E.mesh64(*cats[1], cfg), tol)
+    cats2 = [_cats(900 + i, ng, nr, origin, box) for i, (ng, nr) in enumerate(sizes)]
+    for (d_g, d_r), (g, r) in zip(dev, cats2):
+        for dst, src in ((d_g, g), (d_r, r)):
+            for name in ("x", "y", "z", "w", "nbar", "g1", "g2"):
+                t = getattr(dst, name)
+                if t is not None:
+                    t.copy_(torch.tensor(getattr(src, name), dtype=torch.float64))
+    for rep in range(2):
+        outs2 = plan.estimate_batch([d[0] for d in dev], [d[1] for d in dev])
+        assert plan.batch_stats() == (1, 2 + rep)
+        for (g, r), o in zip(cats2, outs2):
+            _compare(o, E.mesh64(g, r, cfg), tol)
+    # an invalid catalog: its own status; the graph is captured again for the valid ones
+    dev[1][0].x[5] = float("nan")
+    outs3 = plan.estimate_batch([d[0] for d in dev], [d[1] for d in dev])
+    assert isinstance(outs3[1], lpp.LppError) and outs3[1].status == 2
+    for i in (0, 2):
+        _compare(outs3[i], E.mesh64(*cats2[i], cfg), tol)
+    assert plan.batch_stats()[0] == 2
