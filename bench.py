@@ -118,6 +118,53 @@ def committed_traffic():
     return rec.get("bytes_per_launch")
 
 
+def batch_c3(lpp, torch, k, reps):
+    """The 256^3 batch workload: k mocks spread over the 64-mock size ladder
+    N_i = round(0.2e6 10^(i/63)) galaxies (10x randoms), each with its own
+    GRF, device-resident in float32, through lpp_estimate_batch (one captured
+    graph, replayed) and, for comparison, through lpp_estimate one by one."""
+    import numpy as np
+    from synth import WORKLOADS, c3_sizes, make_catalogs
+    wl = dict(WORKLOADS["c3"])
+    ladder = c3_sizes(64)
+    pick = sorted(set(int(round(x)) for x in np.linspace(0, 63, k)))
+    t0 = time.perf_counter()
+    gals, rans = [], []
+    for i in pick:
+        g, r = make_catalogs(wl, mock=i, n_gal=ladder[i], n_ran=10 * ladder[i])
+        f = lambda c: type(c)(*[None if v is None else torch.tensor(v, dtype=torch.float32, device="cuda")
+                                for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+        gals.append(f(g))
+        rans.append(f(r))
+    torch.cuda.synchronize()
+    ngal = sum(ladder[i] for i in pick)
+    log(f"batch: {len(pick)} mocks generated in {time.perf_counter() - t0:.1f} s ({ngal} galaxies)")
+    plan = plan_for(lpp, wl, "f32")
+    outs = plan.estimate_batch(gals, rans)  # capture
+    assert all(isinstance(o, dict) for o in outs), outs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.estimate_batch(gals, rans)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    for g, r in zip(gals, rans):  # warm-up of the eager path
+        plan.estimate(g, r)
+        break
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g, r in zip(gals, rans):
+        plan.estimate(g, r)
+    torch.cuda.synchronize()
+    de = time.perf_counter() - t0
+    caps, launches = plan.batch_stats()
+    log(f"batch: {len(pick)} mocks in {1e3 * dt:.1f} ms per batch (graph), {1e3 * de:.1f} ms one by one")
+    return {"workload": f"{len(pick)} mocks of the 256^3 wedge batch (mock indices {pick[0]}..{pick[-1]} of the "
+                        f"0.2M-2M galaxy ladder, 10x randoms)", "mocks": len(pick), "galaxies": ngal,
+            "mocks_per_s": round(len(pick) / dt, 3), "ms_per_batch": round(1e3 * dt, 2),
+            "eager_mocks_per_s": round(len(pick) / de, 3), "graph_captures": caps, "graph_launches": launches}
+
+
 def cpu_baseline(wl, gal, ran):
     """The FP64 oracle timed on a bounded sample of the same workload.
 
@@ -167,6 +214,10 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--batch-mocks", type=int, default=8,
+                    help="mocks of the 256^3 batch workload (spread over its 64-mock size ladder) "
+                         "timed through the graph-captured batch path; 0 skips it")
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -233,6 +284,9 @@ def main():
         extra["fp64"] = {"value": round(args.fp64_steps / dt64, 4), "ms_per_step": round(1e3 * dt64 / args.fp64_steps, 2)}
         log(f"fp64: {1e3 * dt64 / args.fp64_steps:.1f} ms/estimate")
         del plan64
+
+    if args.batch_mocks > 0:
+        extra["batch_c3"] = batch_c3(lpp, torch, args.batch_mocks, args.batch_reps)
 
     cpu = None
     if args.cpu_baseline:

@@ -164,6 +164,28 @@ lpp_status lpp_estimate_batch(lpp_plan plan, int32_t n, const lpp_catalog* gals,
 /* Graphs captured and launched by lpp_estimate_batch over the plan's life. */
 lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 
+/* Launch shapes of the plan's kernels (0 = the built-in default).  Every
+ * choice gives the same result up to FP32/FP64 rounding order of the shell
+ * sums (the transforms and the deposit are unchanged bit for bit). */
+typedef struct {
+  int32_t fft_rows_x;      /* x pass: rows per workgroup (power of 2)                       */
+  int32_t fft_cols_yz;     /* y and z passes: columns per workgroup (power of 2)            */
+  int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
+  int32_t gather_density;  /* density fields per deposit pass, 1 .. 4                       */
+  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 2                         */
+} lpp_tuning;
+/* Current launch shapes with defaults resolved; set validates each field
+ * (LPP_E_INVALID for an unsupported value, the plan unchanged). */
+lpp_status lpp_get_tuning(lpp_plan plan, lpp_tuning* out);
+lpp_status lpp_set_tuning(lpp_plan plan, const lpp_tuning* t);
+/* Time the candidate launch shapes on this catalog pair (one estimate per
+ * candidate, one dimension at a time), keep the fastest in the plan, and
+ * store them in cache_path (a JSON-lines file, one record per mesh size,
+ * precision, assignment and interlacing; NULL = no file).  A plan created
+ * while the environment variable LPP_AUTOTUNE_CACHE names such a file starts
+ * from its record.  The catalogs follow lpp_estimate's rules. */
+lpp_status lpp_autotune(lpp_plan plan, const lpp_catalog* gal, const lpp_catalog* ran, const char* cache_path);
+
 /* Building blocks, exposed for testing and for callers with their own meshes.
  * All meshes are complex, index x + N*(y + N*z), interleaved (re, im), of the
  * plan's precision (float2 or double2), on the device. */

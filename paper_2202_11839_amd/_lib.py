@@ -25,7 +25,8 @@ STATUS = ["LPP_OK", "LPP_E_INVALID", "LPP_E_NONFINITE", "LPP_E_OUT_OF_BOX", "LPP
 EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace", "lpp_set_stream",
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
-           "lpp_reset_profile", "lpp_batch_stats"]
+           "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune"]
+TUNING_FIELDS = ["fft_rows_x", "fft_cols_yz", "bin_blocks", "gather_density", "gather_shape"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
 
@@ -34,6 +35,10 @@ class LppError(RuntimeError):
         self.status = status
         name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
         super().__init__(f"{what}: {name}")
+
+
+class Tuning(C.Structure):
+    _fields_ = [(name, C.c_int32) for name in TUNING_FIELDS]
 
 
 class Config(C.Structure):
@@ -240,6 +245,32 @@ class Plan:
             else:
                 outs.append(self._pack(res[i][0], RS[i], self.series))
         return outs
+
+    def tuning(self) -> Dict[str, int]:
+        """Launch shapes in use (defaults resolved)."""
+        t = Tuning()
+        _check(self.lib.lpp_get_tuning(self.handle, C.byref(t)), "lpp_get_tuning")
+        return {name: getattr(t, name) for name in TUNING_FIELDS}
+
+    def set_tuning(self, **kw) -> None:
+        """Set launch shapes (fields of lpp_tuning; 0 = default, unnamed fields keep their value)."""
+        t = Tuning()
+        _check(self.lib.lpp_get_tuning(self.handle, C.byref(t)), "lpp_get_tuning")
+        for name, value in kw.items():
+            if name not in TUNING_FIELDS:
+                raise KeyError(name)
+            setattr(t, name, int(value))
+        _check(self.lib.lpp_set_tuning(self.handle, C.byref(t)), "lpp_set_tuning")
+
+    def autotune(self, gal, ran, cache_path: Optional[str] = None) -> Dict[str, int]:
+        """Time the candidate launch shapes on this catalog pair and keep the fastest."""
+        keep: list = []
+        dt = self._dtype(gal)
+        cg, cr = _Cols(gal, dt, keep), _Cols(ran, dt, keep)
+        self._prepare_device(cg.struct.n, cr.struct.n)
+        path = None if cache_path is None else cache_path.encode()
+        _check(self.lib.lpp_autotune(self.handle, C.byref(cg.struct), C.byref(cr.struct), path), "lpp_autotune")
+        return self.tuning()
 
     def batch_stats(self) -> tuple:
         """(graphs captured, graph launches) of estimate_batch over the plan's life."""

@@ -77,6 +77,7 @@ struct lpp_plan_s {
   double* d_batch = nullptr;  // alpha[n], then n rows of acc_doubles
   size_t d_batch_cap = 0;     // doubles
   int64_t graph_captures = 0, graph_replays = 0;
+  lpp_tuning tune{};  // 0 = default
 };
 
 namespace {
@@ -190,7 +191,7 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.sums_partial = take(8 * 8 * static_cast<size_t>(catalog_sum_blocks()));
   L.sums_out = take(8 * 16);
   const int nb = p->cfg.n_kbins;
-  L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * bin_blocks(p->cfg.mesh_n));
+  L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * std::max(bin_blocks(p->cfg.mesh_n), kMaxBinBlocks));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
   for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
   L.total = off;
@@ -515,7 +516,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   ba.phase = p->d_phase;
   ba.invw = p->d_invw;
   ba.partial = partial;
-  ba.nblocks = bin_blocks(N);
+  ba.nblocks = p->tune.bin_blocks > 0 ? p->tune.bin_blocks : bin_blocks(N);
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
   // The base kernels write rows [re, im, cnt, ksum] of width 4nb; they are
   // reduced into their own rows after the series rows.
@@ -533,11 +534,11 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
     const FftPrune pr{fp.row, fp.plane, fp.cube, qmax};
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, pr, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, pr, st);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, pr, st);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz);
+    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
     return e;
   };
@@ -555,7 +556,8 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   const int copies = il ? 2 : 1;
   auto run_set = [&](const std::vector<Job>& jobs, const GObjSet<T>& set, const uint32_t* starts, int cplx,
                      const Footprint& fp) -> lpp_status {
-    const int per = cplx ? kGatherMaxComplex : kGatherMaxReal;
+    const int per = cplx ? (p->tune.gather_shape > 0 ? p->tune.gather_shape : kGatherMaxComplex)
+                         : (p->tune.gather_density > 0 ? p->tune.gather_density : kGatherMaxReal);
     for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
       const int nf = static_cast<int>(std::min<size_t>(per, jobs.size() - j0));
       FieldSpec specs[kWork];
@@ -847,6 +849,170 @@ lpp_status run_batch(lpp_plan_s* p, int32_t n, const lpp_catalog* gals, const lp
   return first;
 }
 
+constexpr int kMinBinBlocks = 64;
+
+lpp_tuning resolved_tuning(const lpp_plan_s* p) {
+  const int N = p->cfg.mesh_n;
+  const bool f64 = p->cfg.precision == LPP_F64;
+  lpp_tuning t = p->tune;
+  if (t.fft_rows_x <= 0) t.fft_rows_x = fft_default_lines(N, f64, 0);
+  if (t.fft_cols_yz <= 0) t.fft_cols_yz = fft_default_lines(N, f64, 1);
+  if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
+  if (t.gather_density <= 0) t.gather_density = kGatherMaxReal;
+  if (t.gather_shape <= 0) t.gather_shape = kGatherMaxComplex;
+  return t;
+}
+
+bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
+  const int N = p->cfg.mesh_n;
+  const bool f64 = p->cfg.precision == LPP_F64;
+  if (t.fft_rows_x != 0 && !fft_lines_supported(N, f64, 0, t.fft_rows_x)) return false;
+  if (t.fft_cols_yz != 0 && !fft_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
+  if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
+  if (t.gather_density < 0 || t.gather_density > kGatherMaxReal) return false;
+  if (t.gather_shape < 0 || t.gather_shape > kGatherMaxComplex) return false;
+  return true;
+}
+
+std::string tuning_key(const lpp_plan_s* p) {
+  char k[96];
+  std::snprintf(k, sizeof k, "N%d_%s_p%d_il%d", p->cfg.mesh_n, p->cfg.precision == LPP_F64 ? "f64" : "f32",
+                p->cfg.assignment, p->cfg.interlacing);
+  return k;
+}
+
+// One JSON object per line: {"key": "...", "fft_rows_x": a, "fft_cols_yz": b, ...}
+bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t) {
+  auto field = [&](const char* name, int32_t& v) {
+    const std::string pat = std::string("\"") + name + "\":";
+    const size_t i = line.find(pat);
+    if (i == std::string::npos) return false;
+    v = static_cast<int32_t>(std::strtol(line.c_str() + i + pat.size(), nullptr, 10));
+    return true;
+  };
+  const std::string kp = "\"key\":";
+  size_t i = line.find(kp);
+  if (i == std::string::npos) return false;
+  i = line.find('"', i + kp.size());
+  const size_t j = i == std::string::npos ? i : line.find('"', i + 1);
+  if (j == std::string::npos) return false;
+  key = line.substr(i + 1, j - i - 1);
+  return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_yz", t.fft_cols_yz) &&
+         field("bin_blocks", t.bin_blocks) && field("gather_density", t.gather_density) &&
+         field("gather_shape", t.gather_shape);
+}
+
+std::string tuning_line(const std::string& key, const lpp_tuning& t) {
+  char b[256];
+  std::snprintf(b, sizeof b,
+                "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_yz\": %d, \"bin_blocks\": %d, "
+                "\"gather_density\": %d, \"gather_shape\": %d}",
+                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape);
+  return b;
+}
+
+void load_tuning_cache(lpp_plan_s* p, const char* path) {
+  if (!path || !*path) return;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string want = tuning_key(p);
+  char buf[512];
+  while (std::fgets(buf, sizeof buf, f)) {
+    std::string key;
+    lpp_tuning t{};
+    if (parse_tuning_line(buf, key, t) && key == want && tuning_valid(p, t)) p->tune = t;
+  }
+  std::fclose(f);
+}
+
+bool store_tuning_cache(const lpp_plan_s* p, const char* path) {
+  std::vector<std::string> keep;
+  const std::string want = tuning_key(p);
+  if (std::FILE* f = std::fopen(path, "r")) {
+    char buf[512];
+    while (std::fgets(buf, sizeof buf, f)) {
+      std::string line(buf), key;
+      while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+      lpp_tuning t{};
+      if (parse_tuning_line(line, key, t) && key != want) keep.push_back(line);
+    }
+    std::fclose(f);
+  }
+  keep.push_back(tuning_line(want, p->tune));
+  std::FILE* f = std::fopen(path, "w");
+  if (!f) return false;
+  for (const std::string& l : keep) std::fprintf(f, "%s\n", l.c_str());
+  return std::fclose(f) == 0;
+}
+
+// Coordinate search over the launch shapes: for each dimension in turn, one
+// estimate per candidate with stage timing on, keeping the fastest by the
+// time of the stage that dimension drives.
+template <typename T>
+lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog* ran) {
+  std::vector<int64_t> nm(static_cast<size_t>(p->cfg.n_kbins));
+  std::vector<double> kv(4 * static_cast<size_t>(p->cfg.n_kbins));
+  std::vector<double> ri(2 * p->tab.series.size() * static_cast<size_t>(p->cfg.n_kbins));
+  lpp_result r{};
+  r.n_modes = nm.data();
+  r.k_eff = kv.data();
+  r.k_lo = kv.data() + p->cfg.n_kbins;
+  r.k_hi = kv.data() + 2 * p->cfg.n_kbins;
+  r.re = ri.data();
+  r.im = ri.data() + ri.size() / 2;
+  const bool prof = p->prof_on;
+  const lpp_tuning saved_tune = p->tune;
+  double saved_ms[LPP_N_STAGES];
+  int64_t saved_l[LPP_N_STAGES];
+  std::copy(p->prof_ms, p->prof_ms + LPP_N_STAGES, saved_ms);
+  std::copy(p->prof_launches, p->prof_launches + LPP_N_STAGES, saved_l);
+  lpp_status s = run_estimate<T>(p, gal, ran, &r);  // warm-up and argument check
+  if (s != LPP_OK) return s;
+  p->prof_on = true;
+  lpp_tuning best = resolved_tuning(p);
+  const int N = p->cfg.mesh_n;
+  const bool f64 = p->cfg.precision == LPP_F64;
+  auto measure = [&](const lpp_tuning& t, std::initializer_list<int> stages, double& ms) -> lpp_status {
+    p->tune = t;
+    for (int i = 0; i < LPP_N_STAGES; ++i) p->prof_ms[i] = 0.0;
+    const lpp_status e = run_estimate<T>(p, gal, ran, &r);
+    ms = 0.0;
+    for (int st : stages) ms += p->prof_ms[st];
+    return e;
+  };
+  auto search = [&](int32_t lpp_tuning::*field, const std::vector<int>& cands, std::initializer_list<int> stages)
+      -> lpp_status {
+    double best_ms = 1e300;
+    int best_v = best.*field;
+    for (int v : cands) {
+      lpp_tuning t = best;
+      t.*field = v;
+      if (!tuning_valid(p, t)) continue;
+      double ms = 0.0;
+      const lpp_status e = measure(t, stages, ms);
+      if (e != LPP_OK) return e;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_v = v;
+      }
+    }
+    best.*field = best_v;
+    return LPP_OK;
+  };
+  const int dx = fft_default_lines(N, f64, 0), dy = fft_default_lines(N, f64, 1);
+  s = search(&lpp_tuning::fft_rows_x, {dx / 2, dx, 2 * dx}, {LPP_STAGE_FFT_X});
+  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {dy / 4, dy / 2, dy, 2 * dy}, {LPP_STAGE_FFT_YZ});
+  if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096}, {LPP_STAGE_BIN});
+  if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 3, 4}, {LPP_STAGE_DEPOSIT});
+  if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2}, {LPP_STAGE_DEPOSIT});
+  p->prof_on = prof;
+  std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);
+  std::copy(saved_l, saved_l + LPP_N_STAGES, p->prof_launches);
+  p->tune = s == LPP_OK ? best : saved_tune;
+  if (s == LPP_OK) drop_graph(p);  // a captured batch used the old shapes
+  return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -916,6 +1082,7 @@ lpp_status lpp_plan_create(const lpp_config* cfg_in, lpp_plan* out) {
   p->geo.interlace = cfg.interlacing;
   p->geo.H = cfg.box_size / N;
   p->geo.box = cfg.box_size;
+  load_tuning_cache(p, std::getenv("LPP_AUTOTUNE_CACHE"));
   for (int i = 0; i < 3; ++i) {
     p->geo.origin[i] = cfg.box_origin[i];
     p->geo.rel[i] = cfg.box_origin[i] - cfg.observer[i];
@@ -996,6 +1163,32 @@ lpp_status lpp_batch_stats(lpp_plan p, int64_t* captures, int64_t* replays) {
   *captures = p->graph_captures;
   *replays = p->graph_replays;
   return LPP_OK;
+}
+
+lpp_status lpp_get_tuning(lpp_plan p, lpp_tuning* out) {
+  if (!p || !out) return LPP_E_INVALID;
+  *out = resolved_tuning(p);
+  return LPP_OK;
+}
+
+lpp_status lpp_set_tuning(lpp_plan p, const lpp_tuning* t) {
+  if (!p || !t || !tuning_valid(p, *t)) return LPP_E_INVALID;
+  p->tune = *t;
+  drop_graph(p);
+  return LPP_OK;
+}
+
+lpp_status lpp_autotune(lpp_plan p, const lpp_catalog* gal, const lpp_catalog* ran, const char* cache_path) {
+  if (!p) return LPP_E_INVALID;
+  try {
+    const lpp_status s = p->cfg.precision == LPP_F64 ? run_autotune<double>(p, gal, ran)
+                                                     : run_autotune<float>(p, gal, ran);
+    if (s != LPP_OK) return s;
+    if (cache_path && !store_tuning_cache(p, cache_path)) return LPP_E_INVALID;
+    return LPP_OK;
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
 }
 
 lpp_status lpp_deposit_weights(lpp_plan p, const lpp_catalog* cat, double scale, void* mesh) {

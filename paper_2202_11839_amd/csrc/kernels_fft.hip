@@ -135,44 +135,86 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   }
 }
 
-template <typename T, int N>
-hipError_t fft_axis_n(void* mesh, const void* tw, int axis, const FftPrune& pr, hipStream_t st) {
+// Lines per workgroup that a pass supports: at most 1024 threads (N/8 per line),
+// at most N columns for the strided passes, and LDS for the lines and twiddles.
+template <typename T, int N, int NCOL, bool ALONG>
+constexpr bool lines_ok() {
   using T2 = typename V2<T>::type;
-  constexpr int TL = N / 8;
-  constexpr int NX = (256 / TL) > 0 ? (256 / TL) : 1;
-  constexpr int LDSX = (sizeof(T) == 4 ? 8192 : 4096) / N;
-  constexpr int NY = LDSX < N ? LDSX : N;
-  T2* d = static_cast<T2*>(mesh);
-  const T2* w = static_cast<const T2*>(tw);
-  if (axis == 0) {
-    const unsigned bx = static_cast<unsigned>(static_cast<int64_t>(N) * N / NX);
-    fft_axis_kernel<T, N, NX, true><<<bx, NX * TL, 0, st>>>(d, 0, w, pr);
+  return NCOL * (N / 8) <= 1024 && (ALONG || NCOL <= N) &&
+         static_cast<size_t>(NCOL + 1) * N * sizeof(T2) <= 160 * 1024;
+}
+
+template <typename T, int N, int NCOL, bool ALONG>
+hipError_t fft_axis_launch(void* mesh, const void* tw, int axis, const FftPrune& pr, hipStream_t st) {
+  if constexpr (!lines_ok<T, N, NCOL, ALONG>()) {
+    return hipErrorInvalidValue;
   } else {
-    const unsigned by = static_cast<unsigned>(static_cast<int64_t>(N / NY) * N);
-    fft_axis_kernel<T, N, NY, false><<<by, NY * TL, 0, st>>>(d, axis, w, pr);
+    using T2 = typename V2<T>::type;
+    const unsigned grid = ALONG ? static_cast<unsigned>(static_cast<int64_t>(N) * N / NCOL)
+                                : static_cast<unsigned>(static_cast<int64_t>(N / NCOL) * N);
+    fft_axis_kernel<T, N, NCOL, ALONG><<<grid, NCOL * (N / 8), 0, st>>>(static_cast<T2*>(mesh), axis,
+                                                                         static_cast<const T2*>(tw), pr);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+}
+
+template <typename T, int N, bool ALONG>
+hipError_t fft_axis_lines(void* mesh, const void* tw, int axis, const FftPrune& pr, int lines, hipStream_t st) {
+  switch (lines) {
+    case 1: return fft_axis_launch<T, N, 1, ALONG>(mesh, tw, axis, pr, st);
+    case 2: return fft_axis_launch<T, N, 2, ALONG>(mesh, tw, axis, pr, st);
+    case 4: return fft_axis_launch<T, N, 4, ALONG>(mesh, tw, axis, pr, st);
+    case 8: return fft_axis_launch<T, N, 8, ALONG>(mesh, tw, axis, pr, st);
+    case 16: return fft_axis_launch<T, N, 16, ALONG>(mesh, tw, axis, pr, st);
+    case 32: return fft_axis_launch<T, N, 32, ALONG>(mesh, tw, axis, pr, st);
+    case 64: return fft_axis_launch<T, N, 64, ALONG>(mesh, tw, axis, pr, st);
+    case 128: return fft_axis_launch<T, N, 128, ALONG>(mesh, tw, axis, pr, st);
+    case 256: return fft_axis_launch<T, N, 256, ALONG>(mesh, tw, axis, pr, st);
+    case 512: return fft_axis_launch<T, N, 512, ALONG>(mesh, tw, axis, pr, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int N>
+hipError_t fft_axis_n(void* mesh, const void* tw, int axis, const FftPrune& pr, int lines, hipStream_t st) {
+  if (lines <= 0) lines = fft_default_lines(N, sizeof(T) == 8, axis);
+  return axis == 0 ? fft_axis_lines<T, N, true>(mesh, tw, axis, pr, lines, st)
+                   : fft_axis_lines<T, N, false>(mesh, tw, axis, pr, lines, st);
 }
 
 }  // namespace
 
+int fft_default_lines(int N, bool fp64, int axis) {
+  if (axis == 0) return std::max(1, 256 / (N / 8));  // 256 threads
+  return std::min(N, (fp64 ? 4096 : 8192) / N);      // 64 KB of lines in LDS
+}
+
+bool fft_lines_supported(int N, bool fp64, int axis, int lines) {
+  if (lines < 1 || (lines & (lines - 1)) != 0) return false;
+  const int threads = lines * (N / 8);
+  const size_t lds = static_cast<size_t>(lines + 1) * N * (fp64 ? 16 : 8);
+  return threads <= 1024 && (axis == 0 || lines <= N) && lds <= 160 * 1024;
+}
+
 template <typename T>
-hipError_t launch_fft_axis(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st) {
+hipError_t launch_fft_axis(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st,
+                           int lines) {
+  if (lines > 0 && !fft_lines_supported(N, sizeof(T) == 8, axis, lines)) return hipErrorInvalidValue;
   switch (N) {
     case 16:
-      return fft_axis_n<T, 16>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 16>(mesh, tw, axis, pr, lines, st);
     case 32:
-      return fft_axis_n<T, 32>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 32>(mesh, tw, axis, pr, lines, st);
     case 64:
-      return fft_axis_n<T, 64>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 64>(mesh, tw, axis, pr, lines, st);
     case 128:
-      return fft_axis_n<T, 128>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 128>(mesh, tw, axis, pr, lines, st);
     case 256:
-      return fft_axis_n<T, 256>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 256>(mesh, tw, axis, pr, lines, st);
     case 512:
-      return fft_axis_n<T, 512>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 512>(mesh, tw, axis, pr, lines, st);
     case 1024:
-      return fft_axis_n<T, 1024>(mesh, tw, axis, pr, st);
+      return fft_axis_n<T, 1024>(mesh, tw, axis, pr, lines, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -182,15 +224,15 @@ template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* tw, hipStream_t st) {
   const FftPrune full{nullptr, nullptr, nullptr, INT_MAX};
   for (int axis = 0; axis < 3; ++axis) {
-    const hipError_t e = launch_fft_axis<T>(mesh, N, tw, axis, full, st);
+    const hipError_t e = launch_fft_axis<T>(mesh, N, tw, axis, full, st, 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 template hipError_t launch_fft3d<float>(void*, int, const void*, hipStream_t);
-template hipError_t launch_fft_axis<float>(void*, int, const void*, int, const FftPrune&, hipStream_t);
-template hipError_t launch_fft_axis<double>(void*, int, const void*, int, const FftPrune&, hipStream_t);
+template hipError_t launch_fft_axis<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
+template hipError_t launch_fft_axis<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
 template hipError_t launch_fft3d<double>(void*, int, const void*, hipStream_t);
 
 }  // namespace lpp

@@ -173,9 +173,13 @@ struct FftPrune {
   const uint8_t* cube;  // x pass: kTile-node segments of a row outside the flagged cubes are zero
   int qmax;
 };
-// one axis (0: x, unit stride; 1: y; 2: z) of the 3D transform
+// one axis (0: x, unit stride; 1: y; 2: z) of the 3D transform; lines: lines
+// per workgroup (x rows, or y / z columns), 0 = fft_default_lines
 template <typename T>
-hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, const FftPrune& pr, hipStream_t st);
+hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, const FftPrune& pr, hipStream_t st,
+                           int lines);
+int fft_default_lines(int N, bool fp64, int axis);
+bool fft_lines_supported(int N, bool fp64, int axis, int lines);
 
 // Binning.  Tables: twiddles (N complex, exp(-2 pi i m/N)), phase (3N+1
 // complex, exp(-i pi m/N) for m = -3N/2..3N/2), invw (N reals, 1/W_1(n)).
@@ -192,7 +196,8 @@ struct BinArgs {
 };
 // The binning kernels read the transformed fields only at modes inside the
 // last shell, |n|^2 < T_nb, and the base kernels write the base only there.
-int bin_blocks(int N);
+int bin_blocks(int N);            // default workgroups of the shell-sum kernels
+constexpr int kMaxBinBlocks = 8192;
 template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st);
 template <typename T>

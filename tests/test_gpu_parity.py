@@ -343,3 +343,32 @@ def test_batch_graph_matches_oracle_and_replays(lpp, prec):
     for i in (0, 2):
         _compare(outs3[i], E.mesh64(*cats2[i], cfg), tol)
     assert plan.batch_stats()[0] == 2
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tuning_variants_match_oracle(lpp, prec):
+    """Every launch shape gives the oracle's result: rows per x-pass workgroup,
+    columns per strided workgroup, shell-sum workgroups and fields per deposit
+    pass, on the compact wedge footprint (64^3)."""
+    g, r, kw, ref = _footprint_case("wedge")
+    plan = lpp.Plan(precision=prec, **kw)
+    tol = 1e-9 if prec == "f64" else 1e-4
+    variants = [dict(fft_rows_x=16), dict(fft_rows_x=64), dict(fft_cols_yz=8), dict(fft_cols_yz=32),
+                dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
+                dict(gather_shape=1)]
+    base = plan.tuning()
+    for v in variants:
+        plan.set_tuning(**{**base, **v})
+        _compare(plan.estimate(g, r), ref, tol)
+
+
+def test_autotune_writes_cache_and_keeps_parity(lpp, tmp_path):
+    g, r, kw, ref = _footprint_case("wedge")
+    plan = lpp.Plan(precision="f32", **kw)
+    path = tmp_path / "tune.jsonl"
+    chosen = plan.autotune(g, r, cache_path=str(path))
+    line = path.read_text().strip().splitlines()
+    assert len(line) == 1 and '"key": "N64_f32_p3_il1"' in line[0]
+    for k, v in chosen.items():
+        assert f'"{k}": {v}' in line[0]
+    _compare(plan.estimate(g, r), ref, 1e-4)
