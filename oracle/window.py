@@ -1,0 +1,236 @@
+"""FP64 oracle of the window-convolved template path (Sec. III.B and IV.C).
+
+Test infrastructure only: the HIP path never imports this module.
+
+``window_multipoles``  the multipoles Q_l(r) of the window's auto-correlation
+    (eqs. windowQ, windowQ_ell) on the mesh, with the end-point line of
+    sight d = xhat of the first point of the pair.  The window is W(x) =
+    alpha sum_r w_r delta_D(x - x_r) (the randoms weighted to the galaxy
+    density), deposited like the estimator's density field.  The Legendre
+    polynomial L_l(rhat . xhat) is expanded in monomials of the Cartesian
+    components of rhat and xhat; every monomial coefficient of xhat is
+    deposited and transformed, cross-correlated with W by FFT, and contracted
+    with the same monomial of rhat in configuration space.  Q_l is the shell
+    average times (2l+1), divided by the cell volume (mesh sum -> integral)
+    and by I = alpha sum_r w_r^2 nbar_r, so that Q_0 -> 1 as r -> 0.
+
+``hankel``  the transforms H_l and H_l^{-1} of Sec. I (the paper's
+    definitions, with the factors 4 pi (-i)^l and i^l / (2 pi^2)) evaluated
+    with FFTLog (Hamilton 2000): on a log-spaced grid the input times r^3
+    (or k^3) is a sum of complex powers, each of which the spherical Bessel
+    kernel maps in closed form through its Mellin transform
+    int_0^inf t^(s-1) j_l(t) dt = sqrt(pi) 2^(s-2) Gamma((l+s)/2) / Gamma((3+l-s)/2).
+
+``template_plain``  the window-convolved multipoles of the linear tidal
+    alignment model used for the emulator: P_lin = (sigma8/sigma8_fid)^2
+    P_fid, P_+ = (A^2/4)(1-mu^2)^2 P_lin (no RSD on shapes) and
+    P_gd = -(A/2)(1-mu^2)(b + f mu^2) P_lin, whose multipoles are
+    P_+^(0,2,4) = A^2 {2/15, -4/21, 2/35} P_lin and P_gd^(2,4) =
+    -A {(7b+f)/42, f/105} P_lin; each is taken to xi by H^{-1}, multiplied by
+    Q^X_{l l'}(r) of eq. def_of_Q_llp and taken back by H_l
+    (eq. window_convolution_X_hankel), then interpolated (linear in ln k) to
+    the output wavenumbers.  The shot noise s_N 2 sigma_gamma^2 / nbar is
+    added to P~_+^(0) unconvolved.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from typing import Dict, Tuple
+
+import numpy as np
+from scipy.special import loggamma
+
+from . import geometry, mesh, special
+
+# ---------------------------------------------------------------------------
+# window multipoles on the mesh
+
+
+def _multinomial_monomials(j: int):
+    """{(a, b, c): multinomial(j; a, b, c)} for a + b + c = j."""
+    out = {}
+    for a in range(j + 1):
+        for b in range(j - a + 1):
+            c = j - a - b
+            out[(a, b, c)] = math.factorial(j) // (math.factorial(a) * math.factorial(b) * math.factorial(c))
+    return out
+
+
+def r_thresholds(n: int, box: float, n_rbins: int, rmax: float) -> np.ndarray:
+    """Integer thresholds on q = |n|^2 (n the minimum-image offset in cells):
+    bin b holds T_b <= q < T_{b+1}, with T_b = ceil((b u)(b u)), u = (rmax /
+    n_rbins) / (box / n), evaluated in FP64 in this order."""
+    u = (rmax / n_rbins) / (box / n)
+    return np.array([math.ceil((b * u) * (b * u)) for b in range(n_rbins + 1)], dtype=np.int64)
+
+
+def window_multipoles(ran, alpha: float, n: int, box: float, origin, observer, assignment: int,
+                      interlacing: int, compensate: int, lmax: int, n_rbins: int, rmax: float) -> Dict:
+    pos = ran.pos()
+    w = alpha * ran.w
+    xh = geometry.los(pos, observer)
+    comp = mesh.compensation(n, assignment) if compensate else np.ones((n,) * 3)
+    phase = mesh.interlace_phase(n) if interlacing else None
+
+    def transform(values):
+        F = np.fft.fftn(mesh.deposit(pos, values, n, box, origin, assignment))
+        if interlacing:
+            F2 = np.fft.fftn(mesh.deposit(pos, values, n, box, origin, assignment, shift=0.5))
+            F = 0.5 * (F + phase * F2)
+        return F / comp
+
+    F0 = transform(w)
+    m = mesh.signed_modes(n).astype(np.float64)
+    rx, ry, rz = np.meshgrid(m, m, m, indexing="ij")
+    q = (rx * rx + ry * ry + rz * rz).astype(np.int64)
+    rr = np.sqrt(q.astype(np.float64))
+    inv = np.where(rr > 0, 1.0 / np.where(rr > 0, rr, 1.0), 0.0)
+    rh = (rx * inv, ry * inv, rz * inv)
+    T = r_thresholds(n, box, n_rbins, rmax)
+    bidx = np.searchsorted(T, q, side="right") - 1
+    bidx[(q <= 0) | (q >= T[-1])] = -1
+    sel = bidx >= 0
+    counts = np.bincount(bidx[sel], minlength=n_rbins)
+    h = box / n
+    rsum = np.bincount(bidx[sel], weights=rr[sel] * h, minlength=n_rbins)
+    I = alpha * float(np.sum(ran.w ** 2 * ran.nbar))
+    vcell = h ** 3
+    ells = list(range(0, lmax + 1, 2))
+    cache = {}
+    Q = np.zeros((len(ells), n_rbins))
+    for i, l in enumerate(ells):
+        G = np.zeros((n,) * 3)
+        for j, c in enumerate(special.legendre(l)):
+            if c == 0:
+                continue
+            for a, mult in _multinomial_monomials(j).items():
+                if a not in cache:
+                    Fa = transform(w * xh[:, 0] ** a[0] * xh[:, 1] ** a[1] * xh[:, 2] ** a[2])
+                    cache[a] = np.real(np.fft.ifftn(np.conj(Fa) * F0))
+                G += float(c) * mult * rh[0] ** a[0] * rh[1] ** a[1] * rh[2] ** a[2] * cache[a]
+        s = np.bincount(bidx[sel], weights=G[sel], minlength=n_rbins)
+        Q[i] = (2 * l + 1) * s / (np.where(counts > 0, counts, 1) * vcell * I)
+    r_eff = np.where(counts > 0, rsum / np.where(counts > 0, counts, 1), 0.0)
+    return dict(ells=ells, Q=Q, counts=counts, r_eff=r_eff, norm_I=I, thresholds=T)
+
+
+# ---------------------------------------------------------------------------
+# FFTLog Hankel transforms
+
+
+def mellin_jl(l: int, s: np.ndarray) -> np.ndarray:
+    """int_0^inf t^(s-1) j_l(t) dt for complex s with -l < Re s < 2."""
+    return np.exp(math.log(math.sqrt(math.pi)) + (s - 2.0) * math.log(2.0) + loggamma(0.5 * (l + s))
+                  - loggamma(0.5 * (3.0 + l - s)))
+
+
+def log_grid(xmin: float, xmax: float, n: int) -> np.ndarray:
+    return np.exp(np.linspace(math.log(xmin), math.log(xmax), n))
+
+
+def fftlog_integral(x: np.ndarray, fx: np.ndarray, l: int, q: float, kr: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
+    """y_j and G(y_j) = int_0^inf f(x) j_l(x y) x^2 dx on the reciprocal log
+    grid y_j = kr / x_{N-1-j}, for f sampled at log-spaced x (FFTLog, bias q).
+
+    With u_n = f(x_n) x_n^(3-q) and c_m its DFT, f(x) x^3 = x^q (1/N) sum_m
+    c_m (x/x_0)^(i w_m), w_m = 2 pi m / (N d), d the log spacing.  Each term
+    integrates in closed form, int x^(q+iw) j_l(xy) dx/x = y^(-q-iw) M(q+iw),
+    and y_j = y_0 e^(j d) turns the sum over m into a second DFT."""
+    n = x.size
+    d = math.log(x[-1] / x[0]) / (n - 1)
+    u = fx * x ** (3.0 - q)
+    c = np.fft.fft(u)
+    w = np.fft.fftfreq(n, d=d) * 2.0 * math.pi
+    y = kr / x[::-1]
+    t = c * mellin_jl(l, q + 1j * w) * (x[0] * y[0]) ** (-1j * w) / n
+    return y, np.fft.fft(t).real * y ** (-q)
+
+
+def hankel(x: np.ndarray, fx: np.ndarray, l: int, inverse: bool, q: float = None) -> Tuple[np.ndarray, np.ndarray]:
+    """The paper's H_l (inverse=False: r -> k, 4 pi (-i)^l int r^2 dr j_l(kr) g)
+    or H_l^{-1} (inverse=True: k -> r, i^l int k^2 dk / (2 pi^2) j_l(kr) g)
+    for even l, on log grids.  q: FFTLog bias; the default (1.5 for k -> r;
+    1.0 for r -> k at l = 0, 0.5 at l >= 2) keeps x^(3-q) f small at both
+    ends of the grid for the template path's integrands (P ~ k at small k,
+    damped at large k; xi finite at small r, windowed at large r), which the
+    quadrature pins confirm."""
+    if l % 2:
+        raise ValueError("even multipoles only")
+    sign = (-1) ** (l // 2)
+    if q is None:
+        q = 1.5 if inverse else (1.0 if l == 0 else 0.5)
+    y, G = fftlog_integral(x, fx, l, q)
+    if inverse:
+        return y, sign * G / (2.0 * math.pi ** 2)
+    return y, sign * 4.0 * math.pi * G
+
+
+# ---------------------------------------------------------------------------
+# model, sigma8 and the plain template path
+
+PLUS_XI = {0: Fraction(2, 15), 2: Fraction(-4, 21), 4: Fraction(2, 35)}
+
+
+def gd_moments(b: float, f: float) -> Dict[int, float]:
+    """m=2 moments of -(1/2)(1-mu^2)(b+f mu^2) (per unit A and P_lin)."""
+    return {2: -(7.0 * b + f) / 42.0, 4: -f / 105.0}
+
+
+def sigma8(k: np.ndarray, pk: np.ndarray) -> float:
+    """Top-hat R = 8 Mpc/h rms of P(k) on a log grid (trapezoid in ln k)."""
+    x = 8.0 * k
+    wth = 3.0 * (np.sin(x) - x * np.cos(x)) / x ** 3
+    integrand = k ** 3 * pk * wth ** 2 / (2.0 * math.pi ** 2)
+    lnk = np.log(k)
+    return math.sqrt(float(np.sum(0.5 * (integrand[1:] + integrand[:-1]) * np.diff(lnk))))
+
+
+def q_on_grid(r_q: np.ndarray, Q: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Tabulated Q_l(r) -> grid r: linear in r, Q(0) = (1, 0, 0, ...), zero beyond the table."""
+    out = np.zeros((Q.shape[0], r.size))
+    xs = np.concatenate([[0.0], r_q])
+    for i in range(Q.shape[0]):
+        ys = np.concatenate([[1.0 if i == 0 else 0.0], Q[i]])
+        out[i] = np.interp(r, xs, ys, right=0.0)
+    return out
+
+
+def interp_lnk(k: np.ndarray, v: np.ndarray, kout: np.ndarray) -> np.ndarray:
+    return np.interp(np.log(kout), np.log(k), v)
+
+
+def template_plain(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.ndarray, params: np.ndarray,
+                   kout: np.ndarray, nbar: float, sigma_gamma: float, sigma8_fid: float = None) -> np.ndarray:
+    """Window-convolved P~_+^(0,2,4) and P~_Ed^(2,4) at kout for every
+    parameter point (A, b, f, sigma8, s_N): shape (n_pts, 5, n_k).
+    k: the log grid of pfid (also the FFTLog grid); Q: Q_0..Q_8 at r_q."""
+    s8f = sigma8(k, pfid) if sigma8_fid is None else sigma8_fid
+    r = 1.0 / k[::-1]
+    Qg = q_on_grid(r_q, Q, r)
+    wc = {}
+    for X, mX, ls, lps in (("plus", 0, (0, 2, 4), (0, 2, 4)), ("gd", 2, (2, 4), (2, 4))):
+        for l in ls:
+            for lp in lps:
+                c = [float(special.window_coef(mX, l, lp, lpp)) for lpp in (0, 2, 4, 6, 8)]
+                wc[(X, l, lp)] = np.tensordot(np.array(c), Qg, axes=(0, 0))
+    out = np.zeros((params.shape[0], 5, kout.size))
+    damp = np.exp(-(k / 10.0) ** 2)  # keeps k^3 P(k) localised on the grid; negligible for k <= 0.3
+    for p_i, (A, b, f, s8, sN) in enumerate(params):
+        plin = (s8 / s8f) ** 2 * pfid * damp
+        xi_plus = {lp: hankel(k, A * A * float(PLUS_XI[lp]) * plin, lp, inverse=True)[1] for lp in (0, 2, 4)}
+        gm = gd_moments(b, f)
+        xi_gd = {Lp: hankel(k, A * gm[Lp] * plin, Lp, inverse=True)[1] for Lp in (2, 4)}
+        row = 0
+        for l in (0, 2, 4):
+            g = sum(wc[("plus", l, lp)] * xi_plus[lp] for lp in (0, 2, 4))
+            kk, P = hankel(r, g, l, inverse=False)
+            out[p_i, row] = interp_lnk(kk, P, kout)
+            row += 1
+        for L in (2, 4):
+            g = sum(wc[("gd", L, Lp)] * xi_gd[Lp] for Lp in (2, 4))
+            kk, P = hankel(r, g, L, inverse=False)
+            out[p_i, row] = interp_lnk(kk, P, kout)
+            row += 1
+        out[p_i, 0] += sN * 2.0 * sigma_gamma ** 2 / nbar
+    return out

@@ -1,0 +1,158 @@
+"""Pins of the window / template oracle (oracle/window.py) against closed
+forms, quadrature and geometry, independent of its own formulas."""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import eval_legendre, spherical_jn
+
+from oracle import special as S
+from oracle import window as W
+from synth import Catalog, box_uniform
+
+
+def test_mellin_transform_of_spherical_bessel_closed_forms():
+    # int_0^inf j_0 = pi/2, int_0^inf j_2 = pi/4, int_0^inf t^(1/2) j_0 = Gamma(1/2) sin(pi/4)
+    assert abs(W.mellin_jl(0, np.array([1.0 + 0j]))[0] - math.pi / 2) < 1e-14
+    assert abs(W.mellin_jl(2, np.array([1.0 + 0j]))[0] - math.pi / 4) < 1e-14
+    assert abs(W.mellin_jl(0, np.array([1.5 + 0j]))[0] - math.sqrt(math.pi) * math.sin(math.pi / 4)) < 1e-14
+
+
+K = W.log_grid(1e-5, 1e3, 4096)
+
+
+@pytest.mark.parametrize("l", [0, 2, 4])
+def test_inverse_hankel_matches_quadrature(l):
+    sig = 2.0
+    r, xi = W.hankel(K, np.exp(-(K * sig) ** 2), l, inverse=True)
+    pts = np.exp(np.linspace(math.log(0.5), math.log(15.0), 22))
+    scale = np.max(np.abs(xi[(r > 0.1) & (r < 50)]))
+    for rr in pts:
+        i = int(np.argmin(np.abs(np.log(r / rr))))
+        val = quad(lambda k: k * k * spherical_jn(l, k * r[i]) * math.exp(-(k * sig) ** 2), 0, 14 / sig,
+                   limit=500, epsabs=1e-16, epsrel=1e-13)[0]
+        ref = (-1) ** (l // 2) * val / (2 * math.pi ** 2)
+        assert abs(xi[i] - ref) <= 1e-6 * scale, (l, r[i], xi[i], ref)
+
+
+@pytest.mark.parametrize("l", [0, 2, 4])
+def test_forward_hankel_matches_quadrature(l):
+    R = 1.0 / K[::-1]
+    g = np.exp(-R ** 2 / 16.0) * (1.0 + R * R / 10.0)
+    k, P = W.hankel(R, g, l, inverse=False)
+    scale = np.max(np.abs(P[(k > 1e-3) & (k < 3)]))
+    for kk in np.exp(np.linspace(math.log(0.01), math.log(2.0), 20)):
+        i = int(np.argmin(np.abs(np.log(k / kk))))
+        val = quad(lambda r: r * r * spherical_jn(l, k[i] * r) * math.exp(-r * r / 16.0) * (1 + r * r / 10.0),
+                   0, 60.0, limit=800, epsabs=1e-14, epsrel=1e-13)[0]
+        ref = 4 * math.pi * (-1) ** (l // 2) * val
+        assert abs(P[i] - ref) <= 1e-6 * scale, (l, k[i], P[i], ref)
+
+
+@pytest.mark.parametrize("l", [0, 2, 4])
+def test_hankel_round_trip(l):
+    P = np.exp(-(K * 2.0) ** 2) * K / (1 + K)
+    r, xi = W.hankel(K, P, l, inverse=True)
+    k2, P2 = W.hankel(r, xi, l, inverse=False)
+    sel = (k2 > 1e-2) & (k2 < 1.0)  # the template path's range
+    assert np.allclose(k2, K)
+    # the two directions use different biases, so the discrete round trip is
+    # not exact; the quadrature pins above fix each direction at 1e-6
+    assert np.max(np.abs(P2[sel] - P[sel])) <= 1e-5 * np.max(np.abs(P[sel]))
+
+
+def test_monomial_expansion_reproduces_legendre():
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((50, 3))
+    b = rng.standard_normal((50, 3))
+    a /= np.linalg.norm(a, axis=1)[:, None]
+    b /= np.linalg.norm(b, axis=1)[:, None]
+    for l in (0, 2, 4, 6, 8):
+        tot = np.zeros(50)
+        for j, c in enumerate(S.legendre(l)):
+            for al, mult in W._multinomial_monomials(j).items():
+                tot += float(c) * mult * np.prod(a ** np.array(al), axis=1) * np.prod(b ** np.array(al), axis=1)
+        assert np.allclose(tot, eval_legendre(l, np.sum(a * b, axis=1)), atol=1e-12)
+
+
+def _box_window(n_ran, sides, origin_in, observer, seed=3):
+    rng = np.random.default_rng(seed)
+    p = np.asarray(origin_in)[None, :] + rng.random((n_ran, 3)) * np.asarray(sides)[None, :]
+    vol = float(np.prod(sides))
+    nbar = 1e-3
+    ran = Catalog(p[:, 0].copy(), p[:, 1].copy(), p[:, 2].copy(), np.ones(n_ran), np.full(n_ran, nbar))
+    alpha = nbar * vol / n_ran  # randoms weighted to the galaxy density
+    return ran, alpha
+
+
+def test_box_window_multipoles_match_overlap_volume():
+    """A rectangular window W = 1 inside sides (a, a, a/2), observer far away
+    along -z (line of sight ~ z for every point): Q_l(r)/I is the shell
+    average of (2l+1) prod_i (1 - |r_i|/a_i) L_l(rhat_z), evaluated on the same
+    mesh shells.  Mesh 32^3, TSC + interlacing, compensated; r in 4-10 cells."""
+    n, box = 32, 200.0
+    sides = np.array([80.0, 80.0, 40.0])
+    origin = (0.0, 0.0, 0.0)
+    obs = (100.0, 100.0, -1.0e7)
+    ran, alpha = _box_window(400_000, sides, (20.0, 20.0, 20.0), obs)
+    nb, rmax = 16, 100.0
+    out = W.window_multipoles(ran, alpha, n, box, origin, obs, 3, 1, 1, 4, nb, rmax)
+    m = np.fft.fftfreq(n, 1.0 / n)
+    rx, ry, rz = np.meshgrid(m, m, m, indexing="ij")
+    h = box / n
+    q = (rx * rx + ry * ry + rz * rz).astype(np.int64)
+    T = out["thresholds"]
+    b = np.searchsorted(T, q, side="right") - 1
+    b[(q <= 0) | (q >= T[-1])] = -1
+    rr = np.sqrt(q.astype(float))
+    ov = np.clip(1 - np.abs(rx) * h / sides[0], 0, None) * np.clip(1 - np.abs(ry) * h / sides[1], 0, None) \
+        * np.clip(1 - np.abs(rz) * h / sides[2], 0, None)
+    mu = np.where(rr > 0, rz / np.where(rr > 0, rr, 1), 0)
+    for i, l in enumerate(out["ells"]):
+        ref = np.array([(2 * l + 1) * np.mean((ov * eval_legendre(l, mu))[b == j]) for j in range(nb)])
+        r_lo = (np.arange(nb) * rmax / nb) / h
+        sel = (r_lo >= 4) & (r_lo <= 10)
+        err = np.abs(out["Q"][i][sel] - ref[sel])
+        assert np.max(err) < 0.01, (l, err, ref[sel])
+    assert abs(out["norm_I"] - 1e-3 ** 2 * np.prod(sides)) < 1e-9 * out["norm_I"]
+    assert np.array_equal(out["counts"], np.bincount(b[b >= 0], minlength=nb))
+
+
+def test_identity_window_returns_model_multipoles():
+    """Q_0 = 1 and Q_l>0 = 0 at every separation: the template path must
+    return the model multipoles themselves (damping negligible at k <= 0.3)."""
+    pfid = 2e4 * (K / 0.02) / (1 + (K / 0.02) ** 2) ** 1.4
+    r_q = 1.0 / K[::-1]
+    Q = np.zeros((5, r_q.size))
+    Q[0] = 1.0
+    kout = np.arange(1, 31) * 0.01
+    pars = np.array([[0.03, 2.0, 0.7, 0.8, 1.0], [0.01, 1.2, 0.9, 0.65, 0.0]])
+    s8f = W.sigma8(K, pfid)
+    out = W.template_plain(K, pfid, r_q, Q, pars, kout, nbar=1e-3, sigma_gamma=0.2, sigma8_fid=s8f)
+    for p, o in zip(pars, out):
+        A, b, f, s8, sN = p
+        plin = (s8 / s8f) ** 2 * np.interp(np.log(kout), np.log(K), pfid)
+        want = [A * A * 2 / 15 * plin + sN * 2 * 0.2 ** 2 / 1e-3, -A * A * 4 / 21 * plin, A * A * 2 / 35 * plin,
+                -A * (7 * b + f) / 42 * plin, -A * f / 105 * plin]
+        for got, w in zip(o, want):
+            assert np.max(np.abs(got - w)) <= 2e-5 * np.max(np.abs(w)) + 1e-12
+
+
+def test_template_is_linear_in_its_amplitudes():
+    """P~_+ scales as A^2 sigma8^2, P~_gd as A sigma8^2 (7b+f | f): exact
+    invariants of the plain path for any window."""
+    pfid = 2e4 * (K / 0.02) / (1 + (K / 0.02) ** 2) ** 1.4
+    r_q = np.linspace(5, 3000, 300)
+    Q = np.vstack([np.exp(-r_q / 800.0) * (1 - 0.1 * i) * (0.2 if i else 1.0) for i in range(5)])
+    kout = np.arange(1, 31) * 0.01
+    base = np.array([[0.02, 1.5, 0.6, 0.7, 0.0]])
+    o1 = W.template_plain(K, pfid, r_q, Q, base, kout, 1e-3, 0.2)[0]
+    o2 = W.template_plain(K, pfid, r_q, Q, base * np.array([[2.0, 1, 1, 1, 1]]), kout, 1e-3, 0.2)[0]
+    o3 = W.template_plain(K, pfid, r_q, Q, base * np.array([[1.0, 1, 1, 1.5, 1]]), kout, 1e-3, 0.2)[0]
+    assert np.allclose(o2[:3], 4 * o1[:3], rtol=1e-12, atol=0)
+    assert np.allclose(o2[3:], 2 * o1[3:], rtol=1e-12, atol=0)
+    assert np.allclose(o3, 2.25 * o1, rtol=1e-12, atol=0)
+    # the hexadecapole of the cross term depends on f only
+    o4 = W.template_plain(K, pfid, r_q, Q, np.array([[0.02, 2.5, 0.6, 0.7, 0.0]]), kout, 1e-3, 0.2)[0]
+    assert not np.allclose(o4[3], o1[3])
