@@ -164,6 +164,27 @@ lpp_status lpp_estimate_batch(lpp_plan plan, int32_t n, const lpp_catalog* gals,
 /* Graphs captured and launched by lpp_estimate_batch over the plan's life. */
 lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 
+/* Multipoles of the window's auto-correlation (Sec. III.B, eqs. windowQ and
+ * windowQ_ell), with the line of sight of the pair taken at its first point
+ * (end point).  The window is alpha * sum_r w_r delta_D(x - x_r) (randoms
+ * weighted to the galaxy density; alpha = sum w_gal / sum w_ran of the data),
+ * deposited, interlaced and compensated as the plan's density field, and
+ * auto-correlated by FFT on the plan's periodic box, which should be at least
+ * twice the window's extent along every axis for the separations of interest.
+ * Shells of the separation r: n_rbins linear bins [b dr, (b+1) dr),
+ * dr = rmax / n_rbins, in integer form T_b <= |n|^2 < T_{b+1} for the
+ * minimum-image offset n in cells, T_b = ceil((b u)(b u)), u = dr / H in FP64;
+ * r = 0 is excluded.  Outputs (host, caller-allocated):
+ *   Q[i * n_rbins + b]  Q_l(r_b) / I for l = 2i, i = 0 .. lmax/2 (lmax even, <= 8),
+ *                       I = alpha sum_r w_r^2 nbar_r (nbar missing: alpha sum w_r / box^3),
+ *                       so that Q_0 -> 1 as r -> 0;
+ *   r_eff[b]            mean separation of the shell;  counts[b]  separations in it;
+ *   *norm_I             I.
+ * The randoms follow lpp_estimate's rules (shapes ignored).  Uses the plan's
+ * workspace (resized like lpp_estimate's); synchronises the plan's stream. */
+lpp_status lpp_window_multipoles(lpp_plan plan, const lpp_catalog* ran, double alpha, int32_t lmax, int32_t n_rbins,
+                                 double rmax, double* Q, double* r_eff, int64_t* counts, double* norm_I);
+
 /* Launch shapes of the plan's kernels (0 = the built-in default).  Every
  * choice gives the same result up to FP32/FP64 rounding order of the shell
  * sums (the transforms and the deposit are unchanged bit for bit). */

@@ -25,7 +25,8 @@ STATUS = ["LPP_OK", "LPP_E_INVALID", "LPP_E_NONFINITE", "LPP_E_OUT_OF_BOX", "LPP
 EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace", "lpp_set_stream",
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
-           "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune"]
+           "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
+           "lpp_window_multipoles"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_yz", "bin_blocks", "gather_density", "gather_shape"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
@@ -271,6 +272,25 @@ class Plan:
         path = None if cache_path is None else cache_path.encode()
         _check(self.lib.lpp_autotune(self.handle, C.byref(cg.struct), C.byref(cr.struct), path), "lpp_autotune")
         return self.tuning()
+
+    def window_multipoles(self, ran, alpha: float, lmax: int = 8, n_rbins: int = 100, rmax: float = 2000.0):
+        """Q_l(r)/I, l = 0, 2, .., lmax, of the window traced by ``ran`` (see lpp_window_multipoles)."""
+        import numpy as np
+        keep: list = []
+        cr = _Cols(ran, self._dtype(ran), keep)
+        self._prepare_device(1, cr.struct.n)
+        nell = lmax // 2 + 1
+        Q = np.zeros(nell * n_rbins)
+        r_eff = np.zeros(n_rbins)
+        counts = np.zeros(n_rbins, dtype=np.int64)
+        norm = C.c_double()
+        dp = C.POINTER(C.c_double)
+        _check(self.lib.lpp_window_multipoles(self.handle, C.byref(cr.struct), C.c_double(alpha), C.c_int32(lmax),
+                                              C.c_int32(n_rbins), C.c_double(rmax), Q.ctypes.data_as(dp),
+                                              r_eff.ctypes.data_as(dp), counts.ctypes.data_as(C.POINTER(C.c_int64)),
+                                              C.byref(norm)), "lpp_window_multipoles")
+        return dict(ells=list(range(0, lmax + 1, 2)), Q=Q.reshape(nell, n_rbins), r_eff=r_eff, counts=counts,
+                    norm_I=norm.value)
 
     def batch_stats(self) -> tuple:
         """(graphs captured, graph launches) of estimate_batch over the plan's life."""

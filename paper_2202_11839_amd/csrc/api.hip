@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -131,13 +132,6 @@ int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size(
 // (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per grid).
 constexpr int kWork = 4;
 static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
-int work_meshes(const lpp_plan_s* p, bool dn, bool sh, bool il) {
-  int n = 1;
-  if (dn) n = std::max(n, std::min<int>(kGatherMaxReal, 1 + static_cast<int>(p->tab.fields.size())));
-  if (sh) n = std::max(n, (il ? 2 : 1) * kGatherMaxComplex);
-  return n;
-}
-
 // Workspace layout (offsets in bytes), computed for capacities (ng, nr).
 struct Layout {
   size_t mesh[2];  // Bd, Bg
@@ -149,6 +143,7 @@ struct Layout {
   size_t sums_partial, sums_out;
   size_t bin_partial, acc;
   size_t fp[2];  // footprints of the density and the shape set (footprint_bytes)
+  size_t rthr, wacc, wpartial;  // window multipoles: r-shell thresholds, rows, per-block partials
   size_t total;
 };
 
@@ -163,10 +158,13 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   const size_t M = mesh_bytes(p), rs = real_size(p);
   const bool dn = need_density(p), sh = need_shape(p);
   const bool il = p->cfg.interlacing != 0;
-  L.mesh[0] = dn ? take(M) : 0;
-  L.mesh[1] = sh ? take(M) : 0;
-  const int nw = work_meshes(p, dn, sh, il);
-  for (int i = 0; i < kWork; ++i) L.work[i] = i < nw ? take(M) : 0;
+  // both bases and every work mesh, whatever the spectra: the window
+  // multipoles use them too (base, pair accumulator, one gather pass)
+  (void)dn;
+  (void)il;
+  L.mesh[0] = take(M);
+  L.mesh[1] = take(M);
+  for (int i = 0; i < kWork; ++i) L.work[i] = take(M);
   const size_t nd = static_cast<size_t>(ng + nr);
   const size_t gg = static_cast<size_t>(ng);
   L.key_d = take(4 * nd);
@@ -194,6 +192,9 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * std::max(bin_blocks(p->cfg.mesh_n), kMaxBinBlocks));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
   for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
+  L.rthr = take(8 * (kMaxShells + 1));
+  L.wacc = take(8 * static_cast<size_t>(kWinMaxRows) * kMaxShells);
+  L.wpartial = take(8 * static_cast<size_t>(kWinMaxRows) * kMaxShells * window_bin_blocks(p->cfg.mesh_n));
   L.total = off;
   return L;
 }
@@ -723,6 +724,130 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   return LPP_OK;
 }
 
+// Window multipoles Q_l(r) / I of a random catalog (Sec. III.B, eq.
+// windowQ_ell, end-point line of sight): see kernels_window.hip.
+template <typename T>
+lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int lmax, int nbr, double rmax, double* Q,
+                      double* r_eff, int64_t* counts, double* norm_I) {
+  lpp_status s;
+  const lpp_config& cfg = p->cfg;
+  if ((s = check_catalog_args(ran, false)) != LPP_OK) return s;
+  if (!(alpha > 0.0) || !std::isfinite(alpha) || lmax < 0 || lmax > 8 || lmax % 2 || nbr < 1 || nbr > kMaxShells ||
+      !(rmax > 0.0) || !std::isfinite(rmax) || !Q || !r_eff || !counts || !norm_I)
+    return LPP_E_INVALID;
+  if ((s = ensure_tables(p)) != LPP_OK) return s;
+  if ((s = ensure_workspace(p, std::max<int64_t>(p->cap_gal, 1), std::max(p->cap_ran, ran->n))) != LPP_OK) return s;
+  const Layout L = layout(p, p->cap_gal, p->cap_ran);
+  const hipStream_t st = p->stream;
+  const int N = cfg.mesh_n;
+  RawCat rr;
+  lpp_catalog rcat = *ran;
+  rcat.g1 = rcat.g2 = nullptr;
+  if ((s = stage(p, &rcat, L.stage_ran, 5, rr)) != LPP_OK) return s;
+  double sums[16];
+  const double vol = cfg.box_size * cfg.box_size * cfg.box_size;
+  if ((s = catalog_sums(p, L, rr, nullptr, 0.0, sums)) != LPP_OK) return s;
+  if ((s = sums_status(sums)) != LPP_OK) return s;
+  if (!ran->nbar && (s = catalog_sums(p, L, rr, nullptr, alpha * sums[0] / vol, sums)) != LPP_OK) return s;
+  const double I = alpha * sums[2];
+  if (!(I > 0.0) || !std::isfinite(I)) return LPP_E_NO_RANDOMS;
+
+  GObjSet<T> setd = objset<T>(p, L, false, rr.n);
+  const uint32_t* starts = reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d));
+  const Footprint fp = footprint_at(p, L.fp[0]);
+  {
+    const double ws[1] = {alpha};
+    const double* wd[1] = {nullptr};
+    if ((s = sort_set<T>(p, L, &rr, ws, wd, 1, false, setd, st)) != LPP_OK) return s;
+  }
+  LPP_TRY(launch_footprint(starts, N, fp, st));
+  // r-shell thresholds, FP64 in this order: T_b = ceil((b u)(b u)), u = (rmax / nbr) / H
+  std::vector<int64_t> thr(static_cast<size_t>(nbr) + 1);
+  const double u = (rmax / nbr) / (cfg.box_size / N);
+  for (int b = 0; b <= nbr; ++b) thr[b] = static_cast<int64_t>(std::ceil((b * u) * (b * u)));
+  int64_t* d_thr = reinterpret_cast<int64_t*>(wsp(p, L.rthr));
+  LPP_TRY(hipMemcpyAsync(d_thr, thr.data(), 8 * thr.size(), hipMemcpyHostToDevice, st));
+  const int nell = lmax / 2 + 1, nrow = nell + 2;
+  WinArgs wa{};
+  wa.N = N;
+  wa.nb = nbr;
+  wa.interlace = cfg.interlacing;
+  wa.n_rows = nrow;
+  wa.thr = d_thr;
+  wa.phase = p->d_phase;
+  wa.invw = p->d_invw;
+  double* wacc = reinterpret_cast<double*>(wsp(p, L.wacc));
+  double* part = reinterpret_cast<double*>(wsp(p, L.wpartial));
+  LPP_TRY(launch_fill_zero(wacc, 8 * static_cast<size_t>(nrow) * nbr, st));
+  void* B0 = wsp(p, L.mesh[0]);
+  void* Zc = wsp(p, L.mesh[1]);
+  void* W[kWork];
+  for (int i = 0; i < kWork; ++i) W[i] = wsp(p, L.work[i]);
+  // the fields: kappa_a h_a(xhat) for every real harmonic of degree l = 0, 2, ..., lmax
+  struct WField {
+    FieldSpec spec;
+    int row;
+  };
+  std::vector<WField> fields;
+  for (int l = 0; l <= lmax; l += 2)
+    for (int M = 0; M <= l; ++M)
+      for (int cs = 0; cs < (M ? 2 : 1); ++cs) fields.push_back(WField{make_spec(0, l, M, cs), l / 2});
+  const FftPrune in_fp{fp.row, fp.plane, fp.cube, INT_MAX};
+  const FftPrune full{nullptr, nullptr, nullptr, INT_MAX};
+  auto fft = [&](void* m, const FftPrune& pr) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int axis = 0; axis < 3 && e == hipSuccess; ++axis)
+      e = launch_fft_axis<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz);
+    return e;
+  };
+  const int per = p->tune.gather_density > 0 ? p->tune.gather_density : kGatherMaxReal;
+  int pending = -1;  // field waiting in slot 0 of Zc
+  bool counted = false;
+  auto bin_pair = [&](int fa, int fb) -> hipError_t {
+    hipError_t e = fft(Zc, full);
+    if (e == hipSuccess)
+      e = launch_window_bin<T>(wa, Zc, &fields[fa].spec, fb >= 0 ? &fields[fb].spec : nullptr, fields[fa].row,
+                               fb >= 0 ? fields[fb].row : -1, counted ? 0 : 1, part, st);
+    if (e == hipSuccess) e = launch_reduce_partials(part, window_bin_blocks(N), nrow * nbr, wacc, st);
+    counted = true;
+    return e;
+  };
+  for (size_t j0 = 0; j0 < fields.size(); j0 += per) {
+    const int nf = static_cast<int>(std::min<size_t>(per, fields.size() - j0));
+    FieldSpec specs[kWork];
+    for (int q = 0; q < nf; ++q) specs[q] = fields[j0 + q].spec;
+    LPP_TRY(launch_gather<T>(setd, starts, p->geo, specs, nf, 0, W, fp.cube, st));
+    for (int q = 0; q < nf; ++q) LPP_TRY(fft(W[q], in_fp));
+    for (int q = 0; q < nf; ++q) {
+      const int gi = static_cast<int>(j0) + q;
+      if (gi == 0) LPP_TRY(launch_window_product<T>(wa, W[q], B0, nullptr, -1, st));
+      if (pending < 0) {
+        LPP_TRY(launch_window_product<T>(wa, W[q], B0, Zc, 0, st));
+        pending = gi;
+      } else {
+        LPP_TRY(launch_window_product<T>(wa, W[q], B0, Zc, 1, st));
+        LPP_TRY(bin_pair(pending, gi));
+        pending = -1;
+      }
+    }
+  }
+  if (pending >= 0) LPP_TRY(bin_pair(pending, -1));
+  std::vector<double> h(static_cast<size_t>(nrow) * nbr);
+  LPP_TRY(hipMemcpyAsync(h.data(), wacc, 8 * h.size(), hipMemcpyDeviceToHost, st));
+  LPP_TRY(hipStreamSynchronize(st));
+  const double H = cfg.box_size / N, n3 = static_cast<double>(N) * N * N;
+  for (int b = 0; b < nbr; ++b) {
+    const double c = h[static_cast<size_t>(nell) * nbr + b];
+    counts[b] = static_cast<int64_t>(std::llround(c));
+    r_eff[b] = c > 0 ? h[static_cast<size_t>(nell + 1) * nbr + b] * H / c : 0.0;
+    for (int i = 0; i < nell; ++i)
+      Q[static_cast<size_t>(i) * nbr + b] =
+          c > 0 ? (4 * i + 1) * h[static_cast<size_t>(i) * nbr + b] / (n3 * c * H * H * H * I) : 0.0;
+  }
+  *norm_I = I;
+  return LPP_OK;
+}
+
 void drop_graph(lpp_plan_s* p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -1186,6 +1311,18 @@ lpp_status lpp_autotune(lpp_plan p, const lpp_catalog* gal, const lpp_catalog* r
     if (s != LPP_OK) return s;
     if (cache_path && !store_tuning_cache(p, cache_path)) return LPP_E_INVALID;
     return LPP_OK;
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
+}
+
+lpp_status lpp_window_multipoles(lpp_plan p, const lpp_catalog* ran, double alpha, int32_t lmax, int32_t n_rbins,
+                                 double rmax, double* Q, double* r_eff, int64_t* counts, double* norm_I) {
+  if (!p) return LPP_E_INVALID;
+  try {
+    return p->cfg.precision == LPP_F64
+               ? run_window<double>(p, ran, alpha, lmax, n_rbins, rmax, Q, r_eff, counts, norm_I)
+               : run_window<float>(p, ran, alpha, lmax, n_rbins, rmax, Q, r_eff, counts, norm_I);
   } catch (...) {
     return LPP_E_NOMEM;
   }

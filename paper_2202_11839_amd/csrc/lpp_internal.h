@@ -209,6 +209,24 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, c
 template <typename T>
 hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
                          hipStream_t st);
+// Window multipoles (kernels_window.hip).  Shells of the separation r in
+// cells: T_b <= |n|^2 < T_{b+1} (thr on the device).
+struct WinArgs {
+  int N, nb, interlace, n_rows;  // n_rows = multipoles + 2 (counts, |n| sums)
+  const int64_t* thr;
+  const void* phase;
+  const void* invw;
+};
+constexpr int kWinMaxRows = 7;
+int window_bin_blocks(int N);
+// slot < 0: B0 = F_0 from the packed copies; 0: Zc = F_a conj(B0); 1: Zc -= i F_b conj(B0) conj'd (see source)
+template <typename T>
+hipError_t launch_window_product(const WinArgs& a, const void* packed, void* B0, void* Zc, int slot, hipStream_t st);
+// per-block partial rows [n_rows * nb][window_bin_blocks(N)] of the shell sums of D = DFT[conj Z]
+template <typename T>
+hipError_t launch_window_bin(const WinArgs& a, const void* D, const FieldSpec* fa, const FieldSpec* fb, int row_a,
+                             int row_b, int with_counts, double* partial, hipStream_t st);
+
 // acc[0..width) += sum over blocks of partial, laid out [width][nblocks] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st);
 

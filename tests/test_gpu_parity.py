@@ -372,3 +372,44 @@ def test_autotune_writes_cache_and_keeps_parity(lpp, tmp_path):
     for k, v in chosen.items():
         assert f'"{k}": {v}' in line[0]
     _compare(plan.estimate(g, r), ref, 1e-4)
+
+
+_WINDOW_REF = {}
+
+
+def _window_case(name):
+    """Randoms of a survey wedge seen from a near observer (wide angles) in a
+    box twice the wedge's extent; the oracle's Q_l at l <= lmax."""
+    from oracle import window as OW
+    from synth import wedge_uniform
+    if name not in _WINDOW_REF:
+        if name == "wedge_l8":
+            n, box, origin, p, il, lmax, nb, rmax, nr = 32, 600.0, (-80.0, -80.0, -80.0), 3, 1, 8, 12, 240.0, 40000
+            pts = lambda k, rng: wedge_uniform(k, rng, (5.0, 80.0), (5.0, 60.0), (60.0, 200.0))
+        else:
+            n, box, origin, p, il, lmax, nb, rmax, nr = 32, 500.0, (100.0, -50.0, 20.0), 2, 0, 4, 10, 200.0, 30000
+            pts = lambda k, rng: box_uniform(k, rng, (180.0, 40.0, 90.0), 160.0)
+        rng = np.random.default_rng(77)
+        rp = pts(nr, rng)
+        ran = Catalog(rp[:, 0].copy(), rp[:, 1].copy(), rp[:, 2].copy(), rng.random(nr) + 0.5, np.full(nr, 3e-4))
+        alpha = 0.05
+        ref = OW.window_multipoles(ran, alpha, n, box, origin, (0.0, 0.0, 0.0), p, il, 1, lmax, nb, rmax)
+        _WINDOW_REF[name] = (ran, alpha, dict(mesh_n=n, box_size=box, box_origin=origin, assignment=p,
+                                              interlacing=il, lmax=4, n_kbins=8), (lmax, nb, rmax), ref)
+    return _WINDOW_REF[name]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["wedge_l8", "box_l4"])
+def test_window_multipoles_match_oracle(lpp, name, prec):
+    ran, alpha, kw, (lmax, nb, rmax), ref = _window_case(name)
+    plan = lpp.Plan(precision=prec, **kw)
+    got = plan.window_multipoles(ran, alpha, lmax=lmax, n_rbins=nb, rmax=rmax)
+    assert list(got["counts"]) == list(ref["counts"])
+    assert abs(got["norm_I"] - ref["norm_I"]) <= 1e-12 * ref["norm_I"]
+    sel = ref["counts"] > 0
+    np.testing.assert_allclose(got["r_eff"][sel], ref["r_eff"][sel], rtol=1e-12)
+    scale = np.max(np.abs(ref["Q"][0][sel]))
+    tol = 1e-9 if prec == "f64" else 1e-4
+    err = np.max(np.abs(got["Q"][:, sel] - ref["Q"][:, sel])) / scale
+    assert err <= tol, (name, prec, err)
