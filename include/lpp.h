@@ -185,6 +185,40 @@ lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 lpp_status lpp_window_multipoles(lpp_plan plan, const lpp_catalog* ran, double alpha, int32_t lmax, int32_t n_rbins,
                                  double rmax, double* Q, double* r_eff, int64_t* counts, double* norm_I);
 
+/* Coefficient of Q_{l''} in the window mixing Q^X_{l l'}(r) of eq.
+ * def_of_Q_llp (Sec. III.B): (2l+1) sqrt((l-m)!/(l+m)! (l'+m)!/(l'-m)!)
+ * (l'' l l'; 0 0 0)(l'' l l'; 0 m -m), m = mX (0 for delta-delta and plus, 2
+ * for the cross, 4 for minus); zero when l < m or l' < m.  Host only. */
+lpp_status lpp_window_coefficient(int32_t mX, int32_t l, int32_t lp, int32_t lpp, double* out);
+
+/* The plain window-convolved template path (Sec. III.B, eq.
+ * window_convolution_X_hankel) of the linear tidal-alignment model, one
+ * FFTLog (Hamilton 2000) per Hankel transform, FP64, on the current device.
+ * Per parameter point (A, b, f, sigma8, s_N) (params[5 p + 0..4]):
+ *   P_lin = (sigma8 / sigma8_fid)^2 P_fid exp(-(k/10)^2), sigma8_fid the
+ *   top-hat R = 8 rms of pfid (trapezoid in ln k on the grid);
+ *   model multipoles P_+^(0,2,4) = A^2 {2/15, -4/21, 2/35} P_lin,
+ *   P_gd^(2,4) = -A {(7b+f)/42, f/105} P_lin;
+ *   xi^(l') = H^{-1}_{l'}[P^(l')] (FFTLog bias 1.5), multiplied by
+ *   Q^X_{l l'}(r) = sum_{l''} lpp_window_coefficient(mX, l, l', l'') Q_{l''}(r),
+ *   P~^(l) = H_l[sum_{l'} Q^X_{l l'} xi^(l')] (bias 1.0 at l = 0, 0.5 above),
+ *   interpolated linearly in ln k to k_out; P~_+^(0) += s_N 2 sigma_gamma^2 / nbar.
+ * pfid: P_fid at k_n = exp(ln k_min + n d), d = ln(k_max/k_min)/(n_log - 1)
+ *   (n_log = 4096; the FFTLog grids are this k grid and r_j = 1/k_{n_log-1-j});
+ * Q[i * n_q + j]: Q_{2i}(r_q[j]) / I, i = 0..4 (lpp_window_multipoles),
+ *   r_q increasing and > 0; linear in r, with Q(0) = (1, 0, 0, 0, 0) and zero
+ *   beyond r_q[n_q-1];
+ * out[(p * 5 + o) * n_k + i]: o = 0, 1, 2 for P~_+^(0,2,4), o = 3, 4 for P~_gd^(2,4)
+ *   at k_out[i] (k_min <= k_out <= k_max, n_k <= 256).
+ * device_io = 0: params and out are host arrays; 1: device arrays (the
+ * tables stay host arrays).  stream: a hipStream_t (NULL = default).  The
+ * call allocates its own device scratch (about 330 MB) and synchronises the
+ * stream before returning.  LPP_E_UNSUPPORTED for another n_log. */
+lpp_status lpp_template_plain(const double* pfid, double k_min, double k_max, int32_t n_log, const double* r_q,
+                              const double* Q, int32_t n_q, const double* params, int64_t n_pts,
+                              const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
+                              int32_t device_io, void* stream);
+
 /* Launch shapes of the plan's kernels (0 = the built-in default).  Every
  * choice gives the same result up to FP32/FP64 rounding order of the shell
  * sums (the transforms and the deposit are unchanged bit for bit). */

@@ -26,7 +26,7 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
-           "lpp_window_multipoles"]
+           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_yz", "bin_blocks", "gather_density", "gather_shape"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
@@ -330,6 +330,50 @@ class Plan:
             import torch
             return LPP_F64 if x.dtype == torch.float64 else LPP_F32
         return LPP_F64 if np.asarray(x).dtype == np.float64 else LPP_F32
+
+
+def window_coefficient(mX: int, l: int, lp: int, lpp: int) -> float:
+    """Coefficient of Q_{l''} in Q^X_{l l'} (host computation of the library)."""
+    out = C.c_double()
+    _check(load().lpp_window_coefficient(C.c_int32(mX), C.c_int32(l), C.c_int32(lp), C.c_int32(lpp), C.byref(out)),
+           "lpp_window_coefficient")
+    return out.value
+
+
+def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float, sigma_gamma: float,
+                   out=None):
+    """The plain window-convolved template path on the GPU (lpp_template_plain).
+
+    ``params`` (n_pts, 5) and ``out`` (n_pts, 5, n_k) may be numpy arrays
+    (host) or float64 CUDA tensors (device, then ``out`` must be given); the
+    tables ``pfid`` (4096), ``r_q``, ``Q`` (5, n_q) and ``k_out`` are host arrays."""
+    import numpy as np
+    lib = load()
+    dp = C.POINTER(C.c_double)
+    pf = np.ascontiguousarray(pfid, dtype=np.float64)
+    rq = np.ascontiguousarray(r_q, dtype=np.float64)
+    qq = np.ascontiguousarray(Q, dtype=np.float64)
+    ko = np.ascontiguousarray(k_out, dtype=np.float64)
+    on_dev = hasattr(params, "is_cuda") and params.is_cuda
+    if on_dev:
+        import torch
+        assert params.dtype == torch.float64 and params.is_contiguous() and out is not None
+        n_pts = params.shape[0]
+        p_ptr = C.cast(C.c_void_p(params.data_ptr()), dp)
+        o_ptr = C.cast(C.c_void_p(out.data_ptr()), dp)
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    else:
+        pr = np.ascontiguousarray(params, dtype=np.float64)
+        n_pts = pr.shape[0]
+        if out is None:
+            out = np.zeros((n_pts, 5, ko.size))
+        p_ptr, o_ptr, stream = pr.ctypes.data_as(dp), out.ctypes.data_as(dp), C.c_void_p(0)
+    _check(lib.lpp_template_plain(pf.ctypes.data_as(dp), C.c_double(k_min), C.c_double(k_max), C.c_int32(pf.size),
+                                  rq.ctypes.data_as(dp), qq.ctypes.data_as(dp), C.c_int32(rq.size), p_ptr,
+                                  C.c_int64(n_pts), ko.ctypes.data_as(dp), C.c_int32(ko.size), C.c_double(nbar),
+                                  C.c_double(sigma_gamma), o_ptr, C.c_int32(1 if on_dev else 0), stream),
+           "lpp_template_plain")
+    return out
 
 
 def version() -> str:

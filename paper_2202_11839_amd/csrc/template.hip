@@ -1,0 +1,364 @@
+// The plain window-convolved template path (Sec. III.B, eq.
+// window_convolution_X_hankel): for every parameter point the model
+// multipoles are taken to configuration space by H^{-1}, multiplied by the
+// window mixing Q^X_{l l'}(r) (eq. def_of_Q_llp) and taken back by H_l, each
+// transform an FFTLog (Hamilton 2000) of length n_log in FP64 on the device,
+// one workgroup per transform.
+//
+// FFTLog: with x_n = x_0 e^{n d} and u_n = f(x_n) x_n^{3-q}, c = DFT[u],
+// G(y_j) = int f(x) j_l(x y_j) x^2 dx = y_j^{-q} DFT[c_m C_m](j), y_j = 1 / x_{N-1-j},
+// C_m = M_l(q + i w_m) (x_0 y_0)^{-i w_m} / N, w_m = 2 pi m' / (N d) (m' the
+// signed frequency), M_l(s) = int t^{s-1} j_l(t) dt = sqrt(pi) 2^{s-2}
+// Gamma((l+s)/2) / Gamma((3+l-s)/2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "device_common.h"
+
+namespace lpp {
+
+namespace {
+
+using cd = std::complex<double>;
+using dev::V2;
+
+constexpr int kLog = 4096;          // FFTLog length
+constexpr int kLogThreads = kLog / 8;
+constexpr int kOut = 5;             // P+_0, P+_2, P+_4, Pgd_2, Pgd_4
+constexpr int kMaxKOut = 256;
+constexpr int kChunk = 2048;        // parameter points per pass (bounds the xi scratch)
+
+// ---- host: special functions ----
+
+// log Gamma(z), Re z > 0: recurrence up to Re z >= 12, then Stirling's series
+cd lgamma_c(cd z) {
+  cd shift = 0.0;
+  while (z.real() < 12.0) {
+    shift += std::log(z);
+    z += 1.0;
+  }
+  static const double B[] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66, -691.0 / 2730, 7.0 / 6};
+  cd s = (z - 0.5) * std::log(z) - z + 0.5 * std::log(2.0 * M_PI);
+  cd zp = z;
+  const cd z2 = z * z;
+  for (int k = 1; k <= 7; ++k) {
+    s += B[k - 1] / (2.0 * k * (2.0 * k - 1.0) * zp);
+    zp *= z2;
+  }
+  return s - shift;
+}
+
+cd mellin_jl(int l, cd s) {
+  return std::exp(0.5 * std::log(M_PI) + (s - 2.0) * std::log(2.0) + lgamma_c(0.5 * (l + s.real()) + cd(0, 0.5 * s.imag())) -
+                  lgamma_c(cd(0.5 * (3.0 + l - s.real()), -0.5 * s.imag())));
+}
+
+long double fact(int n) {
+  long double r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+// Wigner 3j symbol (Racah's sum), integer arguments
+double wigner3j(int j1, int j2, int j3, int m1, int m2, int m3) {
+  if (m1 + m2 + m3 != 0 || j3 < std::abs(j1 - j2) || j3 > j1 + j2 || std::abs(m1) > j1 || std::abs(m2) > j2 ||
+      std::abs(m3) > j3)
+    return 0.0;
+  const long double tri = fact(j1 + j2 - j3) * fact(j1 - j2 + j3) * fact(-j1 + j2 + j3) / fact(j1 + j2 + j3 + 1);
+  const long double pre = std::sqrt(tri * fact(j1 + m1) * fact(j1 - m1) * fact(j2 + m2) * fact(j2 - m2) *
+                                    fact(j3 + m3) * fact(j3 - m3));
+  long double sum = 0;
+  for (int k = 0; k <= j1 + j2 + j3; ++k) {
+    const int a[6] = {k, j3 - j2 + k + m1, j3 - j1 + k - m2, j1 + j2 - j3 - k, j1 - k - m1, j2 - k + m2};
+    bool ok = true;
+    for (int v : a) ok = ok && v >= 0;
+    if (!ok) continue;
+    long double den = 1;
+    for (int v : a) den *= fact(v);
+    sum += ((k % 2) ? -1.0L : 1.0L) / den;
+  }
+  const int sgn = ((j1 - j2 - m3) % 2 + 2) % 2 ? -1 : 1;
+  return static_cast<double>(sgn * pre * sum);
+}
+
+// ---- device: one FFTLog per workgroup ----
+
+struct LogTables {
+  const double2* tw;     // exp(-2 pi i m / N)
+  const double2* cinv;   // [3][N] C_m of H^{-1}_l, l = 0, 2, 4 (bias q_inv)
+  const double2* cfwd;   // [3][N] C_m of H_l (bias q_fwd(l))
+  const double* pd;      // P_fid(k) exp(-(k/10)^2)
+  const double* kpow;    // k^{3 - q_inv}
+  const double* rpow;    // r^{-q_inv}
+  const double* rpowf;   // [3][N] r^{3 - q_fwd(l)}
+  const double* kpowf;   // [3][N] k^{-q_fwd(l)}
+  const double* qc;      // [13][N] Q^X_{l l'}(r): plus (l, l') 3x3, then gd (L, L') 2x2
+};
+
+// v: this thread's 8 inputs (element t + j N/8).  Returns with v[q] the
+// output at row fft_rows(t)[q].
+__device__ __forceinline__ void log_fft(double2* sm, const double2* tw, int t, double2* v) {
+  dev::fft_column_regs<double, kLog>(tw, sm, 0, t, v);
+}
+
+// second half of an FFTLog: c (from log_fft, at rows) times C, then the DFT,
+// with the output written to sm[j] (real part times the caller's scale later)
+__device__ __forceinline__ void log_second(double2* sm, const double2* tw, const double2* C, int t, double2* v) {
+  int row[8];
+  dev::fft_rows<kLog>(t, row);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sm[row[q]] = dev::cmul(v[q], C[row[q]]);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = sm[t + j * kLogThreads];
+  __syncthreads();
+  dev::fft_column_regs<double, kLog>(tw, sm, 0, t, v);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sm[row[q]] = v[q];
+  __syncthreads();
+}
+
+struct PointScale {
+  double plus[3];  // A^2 s^2 {2/15, -4/21, 2/35}
+  double gd[2];    // A s^2 {-(7b+f)/42, -f/105}
+};
+
+__device__ __forceinline__ PointScale point_scale(const double* p, double s8f) {
+  const double A = p[0], b = p[1], f = p[2], s = p[3] / s8f;
+  const double s2 = s * s;
+  PointScale r;
+  r.plus[0] = A * A * s2 * (2.0 / 15.0);
+  r.plus[1] = A * A * s2 * (-4.0 / 21.0);
+  r.plus[2] = A * A * s2 * (2.0 / 35.0);
+  r.gd[0] = A * s2 * (-(7.0 * b + f) / 42.0);
+  r.gd[1] = A * s2 * (-f / 105.0);
+  return r;
+}
+
+// xi[p][t][j], t = 0..2: xi_+^(0,2,4); t = 3, 4: xi_gd^(2,4)
+__global__ void __launch_bounds__(kLogThreads) fftlog_inverse_kernel(LogTables tb, const double* __restrict__ params,
+                                                                     double s8f, double* __restrict__ xi) {
+  __shared__ double2 sm[kLog];
+  const int p = blockIdx.x / kOut, tr = blockIdx.x % kOut, t = threadIdx.x;
+  const PointScale ps = point_scale(params + 5 * static_cast<int64_t>(p), s8f);
+  const int l = tr < 3 ? 2 * tr : 2 * (tr - 2);  // 0, 2, 4, 2, 4
+  const double amp = tr < 3 ? ps.plus[tr] : ps.gd[tr - 3];
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int n = t + j * kLogThreads;
+    v[j] = double2{amp * tb.pd[n] * tb.kpow[n], 0.0};
+  }
+  log_fft(sm, tb.tw, t, v);
+  log_second(sm, tb.tw, tb.cinv + (l / 2) * kLog, t, v);
+  const double sign = (l / 2) % 2 ? -1.0 : 1.0;
+  double* out = xi + (static_cast<int64_t>(p) * kOut + tr) * kLog;
+  for (int j = t; j < kLog; j += kLogThreads) out[j] = sign * sm[j].x * tb.rpow[j] / (2.0 * M_PI * M_PI);
+}
+
+// out[p][o][i]: o = 0..2 P~_+^(0,2,4), o = 3, 4 P~_gd^(2,4) at kout (linear in ln k)
+__global__ void __launch_bounds__(kLogThreads) fftlog_forward_kernel(LogTables tb, const double* __restrict__ xi,
+                                                                     const double* __restrict__ params, double lnk0,
+                                                                     double dlnk, const double* __restrict__ lnkout,
+                                                                     int nk, double shot, double* __restrict__ out) {
+  __shared__ double2 sm[kLog];
+  const int p = blockIdx.x / kOut, o = blockIdx.x % kOut, t = threadIdx.x;
+  const int l = o < 3 ? 2 * o : 2 * (o - 2);
+  const double* xp = xi + static_cast<int64_t>(p) * kOut * kLog;
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int n = t + j * kLogThreads;
+    double g = 0.0;
+    if (o < 3) {
+      for (int lp = 0; lp < 3; ++lp) g += tb.qc[(o * 3 + lp) * kLog + n] * xp[lp * kLog + n];
+    } else {
+      for (int Lp = 0; Lp < 2; ++Lp) g += tb.qc[(9 + (o - 3) * 2 + Lp) * kLog + n] * xp[(3 + Lp) * kLog + n];
+    }
+    v[j] = double2{g * tb.rpowf[(l / 2) * kLog + n], 0.0};
+  }
+  log_fft(sm, tb.tw, t, v);
+  log_second(sm, tb.tw, tb.cfwd + (l / 2) * kLog, t, v);
+  const double sign = (l / 2) % 2 ? -1.0 : 1.0;
+  for (int j = t; j < kLog; j += kLogThreads) sm[j].y = sign * 4.0 * M_PI * sm[j].x * tb.kpowf[(l / 2) * kLog + j];
+  __syncthreads();
+  for (int i = t; i < nk; i += kLogThreads) {
+    const double u = (lnkout[i] - lnk0) / dlnk;
+    int j0 = static_cast<int>(floor(u));
+    j0 = j0 < 0 ? 0 : (j0 > kLog - 2 ? kLog - 2 : j0);
+    const double w = u - j0;
+    double v2 = (1.0 - w) * sm[j0].y + w * sm[j0 + 1].y;
+    if (o == 0) v2 += shot * params[5 * static_cast<int64_t>(p) + 4];
+    out[(static_cast<int64_t>(p) * kOut + o) * nk + i] = v2;
+  }
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) { return hipMalloc(&p, n * sizeof(T)); }
+};
+
+}  // namespace
+
+double window_coefficient(int mX, int l, int lp, int lpp) {
+  if (l < mX || lp < mX) return 0.0;
+  const double f = std::sqrt(static_cast<double>(fact(l - mX) / fact(l + mX) * (fact(lp + mX) / fact(lp - mX))));
+  return (2 * l + 1) * f * wigner3j(lpp, l, lp, 0, 0, 0) * wigner3j(lpp, l, lp, 0, mX, -mX);
+}
+
+}  // namespace lpp
+
+using namespace lpp;
+
+extern "C" {
+
+lpp_status lpp_window_coefficient(int32_t mX, int32_t l, int32_t lp, int32_t lpp, double* out) {
+  if (!out || mX < 0 || l < 0 || lp < 0 || lpp < 0 || l > 16 || lp > 16 || lpp > 16) return LPP_E_INVALID;
+  *out = window_coefficient(mX, l, lp, lpp);
+  return LPP_OK;
+}
+
+lpp_status lpp_template_plain(const double* pfid, double k_min, double k_max, int32_t n_log, const double* r_q,
+                              const double* Q, int32_t n_q, const double* params, int64_t n_pts,
+                              const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
+                              int32_t device_io, void* stream) {
+  if (!pfid || !r_q || !Q || !params || !k_out || !out || n_q < 1 || n_pts < 0 || n_k < 1 || n_k > kMaxKOut)
+    return LPP_E_INVALID;
+  if (n_log != kLog) return LPP_E_UNSUPPORTED;
+  if (!(k_min > 0.0) || !(k_max > k_min) || !(nbar > 0.0) || !std::isfinite(sigma_gamma)) return LPP_E_INVALID;
+  for (int i = 1; i < n_q; ++i)
+    if (!(r_q[i] > r_q[i - 1])) return LPP_E_INVALID;
+  if (!(r_q[0] > 0.0)) return LPP_E_INVALID;
+  const double lnk0 = std::log(k_min), d = (std::log(k_max) - lnk0) / (kLog - 1);
+  for (int i = 0; i < n_k; ++i)
+    if (!(k_out[i] >= k_min) || !(k_out[i] <= k_max)) return LPP_E_INVALID;
+  if (n_pts == 0) return LPP_OK;
+  try {
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int N = kLog;
+    std::vector<double> k(N), r(N);
+    for (int n = 0; n < N; ++n) k[n] = std::exp(lnk0 + n * d);
+    for (int j = 0; j < N; ++j) r[j] = 1.0 / k[N - 1 - j];
+    // sigma8 of P_fid: trapezoid in ln k of k^3 P W_TH(8k)^2 / (2 pi^2)
+    double s8 = 0.0;
+    auto integrand = [&](int n) {
+      const double x = 8.0 * k[n];
+      const double w = 3.0 * (std::sin(x) - x * std::cos(x)) / (x * x * x);
+      return k[n] * k[n] * k[n] * pfid[n] * w * w / (2.0 * M_PI * M_PI);
+    };
+    for (int n = 0; n + 1 < N; ++n) s8 += 0.5 * (integrand(n) + integrand(n + 1)) * (std::log(k[n + 1]) - std::log(k[n]));
+    const double s8f = std::sqrt(s8);
+    // host tables
+    const double qinv = 1.5;
+    auto qfwd = [](int l) { return l == 0 ? 1.0 : 0.5; };
+    std::vector<double2> tw(N), cinv(3 * N), cfwd(3 * N);
+    for (int m = 0; m < N; ++m) {
+      const double a = -2.0 * M_PI * m / N;
+      tw[m] = double2{std::cos(a), std::sin(a)};
+    }
+    const double x0y0 = k[0] / k[N - 1];  // (k_0 r_0) = (r_0 k_0) = k_0 / k_{N-1}
+    for (int li = 0; li < 3; ++li) {
+      const int l = 2 * li;
+      for (int m = 0; m < N; ++m) {
+        const int ms = m < N / 2 ? m : m - N;
+        const double w = 2.0 * M_PI * ms / (N * d);
+        const cd ph = std::exp(cd(0, -w * std::log(x0y0))) / static_cast<double>(N);
+        const cd ci = mellin_jl(l, cd(qinv, w)) * ph, cf = mellin_jl(l, cd(qfwd(l), w)) * ph;
+        cinv[li * N + m] = double2{ci.real(), ci.imag()};
+        cfwd[li * N + m] = double2{cf.real(), cf.imag()};
+      }
+    }
+    std::vector<double> pd(N), kpow(N), rpow(N), rpowf(3 * N), kpowf(3 * N);
+    for (int n = 0; n < N; ++n) {
+      pd[n] = pfid[n] * std::exp(-(k[n] / 10.0) * (k[n] / 10.0));
+      kpow[n] = std::pow(k[n], 3.0 - qinv);
+      rpow[n] = std::pow(r[n], -qinv);
+      for (int li = 0; li < 3; ++li) {
+        rpowf[li * N + n] = std::pow(r[n], 3.0 - qfwd(2 * li));
+        kpowf[li * N + n] = std::pow(k[n], -qfwd(2 * li));
+      }
+    }
+    // Q_l on the r grid: linear in r, Q(0) = (1, 0, ...), zero beyond the table
+    std::vector<double> qg(5 * static_cast<size_t>(N), 0.0);
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < N; ++j) {
+        const double x = r[j];
+        double v = 0.0;
+        if (x <= r_q[n_q - 1]) {
+          if (x < r_q[0]) {
+            const double y0 = i == 0 ? 1.0 : 0.0;
+            v = y0 + (Q[i * n_q] - y0) * (x / r_q[0]);
+          } else {
+            const int hi = static_cast<int>(std::upper_bound(r_q, r_q + n_q, x) - r_q);
+            const int lo = std::max(0, hi - 1);
+            const int h2 = std::min(hi, n_q - 1);
+            const double t = h2 > lo ? (x - r_q[lo]) / (r_q[h2] - r_q[lo]) : 0.0;
+            v = Q[i * n_q + lo] + t * (Q[i * n_q + h2] - Q[i * n_q + lo]);
+          }
+        }
+        qg[static_cast<size_t>(i) * N + j] = v;
+      }
+    std::vector<double> qc(13 * static_cast<size_t>(N), 0.0);
+    int slot = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int mX = pass ? 2 : 0;
+      const int nl = pass ? 2 : 3, l0 = pass ? 2 : 0;
+      for (int a = 0; a < nl; ++a)
+        for (int b = 0; b < nl; ++b, ++slot) {
+          const int l = l0 + 2 * a, lp = l0 + 2 * b;
+          for (int i = 0; i < 5; ++i) {
+            const double c = window_coefficient(mX, l, lp, 2 * i);
+            if (c == 0.0) continue;
+            for (int j = 0; j < N; ++j) qc[static_cast<size_t>(slot) * N + j] += c * qg[static_cast<size_t>(i) * N + j];
+          }
+        }
+    }
+    std::vector<double> lnkout(n_k);
+    for (int i = 0; i < n_k; ++i) lnkout[i] = std::log(k_out[i]);
+    // device buffers
+    DevBuf<double2> d_tw, d_ci, d_cf;
+    DevBuf<double> d_pd, d_kp, d_rp, d_rpf, d_kpf, d_qc, d_lk, d_xi, d_par, d_out;
+    if (d_tw.alloc(N) || d_ci.alloc(3 * N) || d_cf.alloc(3 * N) || d_pd.alloc(N) || d_kp.alloc(N) || d_rp.alloc(N) ||
+        d_rpf.alloc(3 * N) || d_kpf.alloc(3 * N) || d_qc.alloc(13 * N) || d_lk.alloc(n_k) ||
+        d_xi.alloc(static_cast<size_t>(kChunk) * kOut * N))
+      return LPP_E_NOMEM;
+    const size_t chunk_pts = std::min<int64_t>(n_pts, kChunk);
+    if (!device_io && (d_par.alloc(5 * chunk_pts) || d_out.alloc(chunk_pts * kOut * n_k))) return LPP_E_NOMEM;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+      return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    if (up(d_tw.p, tw.data(), 16 * N) || up(d_ci.p, cinv.data(), 16 * 3 * N) || up(d_cf.p, cfwd.data(), 16 * 3 * N) ||
+        up(d_pd.p, pd.data(), 8 * N) || up(d_kp.p, kpow.data(), 8 * N) || up(d_rp.p, rpow.data(), 8 * N) ||
+        up(d_rpf.p, rpowf.data(), 8 * 3 * N) || up(d_kpf.p, kpowf.data(), 8 * 3 * N) ||
+        up(d_qc.p, qc.data(), 8 * 13 * static_cast<size_t>(N)) || up(d_lk.p, lnkout.data(), 8 * n_k))
+      return LPP_E_DEVICE;
+    LogTables tb{d_tw.p, d_ci.p, d_cf.p, d_pd.p, d_kp.p, d_rp.p, d_rpf.p, d_kpf.p, d_qc.p};
+    const double shot = 2.0 * sigma_gamma * sigma_gamma / nbar;
+    for (int64_t p0 = 0; p0 < n_pts; p0 += kChunk) {
+      const int np = static_cast<int>(std::min<int64_t>(kChunk, n_pts - p0));
+      const double* par = device_io ? params + 5 * p0 : d_par.p;
+      double* o = device_io ? out + p0 * kOut * n_k : d_out.p;
+      if (!device_io && up(d_par.p, params + 5 * p0, 8 * 5 * static_cast<size_t>(np))) return LPP_E_DEVICE;
+      fftlog_inverse_kernel<<<np * kOut, kLogThreads, 0, st>>>(tb, par, s8f, d_xi.p);
+      fftlog_forward_kernel<<<np * kOut, kLogThreads, 0, st>>>(tb, d_xi.p, par, lnk0, d, d_lk.p, n_k, shot, o);
+      if (hipGetLastError() != hipSuccess) return LPP_E_DEVICE;
+      if (!device_io && hipMemcpyAsync(out + p0 * kOut * n_k, d_out.p, 8 * static_cast<size_t>(np) * kOut * n_k,
+                                       hipMemcpyDeviceToHost, st) != hipSuccess)
+        return LPP_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return LPP_E_DEVICE;
+    return LPP_OK;
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
+}
+
+}  // extern "C"

@@ -413,3 +413,27 @@ def test_window_multipoles_match_oracle(lpp, name, prec):
     tol = 1e-9 if prec == "f64" else 1e-4
     err = np.max(np.abs(got["Q"][:, sel] - ref["Q"][:, sel])) / scale
     assert err <= tol, (name, prec, err)
+
+
+def test_template_plain_matches_oracle(lpp):
+    """The plain template path (FFTLog on the GPU, FP64) against the oracle's
+    numpy FFTLog, for a smooth window table and a few parameter points, host
+    and device I/O."""
+    import torch
+    from oracle import window as OW
+    k = OW.log_grid(1e-5, 1e3, 4096)
+    pfid = 2e4 * (k / 0.02) / (1 + (k / 0.02) ** 2) ** 1.4
+    r_q = np.linspace(5.0, 3000.0, 300)
+    Q = np.vstack([np.exp(-r_q / 900.0) * (1.0 if i == 0 else 0.3 * (-1) ** i / (i + 1)) *
+                   (1 + 0.2 * np.sin(r_q / 300.0 + i)) for i in range(5)])
+    kout = np.arange(1, 31) * 0.01
+    pars = np.array([[0.03, 2.0, 0.7, 0.8, 1.0], [0.01, 1.2, 0.9, 0.65, 0.5], [0.045, 2.8, 0.55, 0.95, 1.8]])
+    ref = OW.template_plain(k, pfid, r_q, Q, pars, kout, nbar=1.4e-3, sigma_gamma=0.2)
+    got = lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, pars, kout, 1.4e-3, 0.2)
+    for o in range(5):
+        scale = np.max(np.abs(ref[:, o]))
+        assert np.max(np.abs(got[:, o] - ref[:, o])) <= 1e-9 * scale, (o, np.max(np.abs(got[:, o] - ref[:, o])) / scale)
+    dp = torch.tensor(pars, device="cuda")
+    do = torch.zeros((3, 5, 30), dtype=torch.float64, device="cuda")
+    lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, dp, kout, 1.4e-3, 0.2, out=do)
+    assert np.array_equal(do.cpu().numpy(), got)

@@ -125,3 +125,22 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
                               "gather_shape": 1}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
+
+
+def test_window_coefficients_of_the_library_match_the_paper_and_the_oracle():
+    """The library's host-side Q^X_{l l'} coefficients (used by the template
+    path) against the values printed in the paper and the oracle's exact ones."""
+    import json
+    from fractions import Fraction
+    from oracle import special as S
+    pkg = _lib()
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "window_coefficients.json")))
+    for e in gold["entries"]:
+        for lpp_, q in zip((0, 2, 4, 6, 8), e["q"]):
+            assert abs(pkg.window_coefficient(e["mX"], e["l"], e["lp"], lpp_) - float(Fraction(q))) < 1e-14, e
+    for mX in (0, 2, 4):
+        for l in range(mX, 9, 2):
+            for lp in range(mX, 9, 2):
+                for lpp_ in range(0, 17, 2):
+                    want = float(S.window_coef(mX, l, lp, lpp_))
+                    assert abs(pkg.window_coefficient(mX, l, lp, lpp_) - want) < 1e-13, (mX, l, lp, lpp_)
