@@ -219,6 +219,40 @@ lpp_status lpp_template_plain(const double* pfid, double k_min, double k_max, in
                               const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
                               int32_t device_io, void* stream);
 
+/* ---- Emulator network (the learned stand-in for lpp_template_plain) ----
+ * A fully connected network widths[0] -> ... -> widths[n_layers] with SiLU
+ * (x / (1 + exp(-x))) after every layer but the last, trained on the mean
+ * squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Every matrix
+ * product runs on the matrix cores with BF16 operands and FP32 accumulation;
+ * parameters, gradients and moments are FP32, and a BF16 copy of the
+ * parameters (round to nearest even) feeds the products.  Parameter layout
+ * (lpp_mlp_get_params): for each layer l, W_l [widths[l+1]][widths[l]]
+ * row-major (y = x W^T + b), then b_l.  Initial values: uniform in
+ * +-1/sqrt(fan-in) from a splitmix64 stream of `seed`.  All device arrays are
+ * FP32, row-major [rows][width], on the current device; calls on one network
+ * are stream-ordered and must not overlap.  Not a paper method: the paper has
+ * no emulator (the template path it stands in for is Sec. III.B). */
+typedef struct lpp_mlp_s* lpp_mlp;
+lpp_status lpp_mlp_create(const int32_t* widths, int32_t n_layers, int64_t max_batch, uint64_t seed, lpp_mlp* out);
+lpp_status lpp_mlp_destroy(lpp_mlp mlp);
+lpp_status lpp_mlp_set_stream(lpp_mlp mlp, void* hip_stream);
+lpp_status lpp_mlp_num_params(lpp_mlp mlp, int64_t* n);
+/* FP32 parameters and the last step's gradients to host arrays (either may be NULL). */
+lpp_status lpp_mlp_get_params(lpp_mlp mlp, float* params_host, float* grads_host);
+lpp_status lpp_mlp_set_params(lpp_mlp mlp, const float* params_host);
+/* Y[B][widths[n_layers]] = net(X[B][widths[0]]), B <= max_batch (device arrays). */
+lpp_status lpp_mlp_forward(lpp_mlp mlp, const float* X, int64_t B, float* Y);
+/* One Adam step on the batch (X, targets T) at learning rate lr; the batch
+ * loss to *loss_host if not NULL (then the stream is synchronised). */
+lpp_status lpp_mlp_train_step(lpp_mlp mlp, const float* X, const float* T, int64_t B, float lr, float* loss_host);
+/* epochs over the n rows of (X, T) (device arrays), batches of `batch` rows in
+ * a splitmix64-shuffled order per epoch (the last partial batch dropped), the
+ * learning rate following a cosine from lr0 to lr1 over the whole fit; each
+ * epoch's step is captured once into a HIP graph and replayed.  The last
+ * batch loss to *final_loss if not NULL.  Synchronises the stream. */
+lpp_status lpp_mlp_fit(lpp_mlp mlp, const float* X, const float* T, int64_t n, int32_t batch, int32_t epochs, float lr0,
+                       float lr1, uint64_t seed, float* final_loss);
+
 /* Launch shapes of the plan's kernels (0 = the built-in default).  Every
  * choice gives the same result up to FP32/FP64 rounding order of the shell
  * sums (the transforms and the deposit are unchanged bit for bit). */

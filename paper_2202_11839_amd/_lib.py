@@ -26,7 +26,9 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
-           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain"]
+           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_mlp_create",
+           "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
+           "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_yz", "bin_blocks", "gather_density", "gather_shape"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
@@ -330,6 +332,72 @@ class Plan:
             import torch
             return LPP_F64 if x.dtype == torch.float64 else LPP_F32
         return LPP_F64 if np.asarray(x).dtype == np.float64 else LPP_F32
+
+
+class Mlp:
+    """The emulator network of the library (lpp_mlp_*); arrays are float32 CUDA tensors."""
+
+    def __init__(self, widths, max_batch: int, seed: int = 0):
+        self.lib = load()
+        self.widths = list(widths)
+        w = (C.c_int32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(self.lib.lpp_mlp_create(w, C.c_int32(len(self.widths) - 1), C.c_int64(max_batch), C.c_uint64(seed),
+                                       C.byref(h)), "lpp_mlp_create")
+        self.handle = h
+        n = C.c_int64()
+        _check(self.lib.lpp_mlp_num_params(h, C.byref(n)), "lpp_mlp_num_params")
+        self.n_params = n.value
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self.lib.lpp_mlp_destroy(self.handle)
+            self.handle = None
+
+    def _stream(self):
+        import torch
+        self.lib.lpp_mlp_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+    @staticmethod
+    def _ptr(t):
+        assert t.is_cuda and t.is_contiguous(), "float32 contiguous CUDA tensor expected"
+        return C.c_void_p(t.data_ptr())
+
+    def params(self, grads: bool = False):
+        import numpy as np
+        self._stream()
+        p = np.zeros(self.n_params, dtype=np.float32)
+        g = np.zeros(self.n_params, dtype=np.float32) if grads else None
+        fp = C.POINTER(C.c_float)
+        _check(self.lib.lpp_mlp_get_params(self.handle, p.ctypes.data_as(fp),
+                                           g.ctypes.data_as(fp) if grads else None), "lpp_mlp_get_params")
+        return (p, g) if grads else p
+
+    def set_params(self, p) -> None:
+        import numpy as np
+        self._stream()
+        q = np.ascontiguousarray(p, dtype=np.float32)
+        _check(self.lib.lpp_mlp_set_params(self.handle, q.ctypes.data_as(C.POINTER(C.c_float))), "lpp_mlp_set_params")
+
+    def forward(self, X, Y) -> None:
+        self._stream()
+        _check(self.lib.lpp_mlp_forward(self.handle, self._ptr(X), C.c_int64(X.shape[0]), self._ptr(Y)),
+               "lpp_mlp_forward")
+
+    def train_step(self, X, T, lr: float) -> float:
+        self._stream()
+        loss = C.c_float()
+        _check(self.lib.lpp_mlp_train_step(self.handle, self._ptr(X), self._ptr(T), C.c_int64(X.shape[0]),
+                                           C.c_float(lr), C.byref(loss)), "lpp_mlp_train_step")
+        return loss.value
+
+    def fit(self, X, T, batch: int, epochs: int, lr0: float, lr1: float, seed: int = 0) -> float:
+        self._stream()
+        loss = C.c_float()
+        _check(self.lib.lpp_mlp_fit(self.handle, self._ptr(X), self._ptr(T), C.c_int64(X.shape[0]),
+                                    C.c_int32(batch), C.c_int32(epochs), C.c_float(lr0), C.c_float(lr1),
+                                    C.c_uint64(seed), C.byref(loss)), "lpp_mlp_fit")
+        return loss.value
 
 
 def window_coefficient(mX: int, l: int, lp: int, lpp: int) -> float:

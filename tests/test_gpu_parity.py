@@ -437,3 +437,81 @@ def test_template_plain_matches_oracle(lpp):
     do = torch.zeros((3, 5, 30), dtype=torch.float64, device="cuda")
     lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, dp, kout, 1.4e-3, 0.2, out=do)
     assert np.array_equal(do.cpu().numpy(), got)
+
+
+# ---------------------------------------------------------------------------
+# the emulator network
+
+EMU_WIDTHS = [5, 256, 256, 256, 150]
+
+
+def _emu_setup(seed=5, B=300):
+    import torch
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, (B, 5))
+    T = np.sin(X @ rng.standard_normal((5, 150))) + 0.1 * rng.standard_normal((B, 150))
+    return (X, T, torch.tensor(X, dtype=torch.float32, device="cuda"),
+            torch.tensor(T, dtype=torch.float32, device="cuda"))
+
+
+def test_mlp_forward_matches_oracle(lpp):
+    """Forward pass (BF16 MFMA, FP32 accumulation) of the 5-256-256-256-150
+    network against the FP64 oracle with the same BF16 operand rounding, on
+    300 rows (partial 32-row tiles).  Tolerance 3e-3 of the output scale: a
+    BF16 rounding decision taken on an FP32 vs an FP64 sum can differ by one
+    BF16 unit (2^-8 relative) on a few activations."""
+    import torch
+    from oracle import mlp as OM
+    net = lpp.Mlp(EMU_WIDTHS, max_batch=512, seed=11)
+    p = net.params()
+    X, T, Xd, Td = _emu_setup()
+    Y = torch.zeros((X.shape[0], 150), dtype=torch.float32, device="cuda")
+    net.forward(Xd, Y)
+    ref = OM.forward(p.astype(np.float64), EMU_WIDTHS, X.astype(np.float32).astype(np.float64), bf16=True)
+    err = np.max(np.abs(Y.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 3e-3, err
+
+
+def test_mlp_gradients_and_adam_match_oracle(lpp):
+    """One training step: the loss and the gradients (BF16 backward products)
+    against the oracle's chain rule with the same roundings, then Adam's
+    update against the oracle's Adam applied to the device's own gradients."""
+    from oracle import mlp as OM
+    net = lpp.Mlp(EMU_WIDTHS, max_batch=512, seed=12)
+    p0 = net.params().astype(np.float64)
+    X, T, Xd, Td = _emu_setup(6)
+    Xf = X.astype(np.float32).astype(np.float64)
+    Tf = T.astype(np.float32).astype(np.float64)
+    loss = net.train_step(Xd, Td, lr=1e-3)
+    p1, g = net.params(grads=True)
+    ref_loss, ref_g = OM.loss_and_grads(p0, EMU_WIDTHS, Xf, Tf, bf16=True)
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    off = 0
+    for l in range(4):
+        n_w = EMU_WIDTHS[l] * EMU_WIDTHS[l + 1]
+        for seg in (slice(off, off + n_w), slice(off + n_w, off + n_w + EMU_WIDTHS[l + 1])):
+            scale = np.max(np.abs(ref_g[seg]))
+            assert np.max(np.abs(g[seg] - ref_g[seg])) <= 2e-2 * scale, (l, seg)
+        off += n_w + EMU_WIDTHS[l + 1]
+    want, _, _ = OM.adam_step(p0, g.astype(np.float64), 0.0, 0.0, 1, 1e-3)
+    assert np.max(np.abs(p1 - want)) <= 1e-6
+
+
+def test_mlp_fit_learns_and_is_deterministic(lpp):
+    """Graph-replayed training lowers the loss of a smooth map (plus noise of
+    variance 0.01) by over 85% in 30 epochs, and two fits from the same seeds
+    end with identical parameters."""
+    import torch
+    X, T, Xd, Td = _emu_setup(7, B=2048)
+    losses, params = [], []
+    for _ in range(2):
+        net = lpp.Mlp(EMU_WIDTHS, max_batch=2048, seed=3)
+        Y = torch.zeros((2048, 150), dtype=torch.float32, device="cuda")
+        net.forward(Xd, Y)
+        before = float(torch.mean((Y - Td) ** 2))
+        net.fit(Xd, Td, batch=256, epochs=30, lr0=2e-3, lr1=1e-5, seed=9)
+        net.forward(Xd, Y)
+        losses.append((before, float(torch.mean((Y - Td) ** 2))))
+        params.append(net.params())
+    assert losses[0][1] < 0.15 * losses[0][0], losses
+    assert np.array_equal(params[0], params[1])
