@@ -165,6 +165,94 @@ def batch_c3(lpp, torch, k, reps):
             "eager_mocks_per_s": round(len(pick) / de, 3), "graph_captures": caps, "graph_launches": launches}
 
 
+def emulator_c5(lpp, torch, wl, ran, gal, rdev, epochs):
+    """Window multipoles Q_l (l <= 8) of the 512^3 workload's randoms on a
+    padded 3400 Mpc/h box (512^3, r <= 2000 Mpc/h in 200 shells), the plain
+    template path (FFTLog, FP64) over a 22,000-point Latin hypercube of
+    (A, b, f, sigma8, s_N), and the BF16 emulator trained on 20,000 of them;
+    accuracy on the other 2,000 and the time per 2,000 points of each route,
+    plus the separable evaluation (4 basis templates, a 4 x 150 map per point)."""
+    import numpy as np
+    from paper_2202_11839_amd.emulator import Emulator, accuracy
+    from synth import EMU_RANGES, latin_hypercube, power_spectrum
+    out = {}
+    plan = lpp.Plan(512, 3400.0, (-50.0, -50.0, -50.0), wl["observer"], assignment=3, interlacing=1,
+                    precision="f32", lmax=4, n_kbins=50)
+    alpha = float(np.sum(gal.w) / np.sum(ran.w))
+    plan.window_multipoles(rdev, alpha, lmax=8, n_rbins=200, rmax=2000.0)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    win = plan.window_multipoles(rdev, alpha, lmax=8, n_rbins=200, rmax=2000.0)
+    out["window_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
+    del plan
+    torch.cuda.empty_cache()
+    sel = win["counts"] > 0
+    r_q, Q = win["r_eff"][sel], win["Q"][:, sel]
+    kgrid = np.exp(np.linspace(np.log(1e-5), np.log(1e3), 4096))
+    pfid = power_spectrum(kgrid)
+    kout = np.arange(1, 31) * 0.01
+    nbar = float(gal.nbar[0])  # constant over the catalog
+    sig = float(wl["sigma"])
+    pts = latin_hypercube(22000, EMU_RANGES, seed=0)
+    P = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((22000, 5, 30), dtype=torch.float64, device="cuda")
+    lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, P[:100], kout, nbar, sig, out=Y[:100])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, P, kout, nbar, sig, out=Y)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    out["plain_ms_22000"] = round(1e3 * t_plain, 1)
+    t0 = time.perf_counter()
+    lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, P[20000:], kout, nbar, sig, out=Y[20000:])
+    torch.cuda.synchronize()
+    t_plain2k = time.perf_counter() - t0
+    emu = Emulator(EMU_RANGES, n_k=30, max_batch=4096, seed=1)
+    t0 = time.perf_counter()
+    loss = emu.fit(P[:20000], Y[:20000], nbar, sig, epochs=epochs, batch=512, lr0=3e-3, lr1=1e-5, seed=2)
+    torch.cuda.synchronize()
+    out["train_s"] = round(time.perf_counter() - t0, 2)
+    out["train_loss"] = loss
+    E = torch.zeros((2000, 5, 30), dtype=torch.float64, device="cuda")
+    emu.predict(P[20000:], E)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        emu.predict(P[20000:], E)
+    torch.cuda.synchronize()
+    t_emu = (time.perf_counter() - t0) / 10
+    rel, perk = accuracy(E.cpu().numpy(), Y[20000:].cpu().numpy())
+    names = ["P+_0", "P+_2", "P+_4", "Pgd_2", "Pgd_4"]
+    out["heldout_max_rel_err"] = {n_: round(float(rel[:, i].max()), 5) for i, n_ in enumerate(names)}
+    out["heldout_p99_rel_err"] = {n_: round(float(np.percentile(rel[:, i], 99)), 5) for i, n_ in enumerate(names)}
+    out["heldout_max_perk_rel_err"] = {n_: round(float(perk[:, i].max()), 5) for i, n_ in enumerate(names)}
+    out["within_1pct"] = bool(rel.max() <= 0.01)
+    out["plain_ms_2000"] = round(1e3 * t_plain2k, 2)
+    out["emulator_ms_2000"] = round(1e3 * t_emu, 3)
+    out["speedup_vs_plain"] = round(t_plain2k / t_emu, 1)
+    # separable evaluation: four basis templates from the plain path, then a 4 x 150 map per point
+    basis_pts = np.array([[1.0, 1.0, 0.0, 1.0, 0.0], [1.0, 0.0, 1.0, 1.0, 0.0]])
+    Bm = lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, basis_pts, kout, nbar, sig)
+    plus = Bm[0, :3]                       # A^2 sigma8^2 = 1
+    gd_b = Bm[0, 3:]                       # (7b + f) = 7, f = 0
+    gd_f = Bm[1, 3:]                       # (7b + f) = 1, f = 1
+    basis = np.stack([np.concatenate([plus.ravel(), np.zeros(60)]), np.concatenate([np.zeros(90), gd_b.ravel() / 7.0]),
+                      np.concatenate([np.zeros(90), (gd_f - gd_b / 7.0).ravel()]),
+                      np.concatenate([np.full(30, 2 * sig * sig / nbar), np.zeros(120)])])
+    hp = pts[20000:]
+    t0 = time.perf_counter()
+    coef = np.stack([hp[:, 0] ** 2 * hp[:, 3] ** 2, hp[:, 0] * hp[:, 3] ** 2 * (7 * hp[:, 1] + hp[:, 2]),
+                     hp[:, 0] * hp[:, 3] ** 2 * hp[:, 2], hp[:, 4]], axis=1)
+    sepv = coef @ basis
+    t_sep = time.perf_counter() - t0
+    sep_rel, _ = accuracy(sepv.reshape(2000, 5, 30), Y[20000:].cpu().numpy())
+    out["separable_ms_2000_host"] = round(1e3 * t_sep, 3)
+    out["separable_max_rel_err"] = float(sep_rel.max())
+    log(f"emulator: plain {1e3 * t_plain2k:.2f} ms / 2000 pts, emulator {1e3 * t_emu:.3f} ms, "
+        f"max held-out err {rel.max():.4f}, separable {1e3 * t_sep:.3f} ms (err {sep_rel.max():.1e})")
+    return out
+
+
 def cpu_baseline(wl, gal, ran):
     """The FP64 oracle timed on a bounded sample of the same workload.
 
@@ -218,6 +306,10 @@ def main():
                     help="mocks of the 256^3 batch workload (spread over its 64-mock size ladder) "
                          "timed through the graph-captured batch path; 0 skips it")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--emulator", type=int, default=1,
+                    help="1: window multipoles of the 512^3 randoms, the plain template path over the 22,000-point "
+                         "design and the emulator trained on 20,000 of them (accuracy on the other 2,000, speedup)")
+    ap.add_argument("--emu-epochs", type=int, default=600)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -287,6 +379,8 @@ def main():
 
     if args.batch_mocks > 0:
         extra["batch_c3"] = batch_c3(lpp, torch, args.batch_mocks, args.batch_reps)
+    if args.emulator:
+        extra["emulator_c5"] = emulator_c5(lpp, torch, wl, ran, gal, rdev, args.emu_epochs)
 
     cpu = None
     if args.cpu_baseline:

@@ -253,6 +253,24 @@ lpp_status lpp_mlp_train_step(lpp_mlp mlp, const float* X, const float* T, int64
 lpp_status lpp_mlp_fit(lpp_mlp mlp, const float* X, const float* T, int64_t n, int32_t batch, int32_t epochs, float lr0,
                        float lr1, uint64_t seed, float* final_loss);
 
+/* The emulator's encoding of lpp_template_plain's outputs (device arrays;
+ * params [n][5] = (A, b, f, sigma8, s_N), templates [n][5][n_k] FP64):
+ *   X[n][5]       (theta_i - lo_i) / (hi_i - lo_i) * 2 - 1, ranges = {lo_0, hi_0, ..., lo_4, hi_4} (host);
+ *   T[n][5 n_k]   standardised shapes: P~_+^(l) / (A^2 sigma8^2) with the shot noise
+ *                 s_N 2 sigma_gamma^2 / nbar taken out of l = 0, P~_gd^(L) / (A sigma8^2),
+ *                 minus mean[c], over sd[c] (FP64 column statistics over the n rows, written
+ *                 to the device arrays mean, sd [5 n_k]; sd = 1 for a column whose spread is
+ *                 below 1e-9 of its mean, i.e. constant up to rounding).
+ * Synchronises the stream; allocates an FP64 scratch of n * 5 n_k values. */
+lpp_status lpp_emulator_encode(const double* params, const double* templates, int64_t n, int32_t n_k,
+                               const double* ranges, double nbar, double sigma_gamma, float* X, float* T,
+                               double* mean, double* sd, void* hip_stream);
+/* The inverse map around the network: out[n][5][n_k] (device, FP64) for the
+ * parameter points params[n][5] (device), with a network of widths 5 -> ... -> 5 n_k
+ * trained on lpp_emulator_encode's (X, T); batches of the network's max_batch. */
+lpp_status lpp_emulator_predict(lpp_mlp mlp, const double* params, int64_t n, int32_t n_k, const double* ranges,
+                                double nbar, double sigma_gamma, const double* mean, const double* sd, double* out);
+
 /* Launch shapes of the plan's kernels (0 = the built-in default).  Every
  * choice gives the same result up to FP32/FP64 rounding order of the shell
  * sums (the transforms and the deposit are unchanged bit for bit). */

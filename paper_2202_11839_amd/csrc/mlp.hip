@@ -204,6 +204,104 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, const float* __r
 
 int blocks_for(int64_t n) { return static_cast<int>(std::min<int64_t>(4096, (n + kT - 1) / kT)); }
 
+// ---- the emulator's encoding of the template path ----
+// inputs: theta_i scaled to [-1, 1] over ranges [lo_i, hi_i];
+// outputs: P~_+^(l) / (A^2 sigma8^2) (the shot noise taken out of l = 0) and
+// P~_gd^(L) / (A sigma8^2), then standardised per output column.
+struct EmuArgs {
+  double lo[5], hi[5];
+  double shot;  // 2 sigma_gamma^2 / nbar
+  int nk;
+};
+
+__device__ __forceinline__ double emu_prefactor(const double* p, int o) {
+  const double s2 = p[3] * p[3];
+  return o < 3 ? p[0] * p[0] * s2 : p[0] * s2;
+}
+
+__global__ void emu_inputs_kernel(EmuArgs a, const double* __restrict__ params, int64_t n, float* __restrict__ X) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < 5 * n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(i % 5);
+    X[i] = static_cast<float>(2.0 * (params[i] - a.lo[c]) / (a.hi[c] - a.lo[c]) - 1.0);
+  }
+}
+
+// shape-normalised outputs, FP64 [n][5 nk]
+__global__ void emu_shapes_kernel(EmuArgs a, const double* __restrict__ params, const double* __restrict__ templ,
+                                  int64_t n, double* __restrict__ shapes) {
+  const int w = 5 * a.nk;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n * w;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / w;
+    const int o = static_cast<int>((i % w) / a.nk);
+    const double* p = params + 5 * r;
+    double v = templ[i];
+    if (o == 0) v -= a.shot * p[4];
+    shapes[i] = v / emu_prefactor(p, o);
+  }
+}
+
+// per column: mean and standard deviation over the rows (FP64, fixed order)
+__global__ void __launch_bounds__(kT) column_stats_kernel(const double* __restrict__ x, int64_t n, int w,
+                                                        double* __restrict__ mean, double* __restrict__ sd) {
+  __shared__ double sh[kT];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += kT) s += x[r * w + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double mu = sh[0] / static_cast<double>(n);
+  __syncthreads();
+  double q = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += kT) {
+    const double d = x[r * w + c] - mu;
+    q += d * d;
+  }
+  sh[threadIdx.x] = q;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mean[c] = mu;
+    // a column that is constant up to rounding (the plus shapes do not depend
+    // on the parameters) keeps sd = 1: its targets are then ~0, not rounding
+    // noise blown up to unit variance
+    const double v = sh[0] / static_cast<double>(n), floor = 1e-9 * fabs(mu);
+    sd[c] = v > floor * floor && v > 0.0 ? sqrt(v) : 1.0;
+  }
+}
+
+__global__ void standardise_kernel(const double* __restrict__ x, int64_t n, int w, const double* __restrict__ mean,
+                                   const double* __restrict__ sd, float* __restrict__ T) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n * w;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(i % w);
+    T[i] = static_cast<float>((x[i] - mean[c]) / sd[c]);
+  }
+}
+
+__global__ void emu_outputs_kernel(EmuArgs a, const double* __restrict__ params, const float* __restrict__ Y,
+                                   int64_t n, const double* __restrict__ mean, const double* __restrict__ sd,
+                                   double* __restrict__ out) {
+  const int w = 5 * a.nk;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n * w;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = i / w;
+    const int c = static_cast<int>(i % w), o = c / a.nk;
+    const double* p = params + 5 * r;
+    double v = (static_cast<double>(Y[i]) * sd[c] + mean[c]) * emu_prefactor(p, o);
+    if (o == 0) v += a.shot * p[4];
+    out[i] = v;
+  }
+}
+
 template <int EPI>
 hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
                 int64_t sbk, int64_t sbn, const EpiArgs& e) {
@@ -425,6 +523,60 @@ lpp_status lpp_mlp_train_step(lpp_mlp m, const float* X, const float* T, int64_t
   if (e == hipSuccess && loss_host) {
     e = hipMemcpyAsync(loss_host, m->loss, 4, hipMemcpyDeviceToHost, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  }
+  return status_of(e);
+}
+
+lpp_status lpp_emulator_encode(const double* params, const double* templ, int64_t n, int32_t n_k,
+                               const double* ranges, double nbar, double sigma_gamma, float* X, float* T,
+                               double* mean, double* sd, void* stream) {
+  if (!params || !templ || !ranges || !X || !T || !mean || !sd || n < 1 || n_k < 1 || !(nbar > 0.0)) return LPP_E_INVALID;
+  EmuArgs a{};
+  for (int i = 0; i < 5; ++i) {
+    a.lo[i] = ranges[2 * i];
+    a.hi[i] = ranges[2 * i + 1];
+    if (!(a.hi[i] > a.lo[i])) return LPP_E_INVALID;
+  }
+  a.shot = 2.0 * sigma_gamma * sigma_gamma / nbar;
+  a.nk = n_k;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const int w = 5 * n_k;
+  double* shapes = nullptr;
+  if (hipMalloc(&shapes, 8 * static_cast<size_t>(n) * w) != hipSuccess) return LPP_E_NOMEM;
+  emu_inputs_kernel<<<blocks_for(5 * n), kT, 0, st>>>(a, params, n, X);
+  emu_shapes_kernel<<<blocks_for(n * w), kT, 0, st>>>(a, params, templ, n, shapes);
+  column_stats_kernel<<<w, kT, 0, st>>>(shapes, n, w, mean, sd);
+  standardise_kernel<<<blocks_for(n * w), kT, 0, st>>>(shapes, n, w, mean, sd, T);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(shapes);
+  return status_of(e);
+}
+
+lpp_status lpp_emulator_predict(lpp_mlp m, const double* params, int64_t n, int32_t n_k, const double* ranges,
+                                double nbar, double sigma_gamma, const double* mean, const double* sd, double* out) {
+  if (!m || !params || !ranges || !mean || !sd || !out || n < 0 || n_k < 1 || !(nbar > 0.0) ||
+      m->w[0] != 5 || m->w[m->nl] != 5 * n_k)
+    return LPP_E_INVALID;
+  EmuArgs a{};
+  for (int i = 0; i < 5; ++i) {
+    a.lo[i] = ranges[2 * i];
+    a.hi[i] = ranges[2 * i + 1];
+  }
+  a.shot = 2.0 * sigma_gamma * sigma_gamma / nbar;
+  a.nk = n_k;
+  hipError_t e = hipSuccess;
+  for (int64_t r0 = 0; r0 < n && e == hipSuccess; r0 += m->max_batch) {
+    const int64_t B = std::min<int64_t>(m->max_batch, n - r0);
+    emu_inputs_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(a, params + 5 * r0, B, m->Xb);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    to_bf16_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(m->Xb, 5 * B, m->A[0]);
+    e = forward(m, static_cast<int>(B), nullptr);
+    if (e != hipSuccess) break;
+    emu_outputs_kernel<<<blocks_for(B * 5 * n_k), kT, 0, m->stream>>>(a, params + 5 * r0, m->Z[m->nl - 1], B, mean,
+                                                                       sd, out + r0 * 5 * n_k);
+    e = hipGetLastError();
   }
   return status_of(e);
 }

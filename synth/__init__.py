@@ -329,3 +329,20 @@ def lattice_catalogs(n, box, origin, observer, seed, delta_rms=0.1, amp=1.0):
     gal = Catalog(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), w, nbar.copy(), g1, g2)
     ran = Catalog(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), np.ones(n ** 3), nbar)
     return gal, ran, s
+
+
+# ---------------------------------------------------------------------------
+# emulator training design
+
+EMU_RANGES = ((0.0, 0.05), (1.0, 3.0), (0.5, 1.0), (0.6, 1.0), (0.5, 2.0))  # A, b, f, sigma8, s_N
+
+
+def latin_hypercube(n: int, ranges=EMU_RANGES, seed: int = 0) -> np.ndarray:
+    """Seeded Latin hypercube of n points over the box `ranges` (one stratum
+    per point and axis, strata shuffled independently per axis)."""
+    rng = seed_seq(5, seed, 0)
+    d = len(ranges)
+    u = (rng.permuted(np.tile(np.arange(n), (d, 1)), axis=1).T + rng.random((n, d))) / n
+    lo = np.array([r[0] for r in ranges])
+    hi = np.array([r[1] for r in ranges])
+    return lo + u * (hi - lo)

@@ -515,3 +515,26 @@ def test_mlp_fit_learns_and_is_deterministic(lpp):
         params.append(net.params())
     assert losses[0][1] < 0.15 * losses[0][0], losses
     assert np.array_equal(params[0], params[1])
+
+
+def test_emulator_round_trip_on_template_design(lpp):
+    """The emulator's encoding and decoding around the network: trained for a
+    few hundred epochs on 3,000 plain-path templates of a smooth window, its
+    held-out predictions stay within 2 % of the plain path (the 1 % bar is
+    measured on the full 20,000-point design by bench.py)."""
+    import torch
+    from paper_2202_11839_amd.emulator import Emulator, accuracy
+    from synth import EMU_RANGES, latin_hypercube, power_spectrum
+    k = np.exp(np.linspace(np.log(1e-5), np.log(1e3), 4096))
+    r_q = np.linspace(5.0, 2000.0, 200)
+    Q = np.vstack([np.exp(-r_q / 700.0) * (1.0 if i == 0 else 0.2 / (i + 1)) for i in range(5)])
+    pts = latin_hypercube(3300, EMU_RANGES, seed=4)
+    P = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((3300, 5, 30), dtype=torch.float64, device="cuda")
+    lpp.template_plain(power_spectrum(k), 1e-5, 1e3, r_q, Q, P, np.arange(1, 31) * 0.01, 1.4e-3, 0.2, out=Y)
+    emu = Emulator(EMU_RANGES, n_k=30, max_batch=512, seed=1)
+    emu.fit(P[:3000], Y[:3000], 1.4e-3, 0.2, epochs=200, batch=128, lr0=2e-3, lr1=1e-5, seed=3)
+    E = torch.zeros((300, 5, 30), dtype=torch.float64, device="cuda")
+    emu.predict(P[3000:], E)
+    rel, _ = accuracy(E.cpu().numpy(), Y[3000:].cpu().numpy())
+    assert np.all(np.isfinite(rel)) and rel.max() < 0.02, rel.max(axis=0)
