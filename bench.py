@@ -338,7 +338,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     wl = dict(WORKLOADS[args.workload])
     t0 = time.perf_counter()
-    gal, ran = make_catalogs(wl, mock=0)
+    # above 512^3 the galaxies are drawn from a 512^3 GRF of the same box (the
+    # clustering only shapes the footprint's occupancy; the mesh is the workload)
+    gal, ran = make_catalogs(wl, mock=0, grf_mesh=min(wl["mesh"], 512))
     log(f"catalogs generated in {time.perf_counter() - t0:.1f} s: {gal.n} galaxies, {ran.n} randoms")
     gdev, rdev = to_device(gal, torch), to_device(ran, torch)
     torch.cuda.synchronize()
@@ -393,7 +395,9 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": ("single mock, 512^3 mesh, wedge RA 0-90 Dec 0-40 r 1000-1600 Mpc/h, "
                                 "1.5M galaxies + 15M randoms, TSC + interlacing, l<=4, 50 shells")
-                   if args.workload == "c2" else args.workload,
+                   if args.workload == "c2" else
+                   ("single mock, 1024^3 mesh, wedge RA 0-90 Dec 0-40 r 1000-1800 Mpc/h, 10M galaxies + 50M "
+                    "randoms, TSC + interlacing, l<=4, 80 shells") if args.workload == "c4" else args.workload,
                    "mesh": n, "n_gal": gal.n, "n_ran": ran.n, "n_kbins": wl["n_kbins"],
                    "series": len(res["series"]), "fft_fields": 53, "sums": "fp64"},
         "roofline": roof,

@@ -538,3 +538,45 @@ def test_emulator_round_trip_on_template_design(lpp):
     emu.predict(P[3000:], E)
     rel, _ = accuracy(E.cpu().numpy(), Y[3000:].cpu().numpy())
     assert np.all(np.isfinite(rel)) and rel.max() < 0.02, rel.max(axis=0)
+
+
+def test_full_size_512_workload_sampled_outputs(lpp):
+    """The 512^3 workload (1.5M galaxies + 15M randoms, TSC + interlacing,
+    50 shells) in bench.py's launch configuration (device-resident catalogs,
+    FP32): mode counts bit-exact and the scalars at 1e-10 against the oracle,
+    and the two monopoles the oracle computes at full size in FP64 (DD_l0 and
+    PLUS_l0: one deposit and one numpy FFT per grid) at the FP32 tolerance."""
+    import torch
+    from oracle import mesh as OM
+    from synth import WORKLOADS, make_catalogs
+    wl = WORKLOADS["c2"]
+    gal, ran = make_catalogs(wl, mock=0)
+    dev = lambda c: Catalog(*[None if v is None else torch.tensor(v, device="cuda")
+                              for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision="f32", lmax=4, n_kbins=wl["n_kbins"])
+    got = plan.estimate(dev(gal), dev(ran))
+    cfg = E.Config(mesh=wl["mesh"], box=wl["box"], origin=wl["origin"], observer=wl["observer"],
+                   assignment=wl["assignment"], interlacing=wl["interlacing"], lmax=4, n_kbins=wl["n_kbins"])
+    sc = E.scalars(gal, ran)
+    for k in ("alpha", "norm_I", "shot_dd", "shot_plus", "sum_w_gal", "sum_w_ran"):
+        assert abs(got[k] - sc[k]) <= 1e-10 * abs(sc[k]), k
+    num, den = cfg.bin_width()
+    counts = OM.mode_counts(cfg.mesh, cfg.n_kbins, num, den)
+    assert list(got["n_modes"]) == list(counts)
+    bidx = OM.bin_index(cfg.mesh, cfg.n_kbins, num, den)
+    comp = OM.compensation(cfg.mesh, cfg.assignment)
+    phase = OM.interlace_phase(cfg.mesh)
+    safe = np.where(counts > 0, counts, 1)
+    allpos = np.concatenate([gal.pos(), ran.pos()])
+    Fd = E._transform(cfg, allpos, np.concatenate([gal.w, -sc["alpha"] * ran.w]), comp, phase)
+    dd0 = E._bin_sums(cfg, bidx, Fd * np.conj(Fd)).real / (sc["norm_I"] * safe) - sc["shot_dd"]
+    del Fd
+    Fg = E._transform(cfg, gal.pos(), gal.w * (gal.g1 + 1j * gal.g2), comp, phase)
+    pp0 = E._bin_sums(cfg, bidx, Fg * np.conj(Fg)).real / (sc["norm_I"] * safe) - sc["shot_plus"]
+    del Fg
+    s = got["series"]
+    for name, ref, shot in (("DD_l0", dd0, sc["shot_dd"]), ("PLUS_l0", pp0, sc["shot_plus"])):
+        g = got["re"][s.index(name)]
+        scale = np.abs(ref) + shot  # the auto power before shot-noise subtraction
+        assert np.max(np.abs(g - ref) / scale) <= 1e-4, name
