@@ -365,7 +365,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
-            "kernel": "fft_axis_kernel<float, %d, %d, false> (y and z passes)" % (n, min(n, 8192 // n)),
+            "kernel": "fft_zb_kernel<float, %d, %d, false> (y and z passes)" % (n, plan.tuning()["fft_cols_yz"]),
             "alg_bytes_per_launch": round(alg_bytes), "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()}}
 

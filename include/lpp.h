@@ -275,8 +275,8 @@ lpp_status lpp_emulator_predict(lpp_mlp mlp, const double* params, int64_t n, in
  * choice gives the same result up to FP32/FP64 rounding order of the shell
  * sums (the transforms and the deposit are unchanged bit for bit). */
 typedef struct {
-  int32_t fft_rows_x;      /* x pass: rows per workgroup (power of 2)                       */
-  int32_t fft_cols_yz;     /* y and z passes: columns per workgroup (power of 2)            */
+  int32_t fft_rows_x;      /* x pass: lines per workgroup, 8 or 16 (8 z-values of 1 or 2 y) */
+  int32_t fft_cols_yz;     /* y and z passes: lines per workgroup, 8 or 16                  */
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
   int32_t gather_density;  /* density fields per deposit pass, 1 .. 4                       */
   int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 2                         */
@@ -295,7 +295,9 @@ lpp_status lpp_autotune(lpp_plan plan, const lpp_catalog* gal, const lpp_catalog
 
 /* Building blocks, exposed for testing and for callers with their own meshes.
  * All meshes are complex, index x + N*(y + N*z), interleaved (re, im), of the
- * plan's precision (float2 or double2), on the device. */
+ * plan's precision (float2 or double2), on the device.  (The estimator keeps
+ * its own meshes z-blocked, ((z/8 N + y) N + x) 8 + z%8; these entry points
+ * take and return the plain order.) */
 
 /* Mass-assign the weights w of a catalog (times `scale`) onto `mesh` (N^3
  * complex; real part = the grid, imaginary part = the interlaced grid if the

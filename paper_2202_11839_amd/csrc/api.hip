@@ -526,7 +526,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
                      const Footprint& fp) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, st);
+    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, st);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
@@ -535,11 +535,11 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
     const FftPrune pr{fp.row, fp.plane, fp.cube, qmax};
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x);
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz);
-    if (e == hipSuccess) e = launch_fft_axis<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz);
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz);
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
     return e;
   };
@@ -719,7 +719,7 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
   void* meshes[1] = {mesh};
   LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, &s0, 1, 0, meshes,
-                           nullptr, p->stream));
+                           nullptr, false, p->stream));
   LPP_TRY(hipStreamSynchronize(p->stream));
   return LPP_OK;
 }
@@ -797,7 +797,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
   auto fft = [&](void* m, const FftPrune& pr) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int axis = 0; axis < 3 && e == hipSuccess; ++axis)
-      e = launch_fft_axis<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz);
+      e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz);
     return e;
   };
   const int per = p->tune.gather_density > 0 ? p->tune.gather_density : kGatherMaxReal;
@@ -816,7 +816,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
     const int nf = static_cast<int>(std::min<size_t>(per, fields.size() - j0));
     FieldSpec specs[kWork];
     for (int q = 0; q < nf; ++q) specs[q] = fields[j0 + q].spec;
-    LPP_TRY(launch_gather<T>(setd, starts, p->geo, specs, nf, 0, W, fp.cube, st));
+    LPP_TRY(launch_gather<T>(setd, starts, p->geo, specs, nf, 0, W, fp.cube, true, st));
     for (int q = 0; q < nf; ++q) LPP_TRY(fft(W[q], in_fp));
     for (int q = 0; q < nf; ++q) {
       const int gi = static_cast<int>(j0) + q;
@@ -980,8 +980,8 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   const int N = p->cfg.mesh_n;
   const bool f64 = p->cfg.precision == LPP_F64;
   lpp_tuning t = p->tune;
-  if (t.fft_rows_x <= 0) t.fft_rows_x = fft_default_lines(N, f64, 0);
-  if (t.fft_cols_yz <= 0) t.fft_cols_yz = fft_default_lines(N, f64, 1);
+  if (t.fft_rows_x <= 0) t.fft_rows_x = zb_default_lines(N, f64, 0);
+  if (t.fft_cols_yz <= 0) t.fft_cols_yz = zb_default_lines(N, f64, 1);
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
   if (t.gather_density <= 0) t.gather_density = kGatherMaxReal;
   if (t.gather_shape <= 0) t.gather_shape = kGatherMaxComplex;
@@ -991,8 +991,8 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
 bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   const int N = p->cfg.mesh_n;
   const bool f64 = p->cfg.precision == LPP_F64;
-  if (t.fft_rows_x != 0 && !fft_lines_supported(N, f64, 0, t.fft_rows_x)) return false;
-  if (t.fft_cols_yz != 0 && !fft_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
+  if (t.fft_rows_x != 0 && !zb_lines_supported(N, f64, 0, t.fft_rows_x)) return false;
+  if (t.fft_cols_yz != 0 && !zb_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
   if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
   if (t.gather_density < 0 || t.gather_density > kGatherMaxReal) return false;
   if (t.gather_shape < 0 || t.gather_shape > kGatherMaxComplex) return false;
@@ -1124,9 +1124,8 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
     best.*field = best_v;
     return LPP_OK;
   };
-  const int dx = fft_default_lines(N, f64, 0), dy = fft_default_lines(N, f64, 1);
-  s = search(&lpp_tuning::fft_rows_x, {dx / 2, dx, 2 * dx}, {LPP_STAGE_FFT_X});
-  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {dy / 4, dy / 2, dy, 2 * dy}, {LPP_STAGE_FFT_YZ});
+  s = search(&lpp_tuning::fft_rows_x, {8, 16}, {LPP_STAGE_FFT_X});
+  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 3, 4}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2}, {LPP_STAGE_DEPOSIT});

@@ -92,9 +92,17 @@ constexpr int tail_radix(int N) {
   return N;  // 1, 2 or 4
 }
 
+// LDS slot of row `row` of column `col`: the row is XOR-ed with a per-column
+// value swz (< N) so that the lanes of one access fall into different banks.
+// col & 15 suits lanes that run across the columns; a workgroup whose lanes
+// run along 8 rows of 8 columns at a time takes (col & 7) * 9.
 template <int N>
-__device__ __forceinline__ int sidx(int col, int row) {
-  return col * N + (row ^ (col & 15));
+__device__ __forceinline__ int sidx(int col, int row, int swz) {
+  return col * N + (row ^ swz);
+}
+template <int N>
+__device__ __forceinline__ int swizzle_rows8(int col) {
+  return N >= 64 ? (col & 7) * 9 : (col & 15);
 }
 
 // Output rows of the column transform below, per thread t (the Stockham
@@ -123,26 +131,29 @@ __device__ __forceinline__ void fft_rows(int t, int* row) {
 // Forward DFT of length N of the columns of one block, N/8 threads per
 // column: on entry v[j] holds element t + j*N/8 of the column, on
 // return v[q] is output row fft_rows(t)[q] of column col.  sm (NCOL*N values)
-// is free again on return.  Every thread of the block must call it.
+// is free again on return.  Every thread of the block must call it.  swz: the
+// LDS row swizzle of the column (sidx), -1 for col & 15.
 template <typename T, int N>
 __device__ __forceinline__ void fft_column_regs(const typename V2<T>::type* __restrict__ tw,
-                                                typename V2<T>::type* sm, int col, int t, typename V2<T>::type* v) {
+                                                typename V2<T>::type* sm, int col, int t, typename V2<T>::type* v,
+                                                int swz = -1) {
   using T2 = typename V2<T>::type;
   constexpr int TL = N / 8;
   constexpr int A8 = n_radix8(N);
   constexpr int TR = tail_radix(N);
   static_assert(A8 >= 1 && (A8 > 1 || TR > 1), "N >= 16");
+  const int sw = swz >= 0 ? swz : (col & 15);
   // pass 0: radix 8, Ns = 1
   dft8<T>(v);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) sm[sidx<N>(col, t * 8 + j)] = v[j];
+  for (int j = 0; j < 8; ++j) sm[sidx<N>(col, t * 8 + j, sw)] = v[j];
   __syncthreads();
   int Ns = 8;
 #pragma unroll
   for (int p = 1; p < A8; ++p) {
     const bool last = (p == A8 - 1) && (TR == 1);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = sm[sidx<N>(col, t + j * TL)];
+    for (int j = 0; j < 8; ++j) v[j] = sm[sidx<N>(col, t + j * TL, sw)];
     const int k = t % Ns;
     const int step = N / (Ns * 8);
 #pragma unroll
@@ -152,7 +163,7 @@ __device__ __forceinline__ void fft_column_regs(const typename V2<T>::type* __re
     if (last) return;  // outputs at t + j*TL
     const int o = (t / Ns) * Ns * 8 + k;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sm[sidx<N>(col, o + j * Ns)] = v[j];
+    for (int j = 0; j < 8; ++j) sm[sidx<N>(col, o + j * Ns, sw)] = v[j];
     __syncthreads();
     Ns *= 8;
   }
@@ -162,7 +173,7 @@ __device__ __forceinline__ void fft_column_regs(const typename V2<T>::type* __re
     for (int q = 0; q < 2; ++q) {
       const int b = t + q * TL;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) v[q * 4 + j] = sm[sidx<N>(col, b + j * (N / 4))];
+      for (int j = 0; j < 4; ++j) v[q * 4 + j] = sm[sidx<N>(col, b + j * (N / 4), sw)];
     }
     __syncthreads();
 #pragma unroll
@@ -176,8 +187,8 @@ __device__ __forceinline__ void fft_column_regs(const typename V2<T>::type* __re
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int b = t + q * TL;
-      v[q * 2 + 0] = sm[sidx<N>(col, b)];
-      v[q * 2 + 1] = sm[sidx<N>(col, b + N / 2)];
+      v[q * 2 + 0] = sm[sidx<N>(col, b, sw)];
+      v[q * 2 + 1] = sm[sidx<N>(col, b + N / 2, sw)];
     }
     __syncthreads();
 #pragma unroll

@@ -7,10 +7,12 @@
 // and accumulate the real and imaginary parts per shell in FP64 (Sec. III.A,
 // eqs. lpp_dens_app, lpp_estimator_cross_Xiij, lpp_estimator_auto_+/-).
 //
-// Each thread walks runs of 8 consecutive x-modes (one 64-byte load per mesh
-// for float2), keeps a running FP64 sum while the shell index stays the same
-// and flushes it to an LDS accumulator on change; the block's accumulators go
-// to a per-block partial row that a second kernel reduces in block order.
+// The meshes are z-blocked (lpp_internal.h).  Each thread walks runs of the 8
+// z-modes of one (x, y) group (one contiguous 64-byte load per mesh for
+// float2; consecutive threads take consecutive x), keeps a running FP64 sum
+// while the shell index stays the same and flushes it to an LDS accumulator
+// on change; the block's accumulators go to a per-block partial row that a
+// second kernel reduces in block order.
 //
 // Density fields are real: their two interlaced copies are packed as the real
 // and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
@@ -78,12 +80,13 @@ __device__ __forceinline__ void acc_flush(Acc& a, double* sre, double* sim, doub
   a.cur = -1;
 }
 
-// Does the run of kRun x-modes starting at x0 reach inside the last shell,
-// given qyz = ny^2 + nz^2?  (N/2 is a multiple of kRun, so a run is all
+// Does the run of kRun z-modes starting at z0 reach inside the last shell,
+// given qxy = nx^2 + ny^2?  (N/2 is a multiple of kRun, so a run is all
 // non-negative or all negative modes.)
-__device__ __forceinline__ bool run_live(int x0, int N, int qyz, int qmax) {
-  const int mx = x0 < N / 2 ? x0 : N - x0 - (kRun - 1);  // smallest |nx| of the run
-  return mx * mx + qyz < qmax;
+static_assert(kRun == kZb, "a run is one z-group");
+__device__ __forceinline__ bool run_live(int z0, int N, int qxy, int qmax) {
+  const int mz = z0 < N / 2 ? z0 : N - z0 - (kRun - 1);  // smallest |nz| of the run
+  return mz * mz + qxy < qmax;
 }
 
 // shared-memory layout: thr[kMaxBins+1] ints, then 4*nb doubles
@@ -92,9 +95,9 @@ struct Smem {
   double v[4 * kMaxBins];
 };
 
-// Per-x tables staged in dynamic LDS (bytes: tables_bytes<T>(N)): the
-// interlacing phase factor along x, exp(-i pi nx/N) at nx + N/2, and 1/W(x).
-// The full phase is that factor times the row's exp(-i pi (ny+nz)/N).
+// Per-axis tables staged in dynamic LDS (bytes: tables_bytes<T>(N)): the
+// interlacing phase factor along one axis, exp(-i pi n/N) at n + N/2, and
+// 1/W(n).  The full phase is the z factor times the run's exp(-i pi (nx+ny)/N).
 template <typename T>
 constexpr size_t tables_bytes(int N) {
   return static_cast<size_t>(N) * (sizeof(typename V2<T>::type) + sizeof(T));
@@ -141,45 +144,45 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
   const int qmax = s.thr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
-  const int64_t runs_per_row = N / kRun;
-  const int64_t nruns = runs_per_row * N * (N / 2);
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const int64_t nruns = NN * (N / 2 / kRun);  // runs (x, y, z-group) with z < N/2
   Acc acc{-1, 0, 0, 0, 0};
   for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
        r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int x0 = static_cast<int>(r % runs_per_row) * kRun;
-    const int iy = static_cast<int>((r / runs_per_row) % N);
-    const int iz = static_cast<int>(r / (runs_per_row * N));
-    const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
-    if (iz == 0 && !(iy < N / 2)) continue;  // z=0 plane: y in [0, N/2)
-    if (!run_live(x0, N, ny * ny + nz * nz, qmax)) continue;
-    const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
-    const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
-    const T wyz = invw[iy] * invw[iz];
-    const T2 pyz = phase[ny + nz + 3 * N / 2];
+    const int ix = static_cast<int>(r % N);
+    const int iy = static_cast<int>((r / N) % N);
+    const int z0 = static_cast<int>(r / NN) * kRun;
+    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
+    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
+    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
+    const int mx = (N - ix) & mask, my = (N - iy) & mask;
+    const T wxy = invw[ix] * invw[iy];
+    const T2 pxy = phase[nx + ny + 3 * N / 2];
     T2 pv[kRun];
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) pv[j] = P[row + x0 + j];
+    for (int j = 0; j < kRun; ++j) pv[j] = P[run + j];
     T2 bv[kRun];
     if (!BASE) {
 #pragma unroll
-      for (int j = 0; j < kRun; ++j) bv[j] = B[row + x0 + j];
+      for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
     }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
-      const int ix = x0 + j;
-      const int nx = sgn_mode(ix, N);
+      const int iz = z0 + j, nz = iz;  // iz < N/2
+      if (iz == 0 && !(iy < N / 2)) continue;                            // z=0 plane: y in [0, N/2)
       if (iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2)) continue;  // y=0 line: x in (0, N/2)
       const int q = nx * nx + ny * ny + nz * nz;
       const int b = shell_of(q, s.thr, nb, inv_dn);
       if (b < 0) continue;
-      const T2 pm = P[mrow + ((N - ix) & mask)];
+      const int64_t midx = zb_index(mx, my, (N - iz) & mask, N);
+      const T2 pm = P[midx];
       // unpack the two real copies
       const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
       const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
-      const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pyz, px[nx + N / 2]), wyz * iw[ix]);
+      const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
       if (BASE) {
-        B[row + ix] = F;
-        B[mrow + ((N - ix) & mask)] = T2{F.x, -F.y};
+        B[run + j] = F;
+        B[midx] = T2{F.x, -F.y};
         acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
                       2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
       } else {
@@ -219,42 +222,42 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
   const int qmax = s.thr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
-  const int64_t runs_per_row = N / kRun;
-  const int64_t nruns = runs_per_row * N * N;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const int64_t nruns = NN * (N / kRun);  // runs (x, y, z-group)
   Acc acc{-1, 0, 0, 0, 0};
   for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
        r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int x0 = static_cast<int>(r % runs_per_row) * kRun;
-    const int iy = static_cast<int>((r / runs_per_row) % N);
-    const int iz = static_cast<int>(r / (runs_per_row * N));
-    const int ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
-    if (!run_live(x0, N, ny * ny + nz * nz, qmax)) continue;
-    const int64_t row = static_cast<int64_t>(N) * (iy + static_cast<int64_t>(N) * iz);
-    const int64_t mrow = static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
-    const T wyz = invw[iy] * invw[iz];
-    const T2 pyz = phase[ny + nz + 3 * N / 2];
+    const int ix = static_cast<int>(r % N);
+    const int iy = static_cast<int>((r / N) % N);
+    const int z0 = static_cast<int>(r / NN) * kRun;
+    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
+    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
+    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
+    const int mx = (N - ix) & mask, my = (N - iy) & mask;
+    const T wxy = invw[ix] * invw[iy];
+    const T2 pxy = phase[nx + ny + 3 * N / 2];
     T2 g1[kRun], g2[kRun], bv[kRun];
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) g1[j] = G1[row + x0 + j];
+    for (int j = 0; j < kRun; ++j) g1[j] = G1[run + j];
     if (a.interlace) {
 #pragma unroll
-      for (int j = 0; j < kRun; ++j) g2[j] = G2[row + x0 + j];
+      for (int j = 0; j < kRun; ++j) g2[j] = G2[run + j];
     }
     if (KIND == 0) {
 #pragma unroll
-      for (int j = 0; j < kRun; ++j) bv[j] = B[row + x0 + j];
+      for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
     }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
-      const int ix = x0 + j;
-      const int nx = sgn_mode(ix, N);
+      const int iz = z0 + j;
+      const int nz = sgn_mode(iz, N);
       const int q = nx * nx + ny * ny + nz * nz;
       const int b = shell_of(q, s.thr, nb, inv_dn);
       if (b < 0) continue;
-      const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pyz, px[nx + N / 2]),
-                                  wyz * iw[ix]);
+      const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
+                                  wxy * iw[iz]);
       if (KIND == 2) {
-        B[row + ix] = F;
+        B[run + j] = F;
         acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
                       sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
         continue;
@@ -265,7 +268,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
       if (KIND == 0) {
         p = cmulc(F, bv[j]);
       } else {
-        const T2 bm = B[mrow + ((N - ix) & mask)];
+        const T2 bm = B[zb_index(mx, my, (N - iz) & mask, N)];
         p = cmul(F, bm);
       }
       acc_add<false>(acc, b, static_cast<double>(hk * p.x), static_cast<double>(hk * p.y), 0.0, 0.0, sre, sim, scnt,

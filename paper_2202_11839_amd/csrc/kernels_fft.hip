@@ -17,6 +17,12 @@
 // planes, reads flagged rows only and stores the (kx, ky) inside the last
 // k-shell only; the z pass reads flagged planes only, skips the (kx, ky)
 // columns outside the last k-shell and stores the modes inside it only.
+//
+// The estimator's meshes are z-blocked (lpp_internal.h): fft_zb_kernel runs
+// the same three passes on that layout, with every workgroup owning whole
+// groups of 8 z-values, so that each HBM access is a run of 64 (FP32) or 128
+// (FP64) contiguous bytes per line, and the lanes of a wavefront cover 8
+// such runs side by side wherever the lines allow it.
 #include <climits>
 
 #include "device_common.h"
@@ -135,6 +141,165 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
   }
 }
 
+// The passes on a z-blocked mesh.  Lines of a workgroup:
+//   x pass: the 8 z of one z-group for NL/8 consecutive rows y; the lanes run
+//           over z%8 first and then along x, so that 8 lanes read the 64
+//           contiguous values of 8 consecutive x;
+//   y pass: the 8 z of one z-group for NL/8 consecutive columns x; the lanes
+//           run across the lines (one contiguous run of NL values per y);
+//   z pass: NL consecutive columns x of one row y; the lanes run over z%8
+//           first and then across the columns (for N >= 64).
+// Pruning as in fft_axis_kernel.  Element e of a thread's line sits at
+// base + (e >> 3) * hi + (e & 7) * lo.
+template <typename T, int N, int NL, bool ALONG>
+__global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type* __restrict__ data, int axis,
+                                                           const typename V2<T>::type* __restrict__ tw,
+                                                           FftPrune pr) {
+  using T2 = typename V2<T>::type;
+  constexpr int TL = N / 8;
+  constexpr int G = NL / kZb;  // rows (x pass) or columns (y pass) per workgroup
+  static_assert(NL % kZb == 0, "whole z-groups");
+  __shared__ T2 sm[NL * N];
+  __shared__ T2 stw[N];
+  const int tid = threadIdx.x;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  int col, t, swz;
+  int64_t base, hi, lo;
+  bool live = true;
+  int qline = 0, qstore = INT_MAX;
+  const uint8_t* lflag = nullptr;  // load flags along the line (nullable): element e reads lflag[e >> lshift]
+  int lshift = 0;
+  if constexpr (ALONG) {
+    const int c = tid & 7, g = tid / (8 * TL);
+    t = (tid >> 3) % TL;
+    col = c + 8 * g;
+    swz = dev::swizzle_rows8<N>(col);
+    const int yb = blockIdx.x % (N / G), zg = blockIdx.x / (N / G);
+    const int y = yb * G + g, z = zg * kZb + c;
+    if (pr.row) {
+      int any = 0;
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int cc = 0; cc < kZb; ++cc) any |= pr.row[yb * G + r + static_cast<int64_t>(N) * (zg * kZb + cc)];
+      if (!any) return;
+      live = pr.row[y + static_cast<int64_t>(N) * z] != 0;
+    }
+    if (pr.cube) {
+      const int nt = N / kTile;
+      lflag = pr.cube + nt * ((y / kTile) + nt * (z / kTile));
+      lshift = 3;
+    }
+    base = zb_index(0, y, z, N);
+    hi = 8 * kZb;
+    lo = kZb;
+  } else if (axis == 1) {
+    col = tid % NL;
+    t = tid / NL;
+    swz = col & 15;
+    const int xc = blockIdx.x % (N / G), zg = blockIdx.x / (N / G);
+    const int x = xc * G + (col >> 3), z = zg * kZb + (col & 7);
+    if (pr.plane) {
+      int any = 0;
+#pragma unroll
+      for (int cc = 0; cc < kZb; ++cc) any |= pr.plane[zg * kZb + cc];
+      if (!any) return;  // the whole z-group is zero
+      live = pr.plane[z] != 0;
+    }
+    if (pr.row) lflag = pr.row + static_cast<int64_t>(N) * z;
+    base = zb_index(x, 0, z, N);
+    hi = 8 * static_cast<int64_t>(N) * kZb;
+    lo = static_cast<int64_t>(N) * kZb;
+    const int nx = dev::sgn_mode(x, N);
+    qline = nx * nx;
+    qstore = pr.qmax;
+  } else {
+    if (TL >= 8) {
+      col = (tid >> 3) % NL;
+      t = (tid & 7) | ((tid / (8 * NL)) << 3);
+      swz = dev::swizzle_rows8<N>(col);
+    } else {
+      col = tid % NL;
+      t = tid / NL;
+      swz = col & 15;
+    }
+    const int xc = blockIdx.x % (N / NL), y = blockIdx.x / (N / NL);
+    // the whole block of columns outside the last k-shell: nothing to do
+    // (mx is the chunk's smallest |nx| when NL | N/2, and 0 otherwise)
+    const int c0 = xc * NL;
+    const int mx = c0 < N / 2 ? c0 : N - c0 - (NL - 1);
+    const int nyb = dev::sgn_mode(y, N);
+    if (mx * mx + nyb * nyb >= pr.qmax) return;
+    const int x = c0 + col;
+    const int nx = dev::sgn_mode(x, N), ny = dev::sgn_mode(y, N);
+    live = nx * nx + ny * ny < pr.qmax;
+    lflag = pr.plane;
+    qline = nx * nx + ny * ny;
+    qstore = pr.qmax;
+    base = zb_index(x, y, 0, N);
+    hi = NN * kZb;
+    lo = 1;
+  }
+  bool rd[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) rd[j] = live;
+  if (lflag != nullptr) {
+    uint8_t f[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = lflag[(t + j * TL) >> lshift];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rd[j] = rd[j] && f[j] != 0;
+  }
+  T2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int e = t + j * TL;
+    v[j] = T2{0, 0};
+    if (rd[j]) v[j] = data[base + (e >> 3) * hi + (e & 7) * lo];
+  }
+  for (int i = tid; i < N; i += NL * TL) stw[i] = tw[i];
+  dev::fft_column_regs<T, N>(stw, sm, col, t, v, swz);
+  if (!live) return;
+  int row[8];
+  dev::fft_rows<N>(t, row);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int m = dev::sgn_mode(row[q], N);
+    if (qline + m * m < qstore) data[base + (row[q] >> 3) * hi + (row[q] & 7) * lo] = v[q];
+  }
+}
+
+template <typename T, int N, int NL>
+constexpr bool zb_ok() {
+  using T2 = typename V2<T>::type;
+  return NL * (N / 8) <= 1024 && static_cast<size_t>(NL + 1) * N * sizeof(T2) <= 160 * 1024;
+}
+
+template <typename T, int N, int NL, bool ALONG>
+hipError_t fft_zb_launch(void* mesh, const void* tw, int axis, const FftPrune& pr, hipStream_t st) {
+  if constexpr (!zb_ok<T, N, NL>()) {
+    return hipErrorInvalidValue;
+  } else {
+    using T2 = typename V2<T>::type;
+    const unsigned grid = static_cast<unsigned>(static_cast<int64_t>(N) * N / NL);
+    fft_zb_kernel<T, N, NL, ALONG><<<grid, NL * (N / 8), 0, st>>>(static_cast<T2*>(mesh), axis,
+                                                                    static_cast<const T2*>(tw), pr);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int N>
+hipError_t fft_zb_n(void* mesh, const void* tw, int axis, const FftPrune& pr, int lines, hipStream_t st) {
+  if (lines <= 0) lines = zb_default_lines(N, sizeof(T) == 8, axis);
+  if (lines == 8)
+    return axis == 0 ? fft_zb_launch<T, N, 8, true>(mesh, tw, axis, pr, st)
+                     : fft_zb_launch<T, N, 8, false>(mesh, tw, axis, pr, st);
+  if (lines == 16)
+    return axis == 0 ? fft_zb_launch<T, N, 16, true>(mesh, tw, axis, pr, st)
+                     : fft_zb_launch<T, N, 16, false>(mesh, tw, axis, pr, st);
+  return hipErrorInvalidValue;
+}
+
 // Lines per workgroup that a pass supports: at most 1024 threads (N/8 per line),
 // at most N columns for the strided passes, and LDS for the lines and twiddles.
 template <typename T, int N, int NCOL, bool ALONG>
@@ -220,6 +385,42 @@ hipError_t launch_fft_axis(void* mesh, int N, const void* tw, int axis, const Ff
   }
 }
 
+int zb_default_lines(int N, bool fp64, int axis) {
+  if (axis == 0 || fp64) return 8;
+  return N <= 512 ? 16 : 8;
+}
+
+bool zb_lines_supported(int N, bool fp64, int axis, int lines) {
+  (void)axis;
+  if (lines != 8 && lines != 16) return false;
+  const size_t lds = static_cast<size_t>(lines + 1) * N * (fp64 ? 16 : 8);
+  return lines * (N / 8) <= 1024 && lds <= 160 * 1024;
+}
+
+template <typename T>
+hipError_t launch_fft_axis_zb(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st,
+                              int lines) {
+  if (lines > 0 && !zb_lines_supported(N, sizeof(T) == 8, axis, lines)) return hipErrorInvalidValue;
+  switch (N) {
+    case 16:
+      return fft_zb_n<T, 16>(mesh, tw, axis, pr, lines, st);
+    case 32:
+      return fft_zb_n<T, 32>(mesh, tw, axis, pr, lines, st);
+    case 64:
+      return fft_zb_n<T, 64>(mesh, tw, axis, pr, lines, st);
+    case 128:
+      return fft_zb_n<T, 128>(mesh, tw, axis, pr, lines, st);
+    case 256:
+      return fft_zb_n<T, 256>(mesh, tw, axis, pr, lines, st);
+    case 512:
+      return fft_zb_n<T, 512>(mesh, tw, axis, pr, lines, st);
+    case 1024:
+      return fft_zb_n<T, 1024>(mesh, tw, axis, pr, lines, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* tw, hipStream_t st) {
   const FftPrune full{nullptr, nullptr, nullptr, INT_MAX};
@@ -233,6 +434,8 @@ hipError_t launch_fft3d(void* mesh, int N, const void* tw, hipStream_t st) {
 template hipError_t launch_fft3d<float>(void*, int, const void*, hipStream_t);
 template hipError_t launch_fft_axis<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
 template hipError_t launch_fft_axis<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
+template hipError_t launch_fft_axis_zb<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
+template hipError_t launch_fft_axis_zb<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
 template hipError_t launch_fft3d<double>(void*, int, const void*, hipStream_t);
 
 }  // namespace lpp

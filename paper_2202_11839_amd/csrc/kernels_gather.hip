@@ -157,6 +157,24 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
   return v;
 }
 
+// Node (x, y, z) of an output mesh, z-blocked or plain.
+__device__ __forceinline__ int64_t node_at(int x, int y, int z, int N, int zblocked) {
+  return zblocked ? zb_index(x, y, z, N) : x + static_cast<int64_t>(N) * (y + static_cast<int64_t>(N) * z);
+}
+// The i-th node that a workgroup stores: node (kx, r % TT, r / TT) of the
+// tile, in memory order, so that consecutive lanes write consecutive
+// addresses: x fastest in the plain layout, z fastest and then x when
+// z-blocked (a tile is TT = 8 runs of 64 contiguous nodes there).
+__device__ __forceinline__ void store_order(int i, int zblocked, int& kx, int& r) {
+  if (zblocked) {
+    kx = (i / TT) % TT;
+    r = (i / (TT * TT)) + TT * (i % TT);
+  } else {
+    kx = i % TT;
+    r = i / TT;
+  }
+}
+
 // K = 1: NF real (density) fields, each written packed: grid -> .x, interlaced
 //        grid -> .y of mesh f (.y is zero without interlacing).
 // K = 2: NF complex (shape) fields; with interlacing grid -> mesh 2f and
@@ -165,7 +183,7 @@ template <typename T, int P, int K, int NF>
 __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
                                                           int N, int lgN, int interlace, T H, T relx, T rely, T relz,
                                                           SpecSet<T, NF> fs, MeshSet<T> out,
-                                                          const uint8_t* __restrict__ tile_flags) {
+                                                          const uint8_t* __restrict__ tile_flags, int zblocked) {
   using T2 = typename V2<T>::type;
   constexpr int CAP = cap_of<T, K, NF>();
   constexpr int ROWS = rows_of<T, K, NF>();
@@ -241,8 +259,9 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   // empty region: the tile is zero in every output mesh
   if (total == 0) {
     for (int i = tid; i < kRows * TT; i += kThreads) {
-      const int kx = i % TT, r = i / TT;
-      const int64_t idx = t0x + kx + static_cast<int64_t>(N) * ((t0y + r % TT) + static_cast<int64_t>(N) * (t0z + r / TT));
+      int kx, r;
+      store_order(i, zblocked, kx, r);
+      const int64_t idx = node_at(t0x + kx, t0y + r % TT, t0z + r / TT, N, zblocked);
       for (int m = 0; m < nmesh; ++m) out.m[m][idx] = T2{0, 0};
     }
     return;
@@ -351,7 +370,7 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
     }
     __syncthreads();
   }
-  // store each output mesh through LDS: consecutive lanes write consecutive nodes of an x-row
+  // store each output mesh through LDS: consecutive lanes write consecutive nodes (store_order)
   T2* stage = reinterpret_cast<T2*>(red);
   static_assert(ROWS * CAP >= 2 * (TT + 1) * kRows, "output staging fits");
   // (the loops over fields and copies are unrolled: acc[] is only ever indexed
@@ -376,10 +395,9 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
       __syncthreads();
       T2* __restrict__ dst = out.m[m];
       for (int i = tid; i < kRows * TT; i += kThreads) {
-        const int kx = i % TT, r = i / TT;
-        const int64_t idx =
-            t0x + kx + static_cast<int64_t>(N) * ((t0y + r % TT) + static_cast<int64_t>(N) * (t0z + r / TT));
-        dst[idx] = stage[r * (TT + 1) + kx];
+        int kx, r;
+        store_order(i, zblocked, kx, r);
+        dst[node_at(t0x + kx, t0y + r % TT, t0z + r / TT, N, zblocked)] = stage[r * (TT + 1) + kx];
       }
       __syncthreads();
     }
@@ -505,7 +523,7 @@ __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, 
 
 template <typename T, int K, int NF>
 hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
-                    const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, hipStream_t st) {
+                    const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
   const T H = static_cast<T>(g.H), rx = static_cast<T>(g.rel[0]), ry = static_cast<T>(g.rel[1]),
           rz = static_cast<T>(g.rel[2]);
   SpecSet<T, NF> fs;
@@ -517,13 +535,13 @@ hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* start
   while ((1 << lg) < g.N) ++lg;
   switch (p) {
     case 1:
-      gather_kernel<T, 1, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
+      gather_kernel<T, 1, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
       break;
     case 2:
-      gather_kernel<T, 2, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
+      gather_kernel<T, 2, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
       break;
     default:
-      gather_kernel<T, 3, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles);
+      gather_kernel<T, 3, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
       break;
   }
   return hipGetLastError();
@@ -623,31 +641,32 @@ hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale
 
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
-                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags,
+                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
                          hipStream_t st) {
-  static_assert(TT == kTile, "footprint tiles are gather tiles");
+  static_assert(TT == kTile && TT == kZb, "footprint tiles are gather tiles and z-groups");
+  const int zb = zblocked ? 1 : 0;
   if (g.N % TT != 0) return hipErrorInvalidValue;
   const int nt = g.N / TT;
   dim3 grid(static_cast<unsigned>(nt) * nt * nt);
   if (!complex_fields) {
     switch (nf) {
       case 1:
-        return dispatch<T, 1, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+        return dispatch<T, 1, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 2:
-        return dispatch<T, 1, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+        return dispatch<T, 1, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 3:
-        return dispatch<T, 1, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+        return dispatch<T, 1, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 4:
-        return dispatch<T, 1, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+        return dispatch<T, 1, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       default:
         return hipErrorInvalidValue;
     }
   }
   switch (nf) {
     case 1:
-      return dispatch<T, 2, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      return dispatch<T, 2, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
     case 2:
-      return dispatch<T, 2, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, st);
+      return dispatch<T, 2, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -670,8 +689,8 @@ template hipError_t launch_cell_scatter<float>(const RawCat&, const Geometry&, d
 template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, double, const double*, int, const uint32_t*,
                                                 const uint32_t*, const uint32_t*, GObjSet<double>, hipStream_t);
 template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec*,
-                                         int, int, void* const*, const uint8_t*, hipStream_t);
+                                         int, int, void* const*, const uint8_t*, bool, hipStream_t);
 template hipError_t launch_gather<double>(const GObjSet<double>&, const uint32_t*, const Geometry&, const FieldSpec*,
-                                          int, int, void* const*, const uint8_t*, hipStream_t);
+                                          int, int, void* const*, const uint8_t*, bool, hipStream_t);
 
 }  // namespace lpp

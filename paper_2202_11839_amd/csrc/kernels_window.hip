@@ -1,5 +1,5 @@
 // Multipoles of the window's auto-correlation, Q_l(r) (Sec. III.B, eqs.
-// windowQ and windowQ_ell, end-point line of sight).
+// windowQ and windowQ_ell, end-point line of sight), on z-blocked meshes.
 //
 // With the real harmonics h_a of degree l (the same ones the estimator
 // uses), L_l(rhat . xhat) = sum_a kappa_a h_a(rhat) h_a(xhat), so
@@ -28,6 +28,14 @@ using dev::V2;
 
 constexpr int kWinThreads = 256;
 
+// mode (x, y, z) at position i of a z-blocked mesh
+__device__ __forceinline__ void zb_coords(int64_t i, int N, int& x, int& y, int& z) {
+  const int64_t g = i >> 3;
+  x = static_cast<int>(g % N);
+  y = static_cast<int>((g / N) % N);
+  z = static_cast<int>(g / (static_cast<int64_t>(N) * N)) * kZb + static_cast<int>(i & 7);
+}
+
 // the transform of field a at mode (ix, iy, iz) from its packed interlaced copies
 template <typename T>
 __device__ __forceinline__ typename V2<T>::type field_at(const typename V2<T>::type* __restrict__ P, int N,
@@ -53,8 +61,9 @@ __global__ void __launch_bounds__(kWinThreads) window_product_kernel(WinArgs a, 
   const int64_t n3 = static_cast<int64_t>(N) * N * N;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n3;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int ix = static_cast<int>(i % N), iy = static_cast<int>((i / N) % N), iz = static_cast<int>(i / (static_cast<int64_t>(N) * N));
-    const int64_t m = ((N - ix) & mask) + static_cast<int64_t>(N) * (((N - iy) & mask) + static_cast<int64_t>(N) * ((N - iz) & mask));
+    int ix, iy, iz;
+    zb_coords(i, N, ix, iy, iz);
+    const int64_t m = zb_index((N - ix) & mask, (N - iy) & mask, (N - iz) & mask, N);
     const int nsum = sgn_mode(ix, N) + sgn_mode(iy, N) + sgn_mode(iz, N);
     const T2 ph = a.interlace ? phase[nsum + 3 * N / 2] : T2{1, 0};
     const T2 F = field_at<T>(P, N, i, m, a.interlace, ph, invw[ix] * invw[iy] * invw[iz]);
@@ -123,8 +132,9 @@ __global__ void __launch_bounds__(kWinThreads) window_bin_kernel(WinArgs a, cons
   };
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n3;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int nx = sgn_mode(static_cast<int>(i % N), N), ny = sgn_mode(static_cast<int>((i / N) % N), N),
-              nz = sgn_mode(static_cast<int>(i / (static_cast<int64_t>(N) * N)), N);
+    int ix, iy, iz;
+    zb_coords(i, N, ix, iy, iz);
+    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N), nz = sgn_mode(iz, N);
     const int q = nx * nx + ny * ny + nz * nz;
     const int b = dev::shell_of(q, thr, nb, inv_dn);
     if (b < 0) continue;

@@ -102,6 +102,18 @@ struct Geometry {
   double box;
 };
 
+// ---- mesh layouts ----
+// The public entry points take meshes in the plain order x + N (y + N z).
+// The estimator's own meshes (deposits, transforms, bases) are z-blocked:
+// node or mode (x, y, z) sits at ((z/8 N + y) N + x) 8 + z%8, so the 8 z of
+// one (x, y) are contiguous and so are those groups for consecutive x.  Every
+// pass of the 3D transform then reads and writes runs of 8 z-values x the
+// lines it owns, and a z-column touches N/8 memory pages instead of N.
+constexpr int kZb = 8;
+__host__ __device__ inline int64_t zb_index(int x, int y, int z, int N) {
+  return ((static_cast<int64_t>(z >> 3) * N + y) * N + x) * kZb + (z & 7);
+}
+
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
@@ -146,7 +158,7 @@ inline size_t footprint_bytes(int N) {
 hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st);
 
 // Deposits nf fields of one object set in one pass and writes every node of
-// each output mesh (no clearing needed).  With tile_flags (the footprint's
+// each output mesh (no clearing needed), z-blocked or (zblocked = false) plain.  With tile_flags (the footprint's
 // cube flags) the tiles that are not flagged are skipped and left unwritten.  Real fields (complex_fields = 0,
 // nf <= kGatherMaxReal): mesh q holds field q packed (grid -> real part,
 // interlaced grid -> imaginary part).  Complex fields (nf <= kGatherMaxComplex):
@@ -156,8 +168,10 @@ constexpr int kGatherMaxReal = 4;
 constexpr int kGatherMaxComplex = 2;
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
-                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, hipStream_t st);
+                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
+                         hipStream_t st);
 
+// plain-layout 3D transform (the public entry point)
 template <typename T>
 hipError_t launch_fft3d(void* mesh, int N, const void* twiddles, hipStream_t st);
 // Pruning of the 3D transform of a field with a known footprint, keeping only
@@ -180,6 +194,14 @@ hipError_t launch_fft_axis(void* mesh, int N, const void* twiddles, int axis, co
                            int lines);
 int fft_default_lines(int N, bool fp64, int axis);
 bool fft_lines_supported(int N, bool fp64, int axis, int lines);
+// The same passes on a z-blocked mesh.  lines per workgroup, 8 or 16 (0 =
+// zb_default_lines): x pass, 8 z-values of 1 or 2 rows y; y pass, 8 z-values
+// of 1 or 2 columns x; z pass, 8 or 16 columns x of one row y.
+template <typename T>
+hipError_t launch_fft_axis_zb(void* mesh, int N, const void* twiddles, int axis, const FftPrune& pr, hipStream_t st,
+                              int lines);
+int zb_default_lines(int N, bool fp64, int axis);
+bool zb_lines_supported(int N, bool fp64, int axis, int lines);
 
 // Binning.  Tables: twiddles (N complex, exp(-2 pi i m/N)), phase (3N+1
 // complex, exp(-i pi m/N) for m = -3N/2..3N/2), invw (N reals, 1/W_1(n)).
@@ -194,8 +216,9 @@ struct BinArgs {
   double* partial;         // column-major [width][nblocks]
   int nblocks;
 };
-// The binning kernels read the transformed fields only at modes inside the
-// last shell, |n|^2 < T_nb, and the base kernels write the base only there.
+// The binning kernels read the transformed (z-blocked) fields only at modes
+// inside the last shell, |n|^2 < T_nb, and the base kernels write the base
+// only there.
 int bin_blocks(int N);            // default workgroups of the shell-sum kernels
 constexpr int kMaxBinBlocks = 8192;
 template <typename T>
@@ -209,8 +232,8 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, c
 template <typename T>
 hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
                          hipStream_t st);
-// Window multipoles (kernels_window.hip).  Shells of the separation r in
-// cells: T_b <= |n|^2 < T_{b+1} (thr on the device).
+// Window multipoles (kernels_window.hip), on z-blocked meshes.  Shells of the
+// separation r in cells: T_b <= |n|^2 < T_{b+1} (thr on the device).
 struct WinArgs {
   int N, nb, interlace, n_rows;  // n_rows = multipoles + 2 (counts, |n| sums)
   const int64_t* thr;

@@ -100,28 +100,30 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 4, "fft_cols_yz": 16, "bin_blocks": 2048, "gather_density": 4, "gather_shape": 2}
-    for bad in (dict(fft_rows_x=3), dict(fft_rows_x=64), dict(fft_cols_yz=32), dict(bin_blocks=10),
-                dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=3)):
+    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 2048, "gather_density": 4, "gather_shape": 2}
+    for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
+                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=3)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
     plan.set_tuning(fft_cols_yz=8, gather_density=2)
     assert plan.tuning()["fft_cols_yz"] == 8 and plan.tuning()["gather_density"] == 2
-    # FP64: the default strided block holds half as many columns; more than fit one CU's LDS are refused
+    # FP64: the default strided block holds one z-group of one column; more
+    # lines than 1024 threads or one CU's LDS allow are refused
     p64 = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f64", lmax=4, n_kbins=50)
-    assert p64.tuning()["fft_cols_yz"] == 4
-    p64.set_tuning(fft_cols_yz=8)
+    assert p64.tuning()["fft_cols_yz"] == 8 and p64.tuning()["fft_rows_x"] == 8
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_cols_yz=16)
+    with pytest.raises(pkg.LppError):
+        p64.set_tuning(fft_rows_x=16)
     cache = tmp_path / "tune.jsonl"
     cache.write_text('{"key": "N256_f32_p3_il1", "fft_rows_x": 8, "fft_cols_yz": 8, "bin_blocks": 1024, '
                      '"gather_density": 3, "gather_shape": 1}\n'
-                     '{"key": "N512_f32_p3_il1", "fft_rows_x": 8, "fft_cols_yz": 4, "bin_blocks": 4096, '
+                     '{"key": "N512_f32_p3_il1", "fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, '
                      '"gather_density": 2, "gather_shape": 1}\n')
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
-    assert tuned.tuning() == {"fft_rows_x": 8, "fft_cols_yz": 4, "bin_blocks": 4096, "gather_density": 2,
+    assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, "gather_density": 2,
                               "gather_shape": 1}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
