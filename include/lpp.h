@@ -279,7 +279,7 @@ typedef struct {
   int32_t fft_cols_yz;     /* y and z passes: lines per workgroup, 8 or 16                  */
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
   int32_t gather_density;  /* density fields per deposit pass, 1 .. 4                       */
-  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 2                         */
+  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64: 1 .. 2)          */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

@@ -129,9 +129,18 @@ bool need_shape(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_GD | LPP_PL
 int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size()); }
 
 // Work meshes: one gather pass deposits up to kGatherMaxReal density fields
-// (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per grid).
-constexpr int kWork = 4;
+// (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per
+// grid): kWork in FP32, kWorkF64 in FP64 (at most kGatherMaxComplexF64 shape
+// fields per pass there).
+constexpr int kWork = 8;
+constexpr int kWorkF64 = 4;
 static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
+static_assert(kWorkF64 >= kGatherMaxReal && kWorkF64 >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+int work_meshes(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? kWorkF64 : kWork; }
+int max_shape_fields(const lpp_plan_s* p) {
+  return p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex;
+}
+lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
 // Workspace layout (offsets in bytes), computed for capacities (ng, nr).
 struct Layout {
   size_t mesh[2];  // Bd, Bg
@@ -164,7 +173,7 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   (void)il;
   L.mesh[0] = take(M);
   L.mesh[1] = take(M);
-  for (int i = 0; i < kWork; ++i) L.work[i] = take(M);
+  for (int i = 0; i < work_meshes(p); ++i) L.work[i] = take(M);
   const size_t nd = static_cast<size_t>(ng + nr);
   const size_t gg = static_cast<size_t>(ng);
   L.key_d = take(4 * nd);
@@ -557,8 +566,8 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   const int copies = il ? 2 : 1;
   auto run_set = [&](const std::vector<Job>& jobs, const GObjSet<T>& set, const uint32_t* starts, int cplx,
                      const Footprint& fp) -> lpp_status {
-    const int per = cplx ? (p->tune.gather_shape > 0 ? p->tune.gather_shape : kGatherMaxComplex)
-                         : (p->tune.gather_density > 0 ? p->tune.gather_density : kGatherMaxReal);
+    const lpp_tuning tn = resolved_tuning(p);
+    const int per = cplx ? tn.gather_shape : tn.gather_density;
     for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
       const int nf = static_cast<int>(std::min<size_t>(per, jobs.size() - j0));
       FieldSpec specs[kWork];
@@ -782,7 +791,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
   void* B0 = wsp(p, L.mesh[0]);
   void* Zc = wsp(p, L.mesh[1]);
   void* W[kWork];
-  for (int i = 0; i < kWork; ++i) W[i] = wsp(p, L.work[i]);
+  for (int i = 0; i < kWork; ++i) W[i] = L.work[i] ? wsp(p, L.work[i]) : nullptr;
   // the fields: kappa_a h_a(xhat) for every real harmonic of degree l = 0, 2, ..., lmax
   struct WField {
     FieldSpec spec;
@@ -984,7 +993,7 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   if (t.fft_cols_yz <= 0) t.fft_cols_yz = zb_default_lines(N, f64, 1);
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
   if (t.gather_density <= 0) t.gather_density = kGatherMaxReal;
-  if (t.gather_shape <= 0) t.gather_shape = kGatherMaxComplex;
+  if (t.gather_shape <= 0) t.gather_shape = max_shape_fields(p);
   return t;
 }
 
@@ -995,7 +1004,7 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   if (t.fft_cols_yz != 0 && !zb_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
   if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
   if (t.gather_density < 0 || t.gather_density > kGatherMaxReal) return false;
-  if (t.gather_shape < 0 || t.gather_shape > kGatherMaxComplex) return false;
+  if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
   return true;
 }
 
@@ -1128,7 +1137,7 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 3, 4}, {LPP_STAGE_DEPOSIT});
-  if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2}, {LPP_STAGE_DEPOSIT});
+  if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;
   std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);
   std::copy(saved_l, saved_l + LPP_N_STAGES, p->prof_launches);

@@ -668,8 +668,14 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
     case 2:
       return dispatch<T, 2, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
     default:
-      return hipErrorInvalidValue;
+      break;
   }
+  if constexpr (sizeof(T) == 4) {
+    static_assert(kGatherMaxComplex == 4 && kGatherMaxComplexF64 == 2, "complex passes of 3 and 4 fields in FP32");
+    if (nf == 3) return dispatch<T, 2, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    if (nf == 4) return dispatch<T, 2, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st) {

@@ -355,7 +355,9 @@ def test_tuning_variants_match_oracle(lpp, prec):
     tol = 1e-9 if prec == "f64" else 1e-4
     variants = [dict(fft_rows_x=16), dict(fft_cols_yz=8), dict(fft_cols_yz=16),
                 dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
-                dict(gather_shape=1)]
+                dict(gather_shape=1), dict(gather_shape=2)]
+    if prec == "f32":
+        variants += [dict(gather_shape=3)]
     base = plan.tuning()
     for v in variants:
         plan.set_tuning(**{**base, **v})

@@ -100,9 +100,9 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 2048, "gather_density": 4, "gather_shape": 2}
+    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 2048, "gather_density": 4, "gather_shape": 4}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
-                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=3)):
+                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=5)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
@@ -116,6 +116,10 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
         p64.set_tuning(fft_cols_yz=16)
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_rows_x=16)
+    # FP64: at most two shape fields per deposit pass
+    assert p64.tuning()["gather_shape"] == 2
+    with pytest.raises(pkg.LppError):
+        p64.set_tuning(gather_shape=3)
     cache = tmp_path / "tune.jsonl"
     cache.write_text('{"key": "N256_f32_p3_il1", "fft_rows_x": 8, "fft_cols_yz": 8, "bin_blocks": 1024, '
                      '"gather_density": 3, "gather_shape": 1}\n'
