@@ -1135,7 +1135,7 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   };
   s = search(&lpp_tuning::fft_rows_x, {8, 16}, {LPP_STAGE_FFT_X});
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {8, 16}, {LPP_STAGE_FFT_YZ});
-  if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096}, {LPP_STAGE_BIN});
+  if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 3, 4}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;

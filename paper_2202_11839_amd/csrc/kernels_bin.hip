@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const doub
 int bin_blocks(int N) {
   const int64_t runs = static_cast<int64_t>(N) * N * N / kRun;
   int64_t want = (runs + kBinThreads - 1) / kBinThreads;
-  if (want > 2048) want = 2048;
+  if (want > 4096) want = 4096;
   if (want < 1) want = 1;
   return static_cast<int>(want);
 }
