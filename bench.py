@@ -104,7 +104,7 @@ def committed_traffic():
     workload, from the committed rocprofv3 summary, if it was taken on the
     current kernel source (its SHA-256 is recorded in the summary)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fft_axis_strided_c2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "fft_zb_strided_c2_traffic.json")
     src = os.path.join(ROOT, "paper_2202_11839_amd", "csrc", "kernels_fft.hip")
     try:
         with open(path) as f:
@@ -209,7 +209,7 @@ def emulator_c5(lpp, torch, wl, ran, gal, rdev, epochs):
     t_plain2k = time.perf_counter() - t0
     emu = Emulator(EMU_RANGES, n_k=30, max_batch=4096, seed=1)
     t0 = time.perf_counter()
-    loss = emu.fit(P[:20000], Y[:20000], nbar, sig, epochs=epochs, batch=512, lr0=3e-3, lr1=1e-5, seed=2)
+    loss = emu.fit(P[:20000], Y[:20000], nbar, sig, epochs=epochs, batch=128, lr0=1e-3, lr1=1e-5, seed=2)
     torch.cuda.synchronize()
     out["train_s"] = round(time.perf_counter() - t0, 2)
     out["train_loss"] = loss
