@@ -65,13 +65,14 @@ def time_steps(plan, gdev, rdev, steps, warmup, torch, profile=False):
 def launches_per_set(res):
     """Transforms per estimate at l <= 4 with interlacing: the density set has
     15 fields (one packed mesh each), the shape set 38 (two interlaced meshes
-    each): 1 + 5 + 9 plus-type, 5 + 9 cross, 9 minus."""
+    each): 1 + 5 + 9 plus-type, 5 + 9 cross, 9 minus.  Every transform runs
+    one y pass and one z pass of the strided kernel."""
     assert len(res["series"]) == 15, res["series"]
     return 15, 76
 
 
 def strided_pass_bytes(pos, wl):
-    """HBM bytes that the y pass and the z pass of one transform must move,
+    """HBM bytes (y, z) that the y pass and the z pass of one transform move,
     given the footprint of the object set (complex float32 nodes):
       y pass: read every flagged node row, write the (kx, ky) inside the last
               shell in every flagged plane;
@@ -96,24 +97,27 @@ def strided_pass_bytes(pos, wl):
     sphere = int((m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2 < qmax).sum())
     y_bytes = 8 * (int(row.sum()) * n + planes * circle)
     z_bytes = 8 * (circle * planes + sphere)
-    return y_bytes + z_bytes
+    return y_bytes, z_bytes
 
 
 def committed_traffic():
     """Counter-measured HBM bytes per launch of the strided FFT pass at the C2
     workload, from the committed rocprofv3 summary, if it was taken on the
-    current kernel source (its SHA-256 is recorded in the summary)."""
+    current sources (the SHA-256 of the kernel source and of the host code
+    that sequences its launches are recorded in the summary)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fft_zb_strided_c2_traffic.json")
-    src = os.path.join(ROOT, "paper_2202_11839_amd", "csrc", "kernels_fft.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digests = rec.get("sources_sha256") or {}
+        if not digests:
+            return None
+        for name, want in digests.items():
+            with open(os.path.join(ROOT, "paper_2202_11839_amd", "csrc", name), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
     except OSError:
-        return None
-    if rec.get("kernels_fft_sha256") != digest:
         return None
     return rec.get("bytes_per_launch")
 
@@ -357,9 +361,11 @@ def main():
     total_ms, launches = stages["fft_yz"]
     avg_ms = total_ms / launches
     nd_mesh, ns_mesh = launches_per_set(res)
-    by_d = strided_pass_bytes(np.concatenate([gal.pos(), ran.pos()]), wl)
-    by_s = strided_pass_bytes(gal.pos(), wl)
-    alg_bytes = (nd_mesh * by_d + ns_mesh * by_s) / (2 * (nd_mesh + ns_mesh))  # per launch
+    yd, zd = strided_pass_bytes(np.concatenate([gal.pos(), ran.pos()]), wl)
+    ys, zs = strided_pass_bytes(gal.pos(), wl)
+    n_strided = 2 * (nd_mesh + ns_mesh)
+    assert launches == n_strided * args.steps, (launches, n_strided)
+    alg_bytes = (nd_mesh * (yd + zd) + ns_mesh * (ys + zs)) / n_strided  # per launch
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = committed_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

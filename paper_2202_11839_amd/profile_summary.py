@@ -10,7 +10,8 @@
     Both counters are scaled by what they read for a plain device copy of
     known size (``bench.py --copy-calibration``: 1 GiB read and 1 GiB written
     per ``__amd_rocclr_copyBuffer`` launch), and the SHA-256 of the kernel
-    source is recorded so that a stale figure can be recognised.  Without
+    source and of the host code that sequences its launches is recorded, so
+    that a stale figure can be recognised.  Without
     --kernel: a table of read and written bytes per launch of every kernel.
 """
 from __future__ import annotations
@@ -25,6 +26,9 @@ import statistics
 
 COPY_BYTES = 1 << 30  # bytes read and bytes written by one calibration copy
 HERE = os.path.dirname(os.path.abspath(__file__))
+# a traffic record holds for these sources only: the strided-pass kernel and
+# the host code that decides which passes run
+TRAFFIC_SOURCES = ["csrc/kernels_fft.hip", "csrc/api.hip"]
 
 
 def _short(name: str) -> str:
@@ -71,7 +75,9 @@ def main() -> None:
     t.add_argument("copy_fetch_db")
     t.add_argument("copy_write_db")
     t.add_argument("--kernel", default="")
-    t.add_argument("--source", default=os.path.join(HERE, "csrc", "kernels_fft.hip"))
+    t.add_argument("--source", action="append", default=None,
+                   help="source files whose SHA-256 the record keeps (default: the FFT kernels and the "
+                        "host code that sets their launch sequence)")
     t.add_argument("--command", default="")
     args = ap.parse_args()
 
@@ -111,13 +117,16 @@ def main() -> None:
     write = [v for n, vs in counter(args.write_db, "WRITE_SIZE").items() if args.kernel in n for v in vs]
     if not fetch or not write:
         raise SystemExit(f"no launches of {args.kernel!r}")
-    with open(args.source, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
+    sources = args.source or TRAFFIC_SOURCES
+    digests = {}
+    for src in sources:
+        with open(os.path.join(HERE, src) if not os.path.isabs(src) else src, "rb") as f:
+            digests[os.path.basename(src)] = hashlib.sha256(f.read()).hexdigest()
     rd, wr = statistics.mean(fetch) * fs, statistics.mean(write) * ws
     rec = {"kernel": args.kernel, "launches": len(fetch), "read_bytes_per_launch": round(rd),
            "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
            "fetch_scale_bytes_per_unit": fs, "write_scale_bytes_per_unit": ws,
-           "kernels_fft_sha256": digest, "command": args.command}
+           "sources_sha256": digests, "command": args.command}
     print(json.dumps(rec, indent=1))
 
 
