@@ -1104,8 +1104,6 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   if (s != LPP_OK) return s;
   p->prof_on = true;
   lpp_tuning best = resolved_tuning(p);
-  const int N = p->cfg.mesh_n;
-  const bool f64 = p->cfg.precision == LPP_F64;
   auto measure = [&](const lpp_tuning& t, std::initializer_list<int> stages, double& ms) -> lpp_status {
     p->tune = t;
     for (int i = 0; i < LPP_N_STAGES; ++i) p->prof_ms[i] = 0.0;

@@ -137,7 +137,6 @@ template <typename T, int N>
 __device__ __forceinline__ void fft_column_regs(const typename V2<T>::type* __restrict__ tw,
                                                 typename V2<T>::type* sm, int col, int t, typename V2<T>::type* v,
                                                 int swz = -1) {
-  using T2 = typename V2<T>::type;
   constexpr int TL = N / 8;
   constexpr int A8 = n_radix8(N);
   constexpr int TR = tail_radix(N);

@@ -58,7 +58,6 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
   u += 0x7FFFu + ((u >> 16) & 1u);
   return static_cast<uint16_t>(u >> 16);
 }
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 enum Epi { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DELTA = 2, EPI_PLAIN = 3 };
