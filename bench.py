@@ -39,9 +39,15 @@ def to_device(cat, torch):
     return Catalog(f(cat.x), f(cat.y), f(cat.z), f(cat.w), f(cat.nbar), f(cat.g1), f(cat.g2))
 
 
+SERIAL = 0  # --serial: deposits and transforms one after the other on one stream
+
+
 def plan_for(lpp, wl, precision):
-    return lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
                     interlacing=wl["interlacing"], precision=precision, lmax=wl["lmax"], n_kbins=wl["n_kbins"])
+    if SERIAL:
+        plan.set_tuning(serial=1)
+    return plan
 
 
 def time_steps(plan, gdev, rdev, steps, warmup, torch, profile=False):
@@ -314,10 +320,14 @@ def main():
                     help="1: window multipoles of the 512^3 randoms, the plain template path over the 22,000-point "
                          "design and the emulator trained on 20,000 of them (accuracy on the other 2,000, speedup)")
     ap.add_argument("--emu-epochs", type=int, default=600)
+    ap.add_argument("--serial", type=int, default=0,
+                    help="1: run each estimate's deposits and transforms on one stream (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
+    global SERIAL
+    SERIAL = args.serial
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -350,10 +360,15 @@ def main():
     torch.cuda.synchronize()
 
     plan = plan_for(lpp, wl, "f32")
-    dt, res, prof = time_steps(plan, gdev, rdev, args.steps, args.warmup, torch, profile=True)
+    dt, res, _ = time_steps(plan, gdev, rdev, args.steps, args.warmup, torch)
     ms = 1e3 * dt / args.steps
     value = args.steps / dt
     log(f"fp32: {ms:.1f} ms/estimate, {value:.3f} estimates/s")
+    # stage times and the strided pass's launch time from a profiled run
+    # (profiling runs the deposits and the transforms one after the other, so
+    # that every kernel's time is its own)
+    psteps = max(1, min(args.steps, 2))
+    _, _, prof = time_steps(plan, gdev, rdev, psteps, 0, torch, profile=True)
 
     # roofline of the dominant kernel: the strided (y and z) passes of the 3D transforms
     n = wl["mesh"]
@@ -364,7 +379,7 @@ def main():
     yd, zd = strided_pass_bytes(np.concatenate([gal.pos(), ran.pos()]), wl)
     ys, zs = strided_pass_bytes(gal.pos(), wl)
     n_strided = 2 * (nd_mesh + ns_mesh)
-    assert launches == n_strided * args.steps, (launches, n_strided)
+    assert launches == n_strided * psteps, (launches, n_strided)
     alg_bytes = (nd_mesh * (yd + zd) + ns_mesh * (ys + zs)) / n_strided  # per launch
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = committed_traffic()
@@ -373,7 +388,8 @@ def main():
             "traffic": None if traffic is None else round(traffic),
             "kernel": "fft_zb_kernel<float, %d, %d, false> (y and z passes)" % (n, plan.tuning()["fft_cols_yz"]),
             "alg_bytes_per_launch": round(alg_bytes), "avg_launch_ms": round(avg_ms, 4), "launches": launches,
-            "stage_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()}}
+            "stage_ms_per_step": {k: round(v[0] / psteps, 3) for k, v in prof.items()},
+            "stages_serial_ms_per_step": round(sum(v[0] for v in prof.values()) / psteps, 2)}
 
     extra = {}
     if args.fp64_steps > 0:

@@ -280,6 +280,10 @@ typedef struct {
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
   int32_t gather_density;  /* density fields per deposit pass, 1 .. 4                       */
   int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64: 1 .. 2)          */
+  int32_t serial;          /* 1: deposits and transforms on the plan's stream one after the
+                              other; 0: the next pass's deposit runs on a second stream of the
+                              plan while the current pass is transformed (profiling with
+                              lpp_set_profiling always runs them one after the other)      */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

@@ -79,9 +79,29 @@ struct lpp_plan_s {
   size_t d_batch_cap = 0;     // doubles
   int64_t graph_captures = 0, graph_replays = 0;
   lpp_tuning tune{};  // 0 = default
+  // the deposit of the next gather pass runs on a second stream while the
+  // transforms and shell sums of the current one run on the plan's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_dep[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
 };
 
 namespace {
+
+// the second stream and the events that order the two streams (created once)
+hipError_t ensure_aux(lpp_plan_s* p) {
+  if (p->aux) return hipSuccess;
+  hipError_t e = hipSuccess;
+  auto ev = [&](hipEvent_t* x) {
+    if (e == hipSuccess) e = hipEventCreateWithFlags(x, hipEventDisableTiming);
+  };
+  ev(&p->ev_fork);
+  for (int i = 0; i < 2; ++i) {
+    ev(&p->ev_dep[i]);
+    ev(&p->ev_done[i]);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking);
+  return e;
+}
 
 hipError_t prof_begin(lpp_plan_s* p) {
   if (!p->prof_on) return hipSuccess;
@@ -144,7 +164,7 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defa
 // Workspace layout (offsets in bytes), computed for capacities (ng, nr).
 struct Layout {
   size_t mesh[2];  // Bd, Bg
-  size_t work[kWork];
+  size_t work[2][kWork];  // two sets: one pass deposits into a set while the other is transformed
   size_t key_d, fx_d, fy_d, fz_d, wr_d;
   size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
   size_t cell_of, rank, starts_d, starts_g, bsum;
@@ -173,7 +193,8 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   (void)il;
   L.mesh[0] = take(M);
   L.mesh[1] = take(M);
-  for (int i = 0; i < work_meshes(p); ++i) L.work[i] = take(M);
+  for (int s = 0; s < 2; ++s)
+    for (int i = 0; i < work_meshes(p); ++i) L.work[s][i] = take(M);
   const size_t nd = static_cast<size_t>(ng + nr);
   const size_t gg = static_cast<size_t>(ng);
   L.key_d = take(4 * nd);
@@ -485,9 +506,17 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   const int N = cfg.mesh_n, nb = cfg.n_kbins;
   void* Bd = wsp(p, L.mesh[0]);
   void* Bg = wsp(p, L.mesh[1]);
-  void* W[kWork];
-  for (int i = 0; i < kWork; ++i) W[i] = L.work[i] ? wsp(p, L.work[i]) : nullptr;
+  void* Wset[2][kWork];
+  for (int s2 = 0; s2 < 2; ++s2)
+    for (int i = 0; i < kWork; ++i) Wset[s2][i] = L.work[s2][i] ? wsp(p, L.work[s2][i]) : nullptr;
   const bool il = cfg.interlacing != 0;
+  // Gather pass j deposits into work set j & 1 on the deposit stream gs; the
+  // transforms and shell sums of pass j run on st once it is deposited, and
+  // the deposit of pass j + 2 waits until they are done with the set.  With
+  // profiling on (or serial tuning) both run on st, one after the other.
+  const bool overlap = p->aux != nullptr && !p->prof_on && p->tune.serial == 0;
+  const hipStream_t gs = overlap ? p->aux : st;
+  int pass = 0;
 
   GObjSet<T> setd = objset<T>(p, L, false, rg.n + rr.n);
   GObjSet<T> setg = objset<T>(p, L, true, rg.n);
@@ -533,9 +562,9 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   double* base_rows[2] = {acc + static_cast<size_t>(2) * nb * na, acc + static_cast<size_t>(2) * nb * na + 4 * nb};
   // kernel groups, each timed as one stage when profiling is on
   auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
-                     const Footprint& fp) -> hipError_t {
+                     const Footprint& fp, void* const* W) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, st);
+    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
@@ -568,11 +597,17 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
                      const Footprint& fp) -> lpp_status {
     const lpp_tuning tn = resolved_tuning(p);
     const int per = cplx ? tn.gather_shape : tn.gather_density;
-    for (size_t j0 = 0; j0 < jobs.size(); j0 += per) {
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += per, ++pass) {
       const int nf = static_cast<int>(std::min<size_t>(per, jobs.size() - j0));
       FieldSpec specs[kWork];
       for (int q = 0; q < nf; ++q) specs[q] = jobs[j0 + q].spec;
-      LPP_TRY(deposit(set, starts, specs, nf, cplx, fp));
+      void* const* W = Wset[pass & 1];
+      if (overlap && pass >= 2) LPP_TRY(hipStreamWaitEvent(gs, p->ev_done[pass & 1], 0));
+      LPP_TRY(deposit(set, starts, specs, nf, cplx, fp, W));
+      if (overlap) {
+        LPP_TRY(hipEventRecord(p->ev_dep[pass & 1], gs));
+        LPP_TRY(hipStreamWaitEvent(st, p->ev_dep[pass & 1], 0));
+      }
       for (int m = 0; m < nf * (cplx ? copies : 1); ++m) LPP_TRY(fft(W[m], fp));
       for (int q = 0; q < nf; ++q) {
         const Job& jb = jobs[j0 + q];
@@ -601,9 +636,14 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 2 * nb, acc + static_cast<size_t>(2) * nb * jb.series, st));
         LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
       }
+      if (overlap) LPP_TRY(hipEventRecord(p->ev_done[pass & 1], st));
     }
     return LPP_OK;
   };
+  if (overlap) {  // the deposit stream starts after everything enqueued on st so far
+    LPP_TRY(hipEventRecord(p->ev_fork, st));
+    LPP_TRY(hipStreamWaitEvent(gs, p->ev_fork, 0));
+  }
   if ((s = run_set(dens, setd, starts_d, 0, fpd)) != LPP_OK) return s;
   if ((s = run_set(shape, setg, starts_g, 1, fpg)) != LPP_OK) return s;
   return LPP_OK;
@@ -692,6 +732,7 @@ lpp_status run_estimate(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   if (!out || !out->re || !out->im || !out->n_modes || !out->k_eff || !out->k_lo || !out->k_hi) return LPP_E_INVALID;
   if ((s = ensure_tables(p)) != LPP_OK) return s;
   if ((s = ensure_workspace(p, gal->n, ran->n)) != LPP_OK) return s;
+  LPP_TRY(ensure_aux(p));
   const Layout L = layout(p, p->cap_gal, p->cap_ran);
   RawCat rg, rr;
   Scalars sc{};
@@ -791,7 +832,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
   void* B0 = wsp(p, L.mesh[0]);
   void* Zc = wsp(p, L.mesh[1]);
   void* W[kWork];
-  for (int i = 0; i < kWork; ++i) W[i] = L.work[i] ? wsp(p, L.work[i]) : nullptr;
+  for (int i = 0; i < kWork; ++i) W[i] = L.work[0][i] ? wsp(p, L.work[0][i]) : nullptr;
   // the fields: kappa_a h_a(xhat) for every real harmonic of degree l = 0, 2, ..., lmax
   struct WField {
     FieldSpec spec;
@@ -889,6 +930,7 @@ lpp_status run_batch(lpp_plan_s* p, int32_t n, const lpp_catalog* gals, const lp
   if (n == 0) return LPP_OK;
   if ((s = ensure_tables(p)) != LPP_OK) return s;
   if ((s = ensure_workspace(p, mg, mr)) != LPP_OK) return s;
+  LPP_TRY(ensure_aux(p));
   lpp_status first = LPP_OK;
   if (!device) {
     for (int i = 0; i < n; ++i) {
@@ -1005,6 +1047,7 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
   if (t.gather_density < 0 || t.gather_density > kGatherMaxReal) return false;
   if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
+  if (t.serial != 0 && t.serial != 1) return false;
   return true;
 }
 
@@ -1031,6 +1074,7 @@ bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t)
   const size_t j = i == std::string::npos ? i : line.find('"', i + 1);
   if (j == std::string::npos) return false;
   key = line.substr(i + 1, j - i - 1);
+  if (!field("serial", t.serial)) t.serial = 0;  // optional
   return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_yz", t.fft_cols_yz) &&
          field("bin_blocks", t.bin_blocks) && field("gather_density", t.gather_density) &&
          field("gather_shape", t.gather_shape);
@@ -1040,8 +1084,8 @@ std::string tuning_line(const std::string& key, const lpp_tuning& t) {
   char b[256];
   std::snprintf(b, sizeof b,
                 "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_yz\": %d, \"bin_blocks\": %d, "
-                "\"gather_density\": %d, \"gather_shape\": %d}",
-                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape);
+                "\"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d}",
+                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape, t.serial);
   return b;
 }
 
@@ -1230,6 +1274,9 @@ lpp_status lpp_plan_destroy(lpp_plan p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
+  for (hipEvent_t e : {p->ev_fork, p->ev_dep[0], p->ev_dep[1], p->ev_done[0], p->ev_done[1]})
+    if (e) (void)hipEventDestroy(e);
   if (p->d_batch) (void)hipFree(p->d_batch);
   delete p;
   return LPP_OK;

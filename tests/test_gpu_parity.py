@@ -355,13 +355,33 @@ def test_tuning_variants_match_oracle(lpp, prec):
     tol = 1e-9 if prec == "f64" else 1e-4
     variants = [dict(fft_rows_x=16), dict(fft_cols_yz=8), dict(fft_cols_yz=16),
                 dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
-                dict(gather_shape=1), dict(gather_shape=2)]
+                dict(gather_shape=1), dict(gather_shape=2), dict(serial=1)]
     if prec == "f32":
         variants += [dict(gather_shape=3)]
     base = plan.tuning()
     for v in variants:
         plan.set_tuning(**{**base, **v})
         _compare(plan.estimate(g, r), ref, tol)
+
+
+def test_overlapped_deposits_match_serial_order(lpp):
+    """The default pipeline deposits the next gather pass on a second stream
+    while the current pass is transformed (two work-mesh sets); the result is
+    the serial pipeline's to FP64 rounding of the shell sums, for several
+    estimates in a row on the same plan."""
+    g, r, kw, ref = _footprint_case("wedge")
+    plan = lpp.Plan(precision="f64", **kw)
+    base = plan.tuning()
+    plan.set_tuning(**{**base, "serial": 1})
+    serial = plan.estimate(g, r)
+    plan.set_tuning(**{**base, "serial": 0})
+    for _ in range(3):
+        over = plan.estimate(g, r)
+        assert list(over["n_modes"]) == list(serial["n_modes"])
+        for part in ("re", "im"):
+            a, b = np.asarray(over[part]), np.asarray(serial[part])
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+    _compare(over, ref, 1e-9)
 
 
 def test_autotune_writes_cache_and_keeps_parity(lpp, tmp_path):

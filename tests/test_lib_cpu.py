@@ -100,9 +100,11 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 4096, "gather_density": 4, "gather_shape": 4}
+    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 4096, "gather_density": 4, "gather_shape": 4,
+                 "serial": 0}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
-                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=5)):
+                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=5),
+                dict(serial=2)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
@@ -128,7 +130,7 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, "gather_density": 2,
-                              "gather_shape": 1}
+                              "gather_shape": 1, "serial": 0}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
 
