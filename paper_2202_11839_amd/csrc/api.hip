@@ -155,8 +155,11 @@ int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size(
 constexpr int kWork = 8;
 constexpr int kWorkF64 = 4;
 static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
-static_assert(kWorkF64 >= kGatherMaxReal && kWorkF64 >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+static_assert(kWorkF64 >= kGatherMaxRealF64 && kWorkF64 >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
 int work_meshes(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? kWorkF64 : kWork; }
+int max_density_fields(const lpp_plan_s* p) {
+  return p->cfg.precision == LPP_F64 ? kGatherMaxRealF64 : kGatherMaxReal;
+}
 int max_shape_fields(const lpp_plan_s* p) {
   return p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex;
 }
@@ -850,7 +853,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
       e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz);
     return e;
   };
-  const int per = p->tune.gather_density > 0 ? p->tune.gather_density : kGatherMaxReal;
+  const int per = resolved_tuning(p).gather_density;  // one packed mesh each, in work set 0
   int pending = -1;  // field waiting in slot 0 of Zc
   bool counted = false;
   auto bin_pair = [&](int fa, int fb) -> hipError_t {
@@ -1034,7 +1037,7 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   if (t.fft_rows_x <= 0) t.fft_rows_x = zb_default_lines(N, f64, 0);
   if (t.fft_cols_yz <= 0) t.fft_cols_yz = zb_default_lines(N, f64, 1);
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
-  if (t.gather_density <= 0) t.gather_density = kGatherMaxReal;
+  if (t.gather_density <= 0) t.gather_density = max_density_fields(p);
   if (t.gather_shape <= 0) t.gather_shape = max_shape_fields(p);
   return t;
 }
@@ -1045,7 +1048,7 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   if (t.fft_rows_x != 0 && !zb_lines_supported(N, f64, 0, t.fft_rows_x)) return false;
   if (t.fft_cols_yz != 0 && !zb_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
   if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
-  if (t.gather_density < 0 || t.gather_density > kGatherMaxReal) return false;
+  if (t.gather_density < 0 || t.gather_density > max_density_fields(p)) return false;
   if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
   if (t.serial != 0 && t.serial != 1) return false;
   return true;
@@ -1178,7 +1181,7 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   s = search(&lpp_tuning::fft_rows_x, {8, 16}, {LPP_STAGE_FFT_X});
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
-  if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 3, 4}, {LPP_STAGE_DEPOSIT});
+  if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;
   std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);

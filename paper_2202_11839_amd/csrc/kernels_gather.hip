@@ -659,8 +659,19 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
       case 4:
         return dispatch<T, 1, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       default:
-        return hipErrorInvalidValue;
+        break;
     }
+    if constexpr (sizeof(T) == 4) {
+      static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 4, "real passes of 5 to 8 fields in FP32");
+      switch (nf) {
+        case 5: return dispatch<T, 1, 5>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 6: return dispatch<T, 1, 6>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 7: return dispatch<T, 1, 7>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 8: return dispatch<T, 1, 8>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        default: break;
+      }
+    }
+    return hipErrorInvalidValue;
   }
   switch (nf) {
     case 1:

@@ -160,12 +160,14 @@ hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hip
 // Deposits nf fields of one object set in one pass and writes every node of
 // each output mesh (no clearing needed), z-blocked or (zblocked = false) plain.  With tile_flags (the footprint's
 // cube flags) the tiles that are not flagged are skipped and left unwritten.  Real fields (complex_fields = 0,
-// nf <= kGatherMaxReal): mesh q holds field q packed (grid -> real part,
-// interlaced grid -> imaginary part).  Complex fields (nf <= kGatherMaxComplex,
-// kGatherMaxComplexF64 in FP64, whose accumulators take twice the registers):
+// nf <= kGatherMaxReal, kGatherMaxRealF64 in FP64): mesh q holds field q
+// packed (grid -> real part, interlaced grid -> imaginary part).  Complex
+// fields (nf <= kGatherMaxComplex, kGatherMaxComplexF64 in FP64, whose
+// accumulators take twice the registers):
 // with interlacing mesh 2q holds field q on the grid and mesh 2q+1 on the
 // interlaced grid, without it mesh q holds field q.
-constexpr int kGatherMaxReal = 4;
+constexpr int kGatherMaxReal = 8;
+constexpr int kGatherMaxRealF64 = 4;
 constexpr int kGatherMaxComplex = 4;
 constexpr int kGatherMaxComplexF64 = 2;
 template <typename T>

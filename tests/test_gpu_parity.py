@@ -357,7 +357,7 @@ def test_tuning_variants_match_oracle(lpp, prec):
                 dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
                 dict(gather_shape=1), dict(gather_shape=2), dict(serial=1)]
     if prec == "f32":
-        variants += [dict(gather_shape=3)]
+        variants += [dict(gather_shape=3), dict(gather_density=4), dict(gather_density=6)]
     base = plan.tuning()
     for v in variants:
         plan.set_tuning(**{**base, **v})

@@ -100,10 +100,10 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 4096, "gather_density": 4, "gather_shape": 4,
+    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 4096, "gather_density": 8, "gather_shape": 4,
                  "serial": 0}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
-                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=5), dict(gather_shape=5),
+                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=5),
                 dict(serial=2)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
@@ -118,10 +118,12 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
         p64.set_tuning(fft_cols_yz=16)
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_rows_x=16)
-    # FP64: at most two shape fields per deposit pass
-    assert p64.tuning()["gather_shape"] == 2
+    # FP64: at most four density and two shape fields per deposit pass
+    assert p64.tuning()["gather_shape"] == 2 and p64.tuning()["gather_density"] == 4
     with pytest.raises(pkg.LppError):
         p64.set_tuning(gather_shape=3)
+    with pytest.raises(pkg.LppError):
+        p64.set_tuning(gather_density=5)
     cache = tmp_path / "tune.jsonl"
     cache.write_text('{"key": "N256_f32_p3_il1", "fft_rows_x": 8, "fft_cols_yz": 8, "bin_blocks": 1024, '
                      '"gather_density": 3, "gather_shape": 1}\n'
