@@ -222,7 +222,8 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.sums_partial = take(8 * 8 * static_cast<size_t>(catalog_sum_blocks()));
   L.sums_out = take(8 * 16);
   const int nb = p->cfg.n_kbins;
-  L.bin_partial = take(8 * 4 * static_cast<size_t>(nb) * std::max(bin_blocks(p->cfg.mesh_n), kMaxBinBlocks));
+  L.bin_partial = take(8 * std::max(4, 2 * kBinGroup) * static_cast<size_t>(nb) *
+                       std::max(bin_blocks(p->cfg.mesh_n), kMaxBinBlocks));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
   for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
   L.rthr = take(8 * (kMaxShells + 1));
@@ -612,32 +613,54 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         LPP_TRY(hipStreamWaitEvent(st, p->ev_dep[pass & 1], 0));
       }
       for (int m = 0; m < nf * (cplx ? copies : 1); ++m) LPP_TRY(fft(W[m], fp));
-      for (int q = 0; q < nf; ++q) {
+      // the set's base first (if it is in this pass), then the other fields in
+      // groups of up to kBinGroup that share the base and the kind of product
+      for (int q = 0; q < nf;) {
         const Job& jb = jobs[j0 + q];
         const int m0 = cplx ? q * copies : q;
-        void* g1 = W[m0];
-        void* g2 = (cplx && il) ? W[m0 + 1] : nullptr;
-        LPP_TRY(prof_begin(p));
         if (jb.series < 0) {
+          void* g1 = W[m0];
+          void* g2 = (cplx && il) ? W[m0 + 1] : nullptr;
+          LPP_TRY(prof_begin(p));
           if (cplx) LPP_TRY(launch_base_gg<T>(ba, g1, g2, Bg, st));
           else LPP_TRY(launch_base_dd<T>(ba, g1, Bd, st));
           LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
           LPP_TRY(prof_begin(p));
           LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 4 * nb, base_rows[cplx], st));
           LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
+          ++q;
           continue;
         }
-        if (!cplx) {
-          LPP_TRY(launch_bin_dd<T>(ba, jb.spec, g1, Bd, st));
-        } else {
-          const void* base = (jb.fam == FAM_GD) ? Bd : Bg;
-          const int kind = (jb.fam == FAM_MINUS) ? 1 : 0;
-          LPP_TRY(launch_bin_gg<T>(ba, jb.spec, g1, g2, base, kind, st));
+        const void* base = !cplx ? Bd : (jb.fam == FAM_GD ? Bd : Bg);
+        const int kind = (cplx && jb.fam == FAM_MINUS) ? 1 : 0;
+        const FieldSpec* fs[kBinGroup];
+        const void* g1[kBinGroup];
+        const void* g2[kBinGroup];
+        int series[kBinGroup];
+        int n = 0;
+        while (q < nf && n < kBinGroup) {
+          const Job& jq = jobs[j0 + q];
+          if (jq.series < 0) break;
+          const void* bq = !cplx ? Bd : (jq.fam == FAM_GD ? Bd : Bg);
+          const int kq = (cplx && jq.fam == FAM_MINUS) ? 1 : 0;
+          if (bq != base || kq != kind) break;
+          const int mq = cplx ? q * copies : q;
+          fs[n] = &jq.spec;
+          g1[n] = W[mq];
+          g2[n] = (cplx && il) ? W[mq + 1] : nullptr;
+          series[n] = jq.series;
+          ++n;
+          ++q;
         }
+        LPP_TRY(prof_begin(p));
+        if (!cplx) LPP_TRY(launch_bin_dd<T>(ba, fs, g1, n, base, st));
+        else LPP_TRY(launch_bin_gg<T>(ba, fs, g1, il ? g2 : nullptr, n, base, kind, st));
         LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
         LPP_TRY(prof_begin(p));
-        LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 2 * nb, acc + static_cast<size_t>(2) * nb * jb.series, st));
-        LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
+        for (int i = 0; i < n; ++i)
+          LPP_TRY(launch_reduce_partials(partial + static_cast<size_t>(2) * i * nb * ba.nblocks, ba.nblocks, 2 * nb,
+                                         acc + static_cast<size_t>(2) * nb * series[i], st));
+        LPP_TRY(prof_end(p, LPP_STAGE_OTHER, n));
       }
       if (overlap) LPP_TRY(hipEventRecord(p->ev_done[pass & 1], st));
     }

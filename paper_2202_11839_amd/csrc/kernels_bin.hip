@@ -12,7 +12,9 @@
 // float2; consecutive threads take consecutive x), keeps a running FP64 sum
 // while the shell index stays the same and flushes it to an LDS accumulator
 // on change; the block's accumulators go to a per-block partial row that a
-// second kernel reduces in block order.
+// second kernel reduces in block order.  The fields of one gather pass that
+// share the base and the kind of product are summed by one launch, which
+// reads the base once for all of them.
 //
 // Density fields are real: their two interlaced copies are packed as the real
 // and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
@@ -113,9 +115,9 @@ __device__ __forceinline__ void tables_init(const BinArgs& a, typename V2<T>::ty
   }
 }
 
-__device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb) {
+__device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb, int width) {
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) s.thr[i] = static_cast<int>(thr[i]);
-  for (int i = threadIdx.x; i < 4 * nb; i += blockDim.x) s.v[i] = 0.0;
+  for (int i = threadIdx.x; i < width; i += blockDim.x) s.v[i] = 0.0;
   __syncthreads();
 }
 
@@ -125,11 +127,14 @@ __device__ __forceinline__ void smem_store(const Smem& s, double* partial, int w
   for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = s.v[i];
 }
 
-// ---- density fields (packed pair of real copies), half k-space ----
-template <typename T, bool BASE>
-__global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T> h,
-                                                             const typename V2<T>::type* __restrict__ P,
-                                                             typename V2<T>::type* __restrict__ B) {
+// ---- the bases: B = F at every mode inside the last shell, with |F|^2, the
+// mode count and the sum of |n| per shell (rows [re, im, counts, sum |n|]) ----
+
+// density base from the packed pair of real copies, half k-space, B also
+// written at -k as conj(F)
+template <typename T>
+__global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const typename V2<T>::type* __restrict__ P,
+                                                              typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
   __shared__ Smem s;
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -137,7 +142,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb);  // (ends with a barrier)
+  smem_init(s, a.thr, nb, 4 * nb);  // (ends with a barrier)
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
@@ -161,11 +166,6 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
     T2 pv[kRun];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) pv[j] = P[run + j];
-    T2 bv[kRun];
-    if (!BASE) {
-#pragma unroll
-      for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
-    }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
       const int iz = z0 + j, nz = iz;  // iz < N/2
@@ -180,34 +180,21 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_kernel(BinArgs a, KSpec<T>
       const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
       const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
       const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
-      if (BASE) {
-        B[run + j] = F;
-        B[midx] = T2{F.x, -F.y};
-        acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
-                      2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
-      } else {
-        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
-        const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
-        // 2 Re[h F conj(B)]
-        const double v = 2.0 * static_cast<double>(hk * (F.x * bv[j].x + F.y * bv[j].y));
-        acc_add<false>(acc, b, v, 0.0, 0.0, 0.0, sre, sim, scnt, sks);
-      }
+      B[run + j] = F;
+      B[midx] = T2{F.x, -F.y};
+      acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
+                    2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
     }
   }
-  if (BASE)
-    acc_flush<true>(acc, sre, sim, scnt, sks);
-  else
-    acc_flush<false>(acc, sre, sim, scnt, sks);
-  smem_store(s, a.partial, (BASE ? 4 : 2) * nb);
+  acc_flush<true>(acc, sre, sim, scnt, sks);
+  smem_store(s, a.partial, 4 * nb);
 }
 
-// ---- complex (shape) fields, full k-space ----
-// KIND 0: h G conj(B(k)); KIND 1: h G B(-k); KIND 2: base construction (B = G, |G|^2)
-template <typename T, int KIND>
-__global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T> h,
-                                                             const typename V2<T>::type* __restrict__ G1,
-                                                             const typename V2<T>::type* __restrict__ G2,
-                                                             typename V2<T>::type* __restrict__ B) {
+// shape base from the two interlaced copies, full k-space
+template <typename T>
+__global__ void __launch_bounds__(kBinThreads) base_gg_kernel(BinArgs a, const typename V2<T>::type* __restrict__ G1,
+                                                              const typename V2<T>::type* __restrict__ G2,
+                                                              typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
   __shared__ Smem s;
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -215,13 +202,12 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb);  // (ends with a barrier)
+  smem_init(s, a.thr, nb, 4 * nb);  // (ends with a barrier)
   double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
   const int qmax = s.thr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
-  const int mask = N - 1;
   const int64_t NN = static_cast<int64_t>(N) * N;
   const int64_t nruns = NN * (N / kRun);  // runs (x, y, z-group)
   Acc acc{-1, 0, 0, 0, 0};
@@ -233,19 +219,14 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
     const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
     if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
     const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
-    const int mx = (N - ix) & mask, my = (N - iy) & mask;
     const T wxy = invw[ix] * invw[iy];
     const T2 pxy = phase[nx + ny + 3 * N / 2];
-    T2 g1[kRun], g2[kRun], bv[kRun];
+    T2 g1[kRun], g2[kRun];
 #pragma unroll
     for (int j = 0; j < kRun; ++j) g1[j] = G1[run + j];
     if (a.interlace) {
 #pragma unroll
       for (int j = 0; j < kRun; ++j) g2[j] = G2[run + j];
-    }
-    if (KIND == 0) {
-#pragma unroll
-      for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
     }
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
@@ -256,30 +237,202 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_kernel(BinArgs a, KSpec<T>
       if (b < 0) continue;
       const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
                                   wxy * iw[iz]);
-      if (KIND == 2) {
-        B[run + j] = F;
-        acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
-                      sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
-        continue;
-      }
-      const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
-      const T hk = harmonic(h, nx * rq, ny * rq, nz * rq);
-      T2 p;
-      if (KIND == 0) {
-        p = cmulc(F, bv[j]);
-      } else {
-        const T2 bm = B[zb_index(mx, my, (N - iz) & mask, N)];
-        p = cmul(F, bm);
-      }
-      acc_add<false>(acc, b, static_cast<double>(hk * p.x), static_cast<double>(hk * p.y), 0.0, 0.0, sre, sim, scnt,
-                     sks);
+      B[run + j] = F;
+      acc_add<true>(acc, b, static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y, 0.0, 1.0,
+                    sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
     }
   }
-  if (KIND == 2)
-    acc_flush<true>(acc, sre, sim, scnt, sks);
-  else
-    acc_flush<false>(acc, sre, sim, scnt, sks);
-  smem_store(s, a.partial, (KIND == 2 ? 4 : 2) * nb);
+  acc_flush<true>(acc, sre, sim, scnt, sks);
+  smem_store(s, a.partial, 4 * nb);
+}
+
+// ---- several fields of one gather pass against the same base ----
+// The fields of a group share the base (read once per run) and the shell
+// index of every mode; each field keeps its own running sum.  Rows: field f
+// at [2f nb, 2f nb + nb) (real part) and [(2f + 1) nb, ...) (imaginary part).
+template <typename T, int NFB>
+struct DdGroup {
+  KSpec<T> h[NFB];
+  const typename V2<T>::type* P[NFB];  // packed pairs of real copies
+};
+template <typename T, int NFB>
+struct GgGroup {
+  KSpec<T> h[NFB];
+  const typename V2<T>::type* g1[NFB];  // grid copy
+  const typename V2<T>::type* g2[NFB];  // interlaced copy (unused without interlacing)
+};
+
+template <typename T, int NFB>
+__global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, DdGroup<T, NFB> g,
+                                                                   const typename V2<T>::type* __restrict__ B) {
+  using T2 = typename V2<T>::type;
+  __shared__ Smem s;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int N = a.N, nb = a.nb;
+  T2* px = reinterpret_cast<T2*>(dyn);
+  T* iw = reinterpret_cast<T*>(px + N);
+  tables_init<T>(a, px, iw);
+  smem_init(s, a.thr, nb, 2 * NFB * nb);  // (ends with a barrier)
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  const int qmax = s.thr[nb];
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
+  const int mask = N - 1;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const int64_t nruns = NN * (N / 2 / kRun);  // runs (x, y, z-group) with z < N/2
+  int cur[NFB];
+  double sr[NFB];
+#pragma unroll
+  for (int f = 0; f < NFB; ++f) {
+    cur[f] = -1;
+    sr[f] = 0.0;
+  }
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int ix = static_cast<int>(r % N);
+    const int iy = static_cast<int>((r / N) % N);
+    const int z0 = static_cast<int>(r / NN) * kRun;
+    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
+    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
+    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
+    const int mx = (N - ix) & mask, my = (N - iy) & mask;
+    const T wxy = invw[ix] * invw[iy];
+    const T2 pxy = phase[nx + ny + 3 * N / 2];
+    T2 bv[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
+    int bq[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const int iz = z0 + j;  // iz < N/2
+      const bool keep = !(iz == 0 && !(iy < N / 2)) && !(iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2));
+      bq[j] = keep ? shell_of(nx * nx + ny * ny + iz * iz, s.thr, nb, inv_dn) : -1;
+    }
+#pragma unroll
+    for (int f = 0; f < NFB; ++f) {
+      const T2* __restrict__ P = g.P[f];
+      T2 pv[kRun];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) pv[j] = P[run + j];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) {
+        const int b = bq[j];
+        if (b < 0) continue;
+        const int iz = z0 + j, nz = iz;
+        const T2 pm = P[zb_index(mx, my, (N - iz) & mask, N)];
+        const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
+        const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
+        const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
+        const int q = nx * nx + ny * ny + nz * nz;
+        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+        const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
+        if (b != cur[f]) {
+          if (cur[f] >= 0) atomicAdd(&s.v[2 * f * nb + cur[f]], sr[f]);
+          cur[f] = b;
+          sr[f] = 0.0;
+        }
+        // 2 Re[h F conj(B)]
+        sr[f] += 2.0 * static_cast<double>(hk * (F.x * bv[j].x + F.y * bv[j].y));
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NFB; ++f)
+    if (cur[f] >= 0) atomicAdd(&s.v[2 * f * nb + cur[f]], sr[f]);
+  smem_store(s, a.partial, 2 * NFB * nb);
+}
+
+// KIND 0: h G conj(B(k)); KIND 1: h G B(-k)
+template <typename T, int KIND, int NFB>
+__global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, GgGroup<T, NFB> g,
+                                                                   const typename V2<T>::type* __restrict__ B) {
+  using T2 = typename V2<T>::type;
+  __shared__ Smem s;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int N = a.N, nb = a.nb;
+  T2* px = reinterpret_cast<T2*>(dyn);
+  T* iw = reinterpret_cast<T*>(px + N);
+  tables_init<T>(a, px, iw);
+  smem_init(s, a.thr, nb, 2 * NFB * nb);  // (ends with a barrier)
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  const int qmax = s.thr[nb];
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
+  const int mask = N - 1;
+  const int64_t NN = static_cast<int64_t>(N) * N;
+  const int64_t nruns = NN * (N / kRun);  // runs (x, y, z-group)
+  int cur[NFB];
+  double sre[NFB], sim[NFB];
+#pragma unroll
+  for (int f = 0; f < NFB; ++f) {
+    cur[f] = -1;
+    sre[f] = sim[f] = 0.0;
+  }
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int ix = static_cast<int>(r % N);
+    const int iy = static_cast<int>((r / N) % N);
+    const int z0 = static_cast<int>(r / NN) * kRun;
+    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
+    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
+    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
+    const int mx = (N - ix) & mask, my = (N - iy) & mask;
+    const T wxy = invw[ix] * invw[iy];
+    const T2 pxy = phase[nx + ny + 3 * N / 2];
+    int bq[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const int nz = sgn_mode(z0 + j, N);
+      bq[j] = shell_of(nx * nx + ny * ny + nz * nz, s.thr, nb, inv_dn);
+    }
+    // the base at k (plus, cross) or at -k (minus), once for all fields
+    T2 bv[kRun];
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      bv[j] = T2{0, 0};
+      if (KIND == 0) bv[j] = B[run + j];
+      else if (bq[j] >= 0) bv[j] = B[zb_index(mx, my, (N - z0 - j) & mask, N)];
+    }
+#pragma unroll
+    for (int f = 0; f < NFB; ++f) {
+      T2 g1[kRun], g2[kRun];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) g1[j] = g.g1[f][run + j];
+      if (a.interlace) {
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) g2[j] = g.g2[f][run + j];
+      }
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) {
+        const int b = bq[j];
+        if (b < 0) continue;
+        const int iz = z0 + j, nz = sgn_mode(iz, N);
+        const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
+                                    wxy * iw[iz]);
+        const int q = nx * nx + ny * ny + nz * nz;
+        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+        const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
+        const T2 p = KIND == 0 ? cmulc(F, bv[j]) : cmul(F, bv[j]);
+        if (b != cur[f]) {
+          if (cur[f] >= 0) {
+            atomicAdd(&s.v[2 * f * nb + cur[f]], sre[f]);
+            atomicAdd(&s.v[(2 * f + 1) * nb + cur[f]], sim[f]);
+          }
+          cur[f] = b;
+          sre[f] = sim[f] = 0.0;
+        }
+        sre[f] += static_cast<double>(hk * p.x);
+        sim[f] += static_cast<double>(hk * p.y);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NFB; ++f)
+    if (cur[f] >= 0) {
+      atomicAdd(&s.v[2 * f * nb + cur[f]], sre[f]);
+      atomicAdd(&s.v[(2 * f + 1) * nb + cur[f]], sim[f]);
+    }
+  smem_store(s, a.partial, 2 * NFB * nb);
 }
 
 // one block per column: strided partial sums, then a fixed-shape tree (deterministic)
@@ -305,7 +458,7 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const doub
 int bin_blocks(int N) {
   const int64_t runs = static_cast<int64_t>(N) * N * N / kRun;
   int64_t want = (runs + kBinThreads - 1) / kBinThreads;
-  if (want > 4096) want = 4096;
+  if (want > 8192) want = 8192;
   if (want < 1) want = 1;
   return static_cast<int>(want);
 }
@@ -314,9 +467,8 @@ template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  KSpec<T> h{};
-  bin_dd_kernel<T, true><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, h, static_cast<const T2*>(packed),
-                                                              static_cast<T2*>(base));
+  base_dd_kernel<T><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, static_cast<const T2*>(packed),
+                                                                          static_cast<T2*>(base));
   return hipGetLastError();
 }
 
@@ -324,35 +476,70 @@ template <typename T>
 hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  KSpec<T> h{};
-  bin_gg_kernel<T, 2><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, h, static_cast<const T2*>(g1),
-                                                          static_cast<const T2*>(g2), static_cast<T2*>(base));
+  base_gg_kernel<T><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, static_cast<const T2*>(g1),
+                                                                          static_cast<const T2*>(g2),
+                                                                          static_cast<T2*>(base));
+  return hipGetLastError();
+}
+
+template <typename T, int NFB>
+hipError_t bin_dd_group_n(const BinArgs& a, const FieldSpec* const* f, const void* const* packed, const void* base,
+                          hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  DdGroup<T, NFB> g{};
+  for (int i = 0; i < NFB; ++i) {
+    g.h[i] = kspec_of<T>(*f[i]);
+    g.P[i] = static_cast<const T2*>(packed[i]);
+  }
+  bin_dd_group_kernel<T, NFB><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, g, static_cast<const T2*>(base));
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
-                         hipStream_t st) {
+hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec* const* f, const void* const* packed, int n,
+                         const void* base, hipStream_t st) {
+  if (a.nb > kMaxBins || 2 * n * a.nb > 4 * kMaxBins) return hipErrorInvalidValue;
+  switch (n) {
+    case 1: return bin_dd_group_n<T, 1>(a, f, packed, base, st);
+    case 2: return bin_dd_group_n<T, 2>(a, f, packed, base, st);
+    case 3: return bin_dd_group_n<T, 3>(a, f, packed, base, st);
+    case 4: return bin_dd_group_n<T, 4>(a, f, packed, base, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int KIND, int NFB>
+hipError_t bin_gg_group_n(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
+                          const void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
-  if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  bin_dd_kernel<T, false><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(packed),
-                                                               const_cast<T2*>(static_cast<const T2*>(base)));
+  GgGroup<T, NFB> g{};
+  for (int i = 0; i < NFB; ++i) {
+    g.h[i] = kspec_of<T>(*f[i]);
+    g.g1[i] = static_cast<const T2*>(g1[i]);
+    g.g2[i] = static_cast<const T2*>(g2 ? g2[i] : g1[i]);
+  }
+  bin_gg_group_kernel<T, KIND, NFB><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, g,
+                                                                                      static_cast<const T2*>(base));
   return hipGetLastError();
 }
 
+template <typename T, int KIND>
+hipError_t bin_gg_kind(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2, int n,
+                       const void* base, hipStream_t st) {
+  switch (n) {
+    case 1: return bin_gg_group_n<T, KIND, 1>(a, f, g1, g2, base, st);
+    case 2: return bin_gg_group_n<T, KIND, 2>(a, f, g1, g2, base, st);
+    case 3: return bin_gg_group_n<T, KIND, 3>(a, f, g1, g2, base, st);
+    case 4: return bin_gg_group_n<T, KIND, 4>(a, f, g1, g2, base, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
-hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
-                         int kind, hipStream_t st) {
-  using T2 = typename V2<T>::type;
-  if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  T2* b = const_cast<T2*>(static_cast<const T2*>(base));
-  if (kind == 0)
-    bin_gg_kernel<T, 0><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
-                                                            static_cast<const T2*>(g2), b);
-  else
-    bin_gg_kernel<T, 1><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, kspec_of<T>(f), static_cast<const T2*>(g1),
-                                                            static_cast<const T2*>(g2), b);
-  return hipGetLastError();
+hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
+                         int n, const void* base, int kind, hipStream_t st) {
+  if (a.nb > kMaxBins || 2 * n * a.nb > 4 * kMaxBins) return hipErrorInvalidValue;
+  return kind == 0 ? bin_gg_kind<T, 0>(a, f, g1, g2, n, base, st) : bin_gg_kind<T, 1>(a, f, g1, g2, n, base, st);
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st) {
@@ -364,11 +551,13 @@ template hipError_t launch_base_dd<float>(const BinArgs&, const void*, void*, hi
 template hipError_t launch_base_dd<double>(const BinArgs&, const void*, void*, hipStream_t);
 template hipError_t launch_base_gg<float>(const BinArgs&, const void*, const void*, void*, hipStream_t);
 template hipError_t launch_base_gg<double>(const BinArgs&, const void*, const void*, void*, hipStream_t);
-template hipError_t launch_bin_gg<float>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*, int,
+template hipError_t launch_bin_gg<float>(const BinArgs&, const FieldSpec* const*, const void* const*,
+                                         const void* const*, int, const void*, int, hipStream_t);
+template hipError_t launch_bin_gg<double>(const BinArgs&, const FieldSpec* const*, const void* const*,
+                                          const void* const*, int, const void*, int, hipStream_t);
+template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec* const*, const void* const*, int, const void*,
                                          hipStream_t);
-template hipError_t launch_bin_gg<double>(const BinArgs&, const FieldSpec&, const void*, const void*, const void*,
-                                          int, hipStream_t);
-template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
-template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec&, const void*, const void*, hipStream_t);
+template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec* const*, const void* const*, int,
+                                          const void*, hipStream_t);
 
 }  // namespace lpp

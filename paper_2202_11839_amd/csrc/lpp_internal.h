@@ -229,13 +229,17 @@ template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st);
 template <typename T>
 hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st);
-// kind 0: G conj(B(k)) (plus / cross), 1: G B(-k) (minus)
+// n <= kBinGroup fields of one gather pass against the same base: field i
+// with harmonic f[i], rows [re, im] of width nb at 2i nb of the partial rows
+// (width 2 n nb).  kind 0: G conj(B(k)) (plus / cross), 1: G B(-k) (minus);
+// g2 nullable without interlacing.
+constexpr int kBinGroup = 4;
 template <typename T>
-hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec& f, const void* g1, const void* g2, const void* base,
-                         int kind, hipStream_t st);
+hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
+                         int n, const void* base, int kind, hipStream_t st);
 template <typename T>
-hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec& f, const void* packed, const void* base,
-                         hipStream_t st);
+hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec* const* f, const void* const* packed, int n,
+                         const void* base, hipStream_t st);
 // Window multipoles (kernels_window.hip), on z-blocked meshes.  Shells of the
 // separation r in cells: T_b <= |n|^2 < T_{b+1} (thr on the device).
 struct WinArgs {

@@ -100,7 +100,7 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 4096, "gather_density": 8, "gather_shape": 4,
+    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 8192, "gather_density": 8, "gather_shape": 4,
                  "serial": 0}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
                 dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=5),
