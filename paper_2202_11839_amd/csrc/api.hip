@@ -170,7 +170,7 @@ struct Layout {
   size_t work[2][kWork];  // two sets: one pass deposits into a set while the other is transformed
   size_t key_d, fx_d, fy_d, fz_d, wr_d;
   size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
-  size_t cell_of, rank, starts_d, starts_g, bsum;
+  size_t cell_of, rank, order, starts_d, starts_g, bsum;
   size_t stage_gal, stage_ran;
   size_t sums_partial, sums_out;
   size_t bin_partial, acc;
@@ -213,6 +213,7 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.wi_g = take(rs * gg);
   L.cell_of = take(4 * nd);
   L.rank = take(4 * nd);
+  L.order = take(4 * nd);
   const size_t ncell = static_cast<size_t>(p->cfg.mesh_n) * p->cfg.mesh_n * p->cfg.mesh_n;
   L.starts_d = take(4 * (ncell + 1));  // also used by lpp_deposit_weights
   L.starts_g = sh ? take(4 * (ncell + 1)) : 0;
@@ -416,6 +417,7 @@ lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const do
   uint32_t* starts = reinterpret_cast<uint32_t*>(wsp(p, shape ? L.starts_g : L.starts_d));
   uint32_t* cell_of = reinterpret_cast<uint32_t*>(wsp(p, L.cell_of));
   uint32_t* rank = reinterpret_cast<uint32_t*>(wsp(p, L.rank));
+  uint32_t* order = reinterpret_cast<uint32_t*>(wsp(p, L.order));
   uint32_t* bsum = reinterpret_cast<uint32_t*>(wsp(p, L.bsum));
   LPP_TRY(prof_begin(p));
   LPP_TRY(launch_fill_zero(starts, 4 * static_cast<size_t>(ncell + 1), st));
@@ -428,10 +430,11 @@ lpp_status sort_set(lpp_plan_s* p, const Layout& L, const RawCat* cats, const do
   off = 0;
   for (int i = 0; i < k; ++i) {
     LPP_TRY(launch_cell_scatter<T>(cats[i], p->geo, wscale[i], wscale_dev[i], shape ? 1 : 0, starts, rank + off,
-                                   cell_of + off, out, st));
+                                   cell_of + off, out, order, off, st));
     off += cats[i].n;
   }
-  LPP_TRY(prof_end(p, LPP_STAGE_SORT, 4 + 2 * k));
+  LPP_TRY(launch_cell_order<T>(starts, ncell, order, out, shape ? 1 : 0, st));
+  LPP_TRY(prof_end(p, LPP_STAGE_SORT, 5 + 2 * k));
   return LPP_OK;
 }
 

@@ -91,11 +91,11 @@ __device__ __forceinline__ bool run_live(int z0, int N, int qxy, int qmax) {
   return mz * mz + qxy < qmax;
 }
 
-// shared-memory layout: thr[kMaxBins+1] ints, then 4*nb doubles
-struct Smem {
-  int thr[kMaxBins + 1];
-  double v[4 * kMaxBins];
-};
+// Shell sums go to one LDS row set per wavefront (its flushes come in program
+// order, and one instruction's lanes in a fixed order), and the rows of the
+// four wavefronts are added in a fixed order when the block stores its
+// partial row: two runs give bitwise the same sums.
+constexpr int kBinWaves = kBinThreads / 64;
 
 // Per-axis tables staged in dynamic LDS (bytes: tables_bytes<T>(N)): the
 // interlacing phase factor along one axis, exp(-i pi n/N) at n + N/2, and
@@ -115,16 +115,37 @@ __device__ __forceinline__ void tables_init(const BinArgs& a, typename V2<T>::ty
   }
 }
 
-__device__ __forceinline__ void smem_init(Smem& s, const int64_t* thr, int nb, int width) {
-  for (int i = threadIdx.x; i <= nb; i += blockDim.x) s.thr[i] = static_cast<int>(thr[i]);
-  for (int i = threadIdx.x; i < width; i += blockDim.x) s.v[i] = 0.0;
-  __syncthreads();
+// dynamic LDS: the per-axis tables, then kBinWaves rows of `width` FP64 sums
+template <typename T>
+constexpr size_t rows_offset(int N) {
+  return (tables_bytes<T>(N) + 15) / 16 * 16;
+}
+template <typename T>
+size_t bin_lds_bytes(int N, int width) {
+  return rows_offset<T>(N) + 8 * static_cast<size_t>(kBinWaves) * width;
 }
 
-// partial rows are stored column-major, [width][gridDim.x], for a coalesced reduction
-__device__ __forceinline__ void smem_store(const Smem& s, double* partial, int width) {
+// thresholds to LDS, every row to zero; returns this wavefront's row
+__device__ __forceinline__ double* rows_init(unsigned char* dyn, size_t off, int width, const int64_t* thr, int* sthr,
+                                             int nb) {
+  double* rows = reinterpret_cast<double*>(dyn + off);
+  for (int i = threadIdx.x; i <= nb; i += blockDim.x) sthr[i] = static_cast<int>(thr[i]);
+  for (int i = threadIdx.x; i < kBinWaves * width; i += blockDim.x) rows[i] = 0.0;
   __syncthreads();
-  for (int i = threadIdx.x; i < width; i += blockDim.x) partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = s.v[i];
+  return rows + (threadIdx.x >> 6) * width;
+}
+
+// the block's partial row (the wavefront rows added in order), stored
+// column-major, [width][gridDim.x], for a coalesced reduction
+__device__ __forceinline__ void rows_store(const unsigned char* dyn, size_t off, int width, double* partial) {
+  const double* rows = reinterpret_cast<const double*>(dyn + off);
+  __syncthreads();
+  for (int i = threadIdx.x; i < width; i += blockDim.x) {
+    double v = rows[i];
+#pragma unroll
+    for (int w = 1; w < kBinWaves; ++w) v += rows[w * width + i];
+    partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = v;
+  }
 }
 
 // ---- the bases: B = F at every mode inside the last shell, with |F|^2, the
@@ -136,17 +157,17 @@ template <typename T>
 __global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const typename V2<T>::type* __restrict__ P,
                                                               typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
-  __shared__ Smem s;
+  __shared__ int sthr[kMaxBins + 1];
   extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb, 4 * nb);  // (ends with a barrier)
-  double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
+  double* v = rows_init(dyn, rows_offset<T>(N), 4 * nb, a.thr, sthr, nb);  // (ends with a barrier)
+  double *sre = v, *sim = v + nb, *scnt = v + 2 * nb, *sks = v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const int qmax = s.thr[nb];
+  const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
   const int64_t NN = static_cast<int64_t>(N) * N;
@@ -172,7 +193,7 @@ __global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const t
       if (iz == 0 && !(iy < N / 2)) continue;                            // z=0 plane: y in [0, N/2)
       if (iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2)) continue;  // y=0 line: x in (0, N/2)
       const int q = nx * nx + ny * ny + nz * nz;
-      const int b = shell_of(q, s.thr, nb, inv_dn);
+      const int b = shell_of(q, sthr, nb, inv_dn);
       if (b < 0) continue;
       const int64_t midx = zb_index(mx, my, (N - iz) & mask, N);
       const T2 pm = P[midx];
@@ -187,7 +208,7 @@ __global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const t
     }
   }
   acc_flush<true>(acc, sre, sim, scnt, sks);
-  smem_store(s, a.partial, 4 * nb);
+  rows_store(dyn, rows_offset<T>(N), 4 * nb, a.partial);
 }
 
 // shape base from the two interlaced copies, full k-space
@@ -196,17 +217,17 @@ __global__ void __launch_bounds__(kBinThreads) base_gg_kernel(BinArgs a, const t
                                                               const typename V2<T>::type* __restrict__ G2,
                                                               typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
-  __shared__ Smem s;
+  __shared__ int sthr[kMaxBins + 1];
   extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb, 4 * nb);  // (ends with a barrier)
-  double *sre = s.v, *sim = s.v + nb, *scnt = s.v + 2 * nb, *sks = s.v + 3 * nb;
+  double* v = rows_init(dyn, rows_offset<T>(N), 4 * nb, a.thr, sthr, nb);  // (ends with a barrier)
+  double *sre = v, *sim = v + nb, *scnt = v + 2 * nb, *sks = v + 3 * nb;
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const int qmax = s.thr[nb];
+  const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int64_t NN = static_cast<int64_t>(N) * N;
   const int64_t nruns = NN * (N / kRun);  // runs (x, y, z-group)
@@ -233,7 +254,7 @@ __global__ void __launch_bounds__(kBinThreads) base_gg_kernel(BinArgs a, const t
       const int iz = z0 + j;
       const int nz = sgn_mode(iz, N);
       const int q = nx * nx + ny * ny + nz * nz;
-      const int b = shell_of(q, s.thr, nb, inv_dn);
+      const int b = shell_of(q, sthr, nb, inv_dn);
       if (b < 0) continue;
       const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
                                   wxy * iw[iz]);
@@ -243,7 +264,7 @@ __global__ void __launch_bounds__(kBinThreads) base_gg_kernel(BinArgs a, const t
     }
   }
   acc_flush<true>(acc, sre, sim, scnt, sks);
-  smem_store(s, a.partial, 4 * nb);
+  rows_store(dyn, rows_offset<T>(N), 4 * nb, a.partial);
 }
 
 // ---- several fields of one gather pass against the same base ----
@@ -266,16 +287,16 @@ template <typename T, int NFB>
 __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, DdGroup<T, NFB> g,
                                                                    const typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
-  __shared__ Smem s;
+  __shared__ int sthr[kMaxBins + 1];
   extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb, 2 * NFB * nb);  // (ends with a barrier)
+  double* v = rows_init(dyn, rows_offset<T>(N), 2 * NFB * nb, a.thr, sthr, nb);  // (ends with a barrier)
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const int qmax = s.thr[nb];
+  const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
   const int64_t NN = static_cast<int64_t>(N) * N;
@@ -306,7 +327,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
     for (int j = 0; j < kRun; ++j) {
       const int iz = z0 + j;  // iz < N/2
       const bool keep = !(iz == 0 && !(iy < N / 2)) && !(iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2));
-      bq[j] = keep ? shell_of(nx * nx + ny * ny + iz * iz, s.thr, nb, inv_dn) : -1;
+      bq[j] = keep ? shell_of(nx * nx + ny * ny + iz * iz, sthr, nb, inv_dn) : -1;
     }
 #pragma unroll
     for (int f = 0; f < NFB; ++f) {
@@ -327,7 +348,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
         const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
         const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
         if (b != cur[f]) {
-          if (cur[f] >= 0) atomicAdd(&s.v[2 * f * nb + cur[f]], sr[f]);
+          if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
           cur[f] = b;
           sr[f] = 0.0;
         }
@@ -338,8 +359,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
   }
 #pragma unroll
   for (int f = 0; f < NFB; ++f)
-    if (cur[f] >= 0) atomicAdd(&s.v[2 * f * nb + cur[f]], sr[f]);
-  smem_store(s, a.partial, 2 * NFB * nb);
+    if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
+  rows_store(dyn, rows_offset<T>(N), 2 * NFB * nb, a.partial);
 }
 
 // KIND 0: h G conj(B(k)); KIND 1: h G B(-k)
@@ -347,16 +368,16 @@ template <typename T, int KIND, int NFB>
 __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, GgGroup<T, NFB> g,
                                                                    const typename V2<T>::type* __restrict__ B) {
   using T2 = typename V2<T>::type;
-  __shared__ Smem s;
+  __shared__ int sthr[kMaxBins + 1];
   extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb;
   T2* px = reinterpret_cast<T2*>(dyn);
   T* iw = reinterpret_cast<T*>(px + N);
   tables_init<T>(a, px, iw);
-  smem_init(s, a.thr, nb, 2 * NFB * nb);  // (ends with a barrier)
+  double* v = rows_init(dyn, rows_offset<T>(N), 2 * NFB * nb, a.thr, sthr, nb);  // (ends with a barrier)
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
-  const int qmax = s.thr[nb];
+  const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int mask = N - 1;
   const int64_t NN = static_cast<int64_t>(N) * N;
@@ -383,7 +404,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
 #pragma unroll
     for (int j = 0; j < kRun; ++j) {
       const int nz = sgn_mode(z0 + j, N);
-      bq[j] = shell_of(nx * nx + ny * ny + nz * nz, s.thr, nb, inv_dn);
+      bq[j] = shell_of(nx * nx + ny * ny + nz * nz, sthr, nb, inv_dn);
     }
     // the base at k (plus, cross) or at -k (minus), once for all fields
     T2 bv[kRun];
@@ -415,8 +436,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
         const T2 p = KIND == 0 ? cmulc(F, bv[j]) : cmul(F, bv[j]);
         if (b != cur[f]) {
           if (cur[f] >= 0) {
-            atomicAdd(&s.v[2 * f * nb + cur[f]], sre[f]);
-            atomicAdd(&s.v[(2 * f + 1) * nb + cur[f]], sim[f]);
+            atomicAdd(&v[2 * f * nb + cur[f]], sre[f]);
+            atomicAdd(&v[(2 * f + 1) * nb + cur[f]], sim[f]);
           }
           cur[f] = b;
           sre[f] = sim[f] = 0.0;
@@ -429,10 +450,10 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
 #pragma unroll
   for (int f = 0; f < NFB; ++f)
     if (cur[f] >= 0) {
-      atomicAdd(&s.v[2 * f * nb + cur[f]], sre[f]);
-      atomicAdd(&s.v[(2 * f + 1) * nb + cur[f]], sim[f]);
+      atomicAdd(&v[2 * f * nb + cur[f]], sre[f]);
+      atomicAdd(&v[(2 * f + 1) * nb + cur[f]], sim[f]);
     }
-  smem_store(s, a.partial, 2 * NFB * nb);
+  rows_store(dyn, rows_offset<T>(N), 2 * NFB * nb, a.partial);
 }
 
 // one block per column: strided partial sums, then a fixed-shape tree (deterministic)
@@ -467,7 +488,7 @@ template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  base_dd_kernel<T><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, static_cast<const T2*>(packed),
+  base_dd_kernel<T><<<a.nblocks, kBinThreads, bin_lds_bytes<T>(a.N, 4 * a.nb), st>>>(a, static_cast<const T2*>(packed),
                                                                           static_cast<T2*>(base));
   return hipGetLastError();
 }
@@ -476,7 +497,7 @@ template <typename T>
 hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb > kMaxBins) return hipErrorInvalidValue;
-  base_gg_kernel<T><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, static_cast<const T2*>(g1),
+  base_gg_kernel<T><<<a.nblocks, kBinThreads, bin_lds_bytes<T>(a.N, 4 * a.nb), st>>>(a, static_cast<const T2*>(g1),
                                                                           static_cast<const T2*>(g2),
                                                                           static_cast<T2*>(base));
   return hipGetLastError();
@@ -491,7 +512,7 @@ hipError_t bin_dd_group_n(const BinArgs& a, const FieldSpec* const* f, const voi
     g.h[i] = kspec_of<T>(*f[i]);
     g.P[i] = static_cast<const T2*>(packed[i]);
   }
-  bin_dd_group_kernel<T, NFB><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, g, static_cast<const T2*>(base));
+  bin_dd_group_kernel<T, NFB><<<a.nblocks, kBinThreads, bin_lds_bytes<T>(a.N, 2 * NFB * a.nb), st>>>(a, g, static_cast<const T2*>(base));
   return hipGetLastError();
 }
 
@@ -518,7 +539,7 @@ hipError_t bin_gg_group_n(const BinArgs& a, const FieldSpec* const* f, const voi
     g.g1[i] = static_cast<const T2*>(g1[i]);
     g.g2[i] = static_cast<const T2*>(g2 ? g2[i] : g1[i]);
   }
-  bin_gg_group_kernel<T, KIND, NFB><<<a.nblocks, kBinThreads, tables_bytes<T>(a.N), st>>>(a, g,
+  bin_gg_group_kernel<T, KIND, NFB><<<a.nblocks, kBinThreads, bin_lds_bytes<T>(a.N, 2 * NFB * a.nb), st>>>(a, g,
                                                                                       static_cast<const T2*>(base));
   return hipGetLastError();
 }

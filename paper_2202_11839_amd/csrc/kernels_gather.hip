@@ -430,7 +430,8 @@ __global__ void cell_count_kernel(RawCat c, Geometry g, uint32_t* counts, uint32
 template <typename T>
 __global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const double* __restrict__ wscale_dev,
                                     int shape, const uint32_t* starts, const uint32_t* rank,
-                                    const uint32_t* cell_of_obj, GObjSet<T> out) {
+                                    const uint32_t* cell_of_obj, GObjSet<T> out, uint32_t* __restrict__ order,
+                                    uint32_t index_base) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= c.n) return;
   if (wscale_dev != nullptr) wscale *= *wscale_dev;
@@ -442,6 +443,7 @@ __global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const d
   const uint32_t cell = cell_of_obj[i];
   const int64_t d = static_cast<int64_t>(starts[cell]) + rank[i];
   out.key[d] = cell;
+  order[d] = index_base + static_cast<uint32_t>(i);
   out.fx[d] = static_cast<T>(ux - cx);
   out.fy[d] = static_cast<T>(uy - cy);
   out.fz[d] = static_cast<T>(uz - cz);
@@ -451,6 +453,43 @@ __global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const d
     out.wi[d] = static_cast<T>(w * ldc(c.g2, i, c.dtype));
   } else {
     out.wr[d] = static_cast<T>(wscale * w);
+  }
+}
+
+// The atomic ranks of cell_count_kernel leave the objects of a cell in an
+// order that changes from run to run, and the gather sums them in storage
+// order.  This puts every cell's objects in the order of their index in the
+// set (insertion sort by that index; cells hold a handful of objects), which
+// makes the sort, and with it the deposit, bitwise reproducible.
+template <typename T>
+__global__ void cell_order_kernel(const uint32_t* __restrict__ starts, int64_t ncell, uint32_t* __restrict__ order,
+                                  GObjSet<T> o, int shape) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c >= ncell) return;
+  const uint32_t s = starts[c], e = starts[c + 1];
+  if (e - s < 2) return;
+  for (uint32_t i = s + 1; i < e; ++i) {
+    const uint32_t k = order[i];
+    const T fx = o.fx[i], fy = o.fy[i], fz = o.fz[i], wr = o.wr[i];
+    const T wi = shape ? o.wi[i] : static_cast<T>(0);
+    uint32_t j = i;
+    while (j > s && order[j - 1] > k) {
+      order[j] = order[j - 1];
+      o.fx[j] = o.fx[j - 1];
+      o.fy[j] = o.fy[j - 1];
+      o.fz[j] = o.fz[j - 1];
+      o.wr[j] = o.wr[j - 1];
+      if (shape) o.wi[j] = o.wi[j - 1];
+      --j;
+    }
+    if (j != i) {
+      order[j] = k;
+      o.fx[j] = fx;
+      o.fy[j] = fy;
+      o.fz[j] = fz;
+      o.wr[j] = wr;
+      if (shape) o.wi[j] = wi;
+    }
   }
 }
 
@@ -632,10 +671,18 @@ hipError_t launch_big_scan(const uint32_t* counts, int64_t n, uint32_t* bsum, ui
 
 template <typename T>
 hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, const double* wscale_dev, int shape, const uint32_t* starts,
-                               const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, hipStream_t st) {
+                               const uint32_t* rank, const uint32_t* cell_of_obj, GObjSet<T> out, uint32_t* order,
+                               int64_t index_base, hipStream_t st) {
   if (c.n == 0) return hipSuccess;
-  cell_scatter_kernel<T><<<static_cast<unsigned>((c.n + 255) / 256), 256, 0, st>>>(c, g, wscale, wscale_dev, shape,
-                                                                                    starts, rank, cell_of_obj, out);
+  cell_scatter_kernel<T><<<static_cast<unsigned>((c.n + 255) / 256), 256, 0, st>>>(
+      c, g, wscale, wscale_dev, shape, starts, rank, cell_of_obj, out, order, static_cast<uint32_t>(index_base));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* order, GObjSet<T> out, int shape,
+                             hipStream_t st) {
+  cell_order_kernel<T><<<static_cast<unsigned>((ncell + 255) / 256), 256, 0, st>>>(starts, ncell, order, out, shape);
   return hipGetLastError();
 }
 
@@ -702,9 +749,13 @@ hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hip
 }
 
 template hipError_t launch_cell_scatter<float>(const RawCat&, const Geometry&, double, const double*, int, const uint32_t*,
-                                               const uint32_t*, const uint32_t*, GObjSet<float>, hipStream_t);
+                                               const uint32_t*, const uint32_t*, GObjSet<float>, uint32_t*, int64_t,
+                                               hipStream_t);
 template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, double, const double*, int, const uint32_t*,
-                                                const uint32_t*, const uint32_t*, GObjSet<double>, hipStream_t);
+                                                const uint32_t*, const uint32_t*, GObjSet<double>, uint32_t*, int64_t,
+                                                hipStream_t);
+template hipError_t launch_cell_order<float>(const uint32_t*, int64_t, uint32_t*, GObjSet<float>, int, hipStream_t);
+template hipError_t launch_cell_order<double>(const uint32_t*, int64_t, uint32_t*, GObjSet<double>, int, hipStream_t);
 template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec*,
                                          int, int, void* const*, const uint8_t*, bool, hipStream_t);
 template hipError_t launch_gather<double>(const GObjSet<double>&, const uint32_t*, const Geometry&, const FieldSpec*,

@@ -27,6 +27,7 @@ using dev::sgn_mode;
 using dev::V2;
 
 constexpr int kWinThreads = 256;
+constexpr int kWinWaves = kWinThreads / 64;
 
 // mode (x, y, z) at position i of a z-blocked mesh
 __device__ __forceinline__ void zb_coords(int64_t i, int N, int& x, int& y, int& z) {
@@ -104,11 +105,15 @@ __global__ void __launch_bounds__(kWinThreads) window_bin_kernel(WinArgs a, cons
   using T2 = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char dyn[];
   const int N = a.N, nb = a.nb, nrow = a.n_rows;
+  // one row set per wavefront, added in a fixed order at the end (bitwise
+  // reproducible sums)
   int* thr = reinterpret_cast<int*>(dyn);
-  double* acc = reinterpret_cast<double*>(dyn + 16 * ((4 * (nb + 1) + 15) / 16));
+  double* rows = reinterpret_cast<double*>(dyn + 16 * ((4 * (nb + 1) + 15) / 16));
+  const int width = nrow * nb;
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) thr[i] = static_cast<int>(a.thr[i]);
-  for (int i = threadIdx.x; i < nrow * nb; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < kWinWaves * width; i += blockDim.x) rows[i] = 0.0;
   __syncthreads();
+  double* acc = rows + (threadIdx.x >> 6) * width;
   const int qmax = thr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
   const int64_t n3 = static_cast<int64_t>(N) * N * N;
@@ -152,8 +157,12 @@ __global__ void __launch_bounds__(kWinThreads) window_bin_kernel(WinArgs a, cons
   }
   flush();
   __syncthreads();
-  for (int i = threadIdx.x; i < nrow * nb; i += blockDim.x)
-    partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = acc[i];
+  for (int i = threadIdx.x; i < width; i += blockDim.x) {
+    double v = rows[i];
+#pragma unroll
+    for (int w = 1; w < kWinWaves; ++w) v += rows[w * width + i];
+    partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = v;
+  }
 }
 
 int grid_for(int64_t n3) {
@@ -179,7 +188,7 @@ hipError_t launch_window_bin(const WinArgs& a, const void* D, const FieldSpec* f
                              int row_b, int with_counts, double* partial, hipStream_t st) {
   using T2 = typename V2<T>::type;
   if (a.nb < 1 || a.nb > kMaxShells || a.n_rows > kWinMaxRows) return hipErrorInvalidValue;
-  const size_t lds = 16 * ((4 * (a.nb + 1) + 15) / 16) + 8 * static_cast<size_t>(a.n_rows) * a.nb;
+  const size_t lds = 16 * ((4 * (a.nb + 1) + 15) / 16) + 8 * static_cast<size_t>(kWinWaves) * a.n_rows * a.nb;
   KSpec<T> ha = kspec_of<T>(*fa), hb = fb ? kspec_of<T>(*fb) : KSpec<T>{};
   window_bin_kernel<T><<<window_bin_blocks(a.N), kWinThreads, lds, st>>>(a, static_cast<const T2*>(D), ha, hb, row_a,
                                                                           fb ? row_b : -1, with_counts, partial);

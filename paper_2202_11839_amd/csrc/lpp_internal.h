@@ -134,7 +134,12 @@ template <typename T>
 // The density weight of each object is w * wscale * (*wscale_dev) (wscale_dev nullable).
 hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale, const double* wscale_dev, int shape,
                                const uint32_t* starts, const uint32_t* rank, const uint32_t* cell_of_obj,
-                               GObjSet<T> out, hipStream_t st);
+                               GObjSet<T> out, uint32_t* order, int64_t index_base, hipStream_t st);
+// Puts the objects of every cell in the order of their index in the set
+// (order[d]: that index, written by the scatter as index_base + i).
+template <typename T>
+hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* order, GObjSet<T> out, int shape,
+                             hipStream_t st);
 // Footprint of a cell-sorted object set, as 0/1 byte flags (nt = N / kTile):
 //   row[y + N z]      node row (y, z) can receive weight: some object lies in
 //                     cells y-2..y+1, z-2..z+1 (the reach of every window

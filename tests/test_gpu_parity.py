@@ -175,6 +175,34 @@ def _footprint_case(layout):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_distant_observer_matches_global_plane_parallel(lpp, prec):
+    """A physics pin of the GPU path that does not go through the oracle's LPP
+    code: for an observer 2e7 Mpc/h away the local lines of sight are all
+    parallel to nhat, and the LPP multipoles equal the global-plane-parallel
+    ones computed from Gamma = gamma exp(-2 i phi_{k,n}) (Sec. III.A, eqs.
+    lpp_dens and gpp_dens; Sec. IV.B case (c)), to 1e-4 of each series' scale
+    (the endpoint directions differ from nhat by < 1e-5)."""
+    nhat = np.array([1.0, 2.0, 3.0]) / np.sqrt(14.0)
+    box, n = 80.0, 16
+    origin = tuple(2.0e7 * nhat - box / 2)
+    g, r = _cats(21, 600, 1800, origin, box, wfun=False)
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=(0.0, 0.0, 0.0), assignment=2, interlacing=1,
+                   n_kbins=6, lmax=4)
+    ref = E.gpp(g, r, cfg, nhat)
+    plan = lpp.Plan(n, box, origin, (0.0, 0.0, 0.0), assignment=2, interlacing=1, precision=prec, lmax=4,
+                    n_kbins=6)
+    got = plan.estimate(g, r)
+    assert got["series"][:len(ref["series"])] == ref["series"]
+    assert list(got["n_modes"]) == list(ref["n_modes"])
+    sc = _scales(ref)
+    sel = ref["n_modes"] > 0
+    for i, name in enumerate(ref["series"]):
+        for part in ("re", "im"):
+            err = np.abs(np.asarray(got[part][i]) - ref[part][i])[sel] / sc[i][sel]
+            assert err.max() <= 1e-4, (name, part, err.max())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["wedge", "wrapped_slabs"])
 def test_estimate_compact_footprint(lpp, layout, prec):
     """Catalogs that cover a small part of the box, so that most node rows,
@@ -367,8 +395,8 @@ def test_tuning_variants_match_oracle(lpp, prec):
 def test_overlapped_deposits_match_serial_order(lpp):
     """The default pipeline deposits the next gather pass on a second stream
     while the current pass is transformed (two work-mesh sets); the result is
-    the serial pipeline's to FP64 rounding of the shell sums, for several
-    estimates in a row on the same plan."""
+    bitwise the serial pipeline's, for several estimates in a row on the same
+    plan."""
     g, r, kw, ref = _footprint_case("wedge")
     plan = lpp.Plan(precision="f64", **kw)
     base = plan.tuning()
@@ -378,10 +406,26 @@ def test_overlapped_deposits_match_serial_order(lpp):
     for _ in range(3):
         over = plan.estimate(g, r)
         assert list(over["n_modes"]) == list(serial["n_modes"])
-        for part in ("re", "im"):
-            a, b = np.asarray(over[part]), np.asarray(serial[part])
-            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+        for part in ("re", "im", "k_eff"):
+            assert np.array_equal(np.asarray(over[part]), np.asarray(serial[part])), part
     _compare(over, ref, 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_two_runs_are_bitwise_equal(lpp, prec):
+    """Every step is reproducible bit for bit: the counting sort puts the
+    objects of each cell in index order before the (atomic-free) gather, the
+    shell sums go through one LDS row set per wavefront added in a fixed
+    order, and every cross-block reduction has a fixed shape.  Two plans,
+    same catalogs: identical estimates and window multipoles."""
+    g, r, kw, _ = _footprint_case("wedge")
+    a = lpp.Plan(precision=prec, **kw).estimate(g, r)
+    b = lpp.Plan(precision=prec, **kw).estimate(g, r)
+    for part in ("re", "im", "k_eff"):
+        assert np.array_equal(np.asarray(a[part]), np.asarray(b[part])), part
+    wa = lpp.Plan(precision=prec, **kw).window_multipoles(r, 0.25, lmax=4, n_rbins=12, rmax=40.0)
+    wb = lpp.Plan(precision=prec, **kw).window_multipoles(r, 0.25, lmax=4, n_rbins=12, rmax=40.0)
+    assert np.array_equal(wa["Q"], wb["Q"])
 
 
 def test_autotune_writes_cache_and_keeps_parity(lpp, tmp_path):
