@@ -22,7 +22,8 @@
 // the same three passes on that layout, with every workgroup owning whole
 // groups of 8 z-values, so that each HBM access is a run of 64 (FP32) or 128
 // (FP64) contiguous bytes per line, and the lanes of a wavefront cover 8
-// such runs side by side wherever the lines allow it.
+// such runs side by side wherever the lines allow it.  Every element is read
+// and written once per pass, with non-temporal (streaming) accesses.
 #include <climits>
 
 #include "device_common.h"
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type*
   for (int j = 0; j < 8; ++j) {
     const int e = t + j * TL;
     v[j] = T2{0, 0};
-    if (rd[j]) v[j] = data[base + (e >> 3) * hi + (e & 7) * lo];
+    if (rd[j]) v[j] = dev::nt_load(&data[base + (e >> 3) * hi + (e & 7) * lo]);
   }
   for (int i = tid; i < N; i += NL * TL) stw[i] = tw[i];
   dev::fft_column_regs<T, N>(stw, sm, col, t, v, swz);
@@ -265,7 +266,7 @@ __global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type*
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int m = dev::sgn_mode(row[q], N);
-    if (qline + m * m < qstore) data[base + (row[q] >> 3) * hi + (row[q] & 7) * lo] = v[q];
+    if (qline + m * m < qstore) dev::nt_store(&data[base + (row[q] >> 3) * hi + (row[q] & 7) * lo], v[q]);
   }
 }
 
