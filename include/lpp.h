@@ -284,6 +284,9 @@ typedef struct {
                               other; 0: the next pass's deposit runs on a second stream of the
                               plan while the current pass is transformed (profiling with
                               lpp_set_profiling always runs them one after the other)      */
+  int32_t fft_streaming;   /* 8 + a bit mask of the passes of the 3D transform (1 x, 2 y, 4 z)
+                              that use non-temporal loads and stores; 0 = the default
+                              (all three)                                                 */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

@@ -164,6 +164,8 @@ int max_shape_fields(const lpp_plan_s* p) {
   return p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex;
 }
 lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
+// passes of the 3D transform with non-temporal accesses (bit a for pass a), -1 = default
+int streaming(const lpp_plan_s* p) { return p->tune.fft_streaming > 0 ? (p->tune.fft_streaming & 7) : -1; }
 // Workspace layout (offsets in bytes), computed for capacities (ng, nr).
 struct Layout {
   size_t mesh[2];  // Bd, Bg
@@ -580,11 +582,11 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
     const FftPrune pr{fp.row, fp.plane, fp.cube, qmax};
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x);
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x, streaming(p));
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz);
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz);
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz, streaming(p));
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz, streaming(p));
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
     return e;
   };
@@ -876,7 +878,8 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
   auto fft = [&](void* m, const FftPrune& pr) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int axis = 0; axis < 3 && e == hipSuccess; ++axis)
-      e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz);
+      e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz,
+                                streaming(p));
     return e;
   };
   const int per = resolved_tuning(p).gather_density;  // one packed mesh each, in work set 0
@@ -1065,6 +1068,7 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
   if (t.gather_density <= 0) t.gather_density = max_density_fields(p);
   if (t.gather_shape <= 0) t.gather_shape = max_shape_fields(p);
+  if (t.fft_streaming <= 0) t.fft_streaming = 8 | zb_default_streaming(N);
   return t;
 }
 
@@ -1077,6 +1081,7 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   if (t.gather_density < 0 || t.gather_density > max_density_fields(p)) return false;
   if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
   if (t.serial != 0 && t.serial != 1) return false;
+  if (t.fft_streaming != 0 && (t.fft_streaming < 8 || t.fft_streaming > 15)) return false;
   return true;
 }
 
@@ -1104,6 +1109,7 @@ bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t)
   if (j == std::string::npos) return false;
   key = line.substr(i + 1, j - i - 1);
   if (!field("serial", t.serial)) t.serial = 0;  // optional
+  if (!field("fft_streaming", t.fft_streaming)) t.fft_streaming = 0;
   return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_yz", t.fft_cols_yz) &&
          field("bin_blocks", t.bin_blocks) && field("gather_density", t.gather_density) &&
          field("gather_shape", t.gather_shape);
@@ -1113,8 +1119,9 @@ std::string tuning_line(const std::string& key, const lpp_tuning& t) {
   char b[256];
   std::snprintf(b, sizeof b,
                 "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_yz\": %d, \"bin_blocks\": %d, "
-                "\"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d}",
-                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape, t.serial);
+                "\"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d, \"fft_streaming\": %d}",
+                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape, t.serial,
+                t.fft_streaming);
   return b;
 }
 

@@ -23,7 +23,8 @@
 // groups of 8 z-values, so that each HBM access is a run of 64 (FP32) or 128
 // (FP64) contiguous bytes per line, and the lanes of a wavefront cover 8
 // such runs side by side wherever the lines allow it.  Every element is read
-// and written once per pass, with non-temporal (streaming) accesses.
+// and written once per pass, with non-temporal (streaming) accesses where
+// the runs are long enough.
 #include <climits>
 
 #include "device_common.h"
@@ -152,8 +153,19 @@ __global__ void __launch_bounds__(NCOL* N / 8) fft_axis_kernel(typename V2<T>::t
 //           first and then across the columns (for N >= 64).
 // Pruning as in fft_axis_kernel.  Element e of a thread's line sits at
 // base + (e >> 3) * hi + (e & 7) * lo.
-template <typename T, int N, int NL, bool ALONG>
-__global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type* __restrict__ data, int axis,
+// waves per SIMD that the LDS allows (up to two workgroups per CU): the
+// kernel must leave registers for them
+template <typename T, int N, int NL>
+constexpr int zb_min_waves() {
+  constexpr int threads = NL * N / 8;
+  constexpr size_t lds = static_cast<size_t>(NL + 1) * N * sizeof(typename V2<T>::type);
+  constexpr int blocks = lds * 2 <= 160 * 1024 ? 2 : 1;
+  constexpr int w = blocks * threads / 256;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+template <typename T, int N, int NL, bool ALONG, bool NT>
+__global__ void __launch_bounds__(NL* N / 8, (zb_min_waves<T, N, NL>())) fft_zb_kernel(typename V2<T>::type* __restrict__ data, int axis,
                                                            const typename V2<T>::type* __restrict__ tw,
                                                            FftPrune pr) {
   using T2 = typename V2<T>::type;
@@ -255,8 +267,14 @@ __global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type*
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int e = t + j * TL;
+    const T2* src = &data[base + (e >> 3) * hi + (e & 7) * lo];
     v[j] = T2{0, 0};
-    if (rd[j]) v[j] = dev::nt_load(&data[base + (e >> 3) * hi + (e & 7) * lo]);
+    if (rd[j]) {
+      if constexpr (NT)
+        v[j] = dev::nt_load(src);
+      else
+        v[j] = *src;
+    }
   }
   for (int i = tid; i < N; i += NL * TL) stw[i] = tw[i];
   dev::fft_column_regs<T, N>(stw, sm, col, t, v, swz);
@@ -266,7 +284,13 @@ __global__ void __launch_bounds__(NL* N / 8) fft_zb_kernel(typename V2<T>::type*
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int m = dev::sgn_mode(row[q], N);
-    if (qline + m * m < qstore) dev::nt_store(&data[base + (row[q] >> 3) * hi + (row[q] & 7) * lo], v[q]);
+    if (qline + m * m < qstore) {
+      T2* dst = &data[base + (row[q] >> 3) * hi + (row[q] & 7) * lo];
+      if constexpr (NT)
+        dev::nt_store(dst, v[q]);
+      else
+        *dst = v[q];
+    }
   }
 }
 
@@ -277,27 +301,34 @@ constexpr bool zb_ok() {
 }
 
 template <typename T, int N, int NL, bool ALONG>
-hipError_t fft_zb_launch(void* mesh, const void* tw, int axis, const FftPrune& pr, hipStream_t st) {
+hipError_t fft_zb_launch(void* mesh, const void* tw, int axis, const FftPrune& pr, int streaming, hipStream_t st) {
+  // (the streaming choice is a template parameter: one access path per
+  // kernel keeps the register count, and two workgroups per CU)
   if constexpr (!zb_ok<T, N, NL>()) {
     return hipErrorInvalidValue;
   } else {
     using T2 = typename V2<T>::type;
     const unsigned grid = static_cast<unsigned>(static_cast<int64_t>(N) * N / NL);
-    fft_zb_kernel<T, N, NL, ALONG><<<grid, NL * (N / 8), 0, st>>>(static_cast<T2*>(mesh), axis,
-                                                                    static_cast<const T2*>(tw), pr);
+    if (streaming)
+      fft_zb_kernel<T, N, NL, ALONG, true><<<grid, NL * (N / 8), 0, st>>>(static_cast<T2*>(mesh), axis,
+                                                                          static_cast<const T2*>(tw), pr);
+    else
+      fft_zb_kernel<T, N, NL, ALONG, false><<<grid, NL * (N / 8), 0, st>>>(static_cast<T2*>(mesh), axis,
+                                                                           static_cast<const T2*>(tw), pr);
     return hipGetLastError();
   }
 }
 
 template <typename T, int N>
-hipError_t fft_zb_n(void* mesh, const void* tw, int axis, const FftPrune& pr, int lines, hipStream_t st) {
+hipError_t fft_zb_n(void* mesh, const void* tw, int axis, const FftPrune& pr, int lines, int streaming,
+                    hipStream_t st) {
   if (lines <= 0) lines = zb_default_lines(N, sizeof(T) == 8, axis);
   if (lines == 8)
-    return axis == 0 ? fft_zb_launch<T, N, 8, true>(mesh, tw, axis, pr, st)
-                     : fft_zb_launch<T, N, 8, false>(mesh, tw, axis, pr, st);
+    return axis == 0 ? fft_zb_launch<T, N, 8, true>(mesh, tw, axis, pr, streaming, st)
+                     : fft_zb_launch<T, N, 8, false>(mesh, tw, axis, pr, streaming, st);
   if (lines == 16)
-    return axis == 0 ? fft_zb_launch<T, N, 16, true>(mesh, tw, axis, pr, st)
-                     : fft_zb_launch<T, N, 16, false>(mesh, tw, axis, pr, st);
+    return axis == 0 ? fft_zb_launch<T, N, 16, true>(mesh, tw, axis, pr, streaming, st)
+                     : fft_zb_launch<T, N, 16, false>(mesh, tw, axis, pr, streaming, st);
   return hipErrorInvalidValue;
 }
 
@@ -398,25 +429,32 @@ bool zb_lines_supported(int N, bool fp64, int axis, int lines) {
   return lines * (N / 8) <= 1024 && lds <= 160 * 1024;
 }
 
+int zb_default_streaming(int N) {
+  (void)N;
+  return 7;
+}
+
 template <typename T>
 hipError_t launch_fft_axis_zb(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st,
-                              int lines) {
+                              int lines, int streaming) {
   if (lines > 0 && !zb_lines_supported(N, sizeof(T) == 8, axis, lines)) return hipErrorInvalidValue;
+  if (streaming < 0) streaming = zb_default_streaming(N);
+  const int nt = (streaming >> axis) & 1;
   switch (N) {
     case 16:
-      return fft_zb_n<T, 16>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 16>(mesh, tw, axis, pr, lines, nt, st);
     case 32:
-      return fft_zb_n<T, 32>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 32>(mesh, tw, axis, pr, lines, nt, st);
     case 64:
-      return fft_zb_n<T, 64>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 64>(mesh, tw, axis, pr, lines, nt, st);
     case 128:
-      return fft_zb_n<T, 128>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 128>(mesh, tw, axis, pr, lines, nt, st);
     case 256:
-      return fft_zb_n<T, 256>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 256>(mesh, tw, axis, pr, lines, nt, st);
     case 512:
-      return fft_zb_n<T, 512>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 512>(mesh, tw, axis, pr, lines, nt, st);
     case 1024:
-      return fft_zb_n<T, 1024>(mesh, tw, axis, pr, lines, st);
+      return fft_zb_n<T, 1024>(mesh, tw, axis, pr, lines, nt, st);
     default:
       return hipErrorInvalidValue;
   }
@@ -435,8 +473,8 @@ hipError_t launch_fft3d(void* mesh, int N, const void* tw, hipStream_t st) {
 template hipError_t launch_fft3d<float>(void*, int, const void*, hipStream_t);
 template hipError_t launch_fft_axis<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
 template hipError_t launch_fft_axis<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
-template hipError_t launch_fft_axis_zb<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
-template hipError_t launch_fft_axis_zb<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int);
+template hipError_t launch_fft_axis_zb<float>(void*, int, const void*, int, const FftPrune&, hipStream_t, int, int);
+template hipError_t launch_fft_axis_zb<double>(void*, int, const void*, int, const FftPrune&, hipStream_t, int, int);
 template hipError_t launch_fft3d<double>(void*, int, const void*, hipStream_t);
 
 }  // namespace lpp

@@ -461,34 +461,43 @@ __global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const d
 // order.  This puts every cell's objects in the order of their index in the
 // set (insertion sort by that index; cells hold a handful of objects), which
 // makes the sort, and with it the deposit, bitwise reproducible.
+constexpr int kOrderCells = 8;  // cells per thread of cell_order_kernel
+
 template <typename T>
 __global__ void cell_order_kernel(const uint32_t* __restrict__ starts, int64_t ncell, uint32_t* __restrict__ order,
                                   GObjSet<T> o, int shape) {
-  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (c >= ncell) return;
-  const uint32_t s = starts[c], e = starts[c + 1];
-  if (e - s < 2) return;
-  for (uint32_t i = s + 1; i < e; ++i) {
-    const uint32_t k = order[i];
-    const T fx = o.fx[i], fy = o.fy[i], fz = o.fz[i], wr = o.wr[i];
-    const T wi = shape ? o.wi[i] : static_cast<T>(0);
-    uint32_t j = i;
-    while (j > s && order[j - 1] > k) {
-      order[j] = order[j - 1];
-      o.fx[j] = o.fx[j - 1];
-      o.fy[j] = o.fy[j - 1];
-      o.fz[j] = o.fz[j - 1];
-      o.wr[j] = o.wr[j - 1];
-      if (shape) o.wi[j] = o.wi[j - 1];
-      --j;
-    }
-    if (j != i) {
-      order[j] = k;
-      o.fx[j] = fx;
-      o.fy[j] = fy;
-      o.fz[j] = fz;
-      o.wr[j] = wr;
-      if (shape) o.wi[j] = wi;
+  const int64_t c0 = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) * kOrderCells;
+  if (c0 >= ncell) return;
+  // the starts of kOrderCells consecutive cells and the end of the last one
+  uint32_t st[kOrderCells + 1];
+#pragma unroll
+  for (int u = 0; u <= kOrderCells; ++u) st[u] = c0 + u <= ncell ? starts[c0 + u] : st[u - 1];
+#pragma unroll
+  for (int u = 0; u < kOrderCells; ++u) {
+    const uint32_t s = st[u], e = st[u + 1];
+    if (e - s < 2) continue;
+    for (uint32_t i = s + 1; i < e; ++i) {
+      const uint32_t k = order[i];
+      const T fx = o.fx[i], fy = o.fy[i], fz = o.fz[i], wr = o.wr[i];
+      const T wi = shape ? o.wi[i] : static_cast<T>(0);
+      uint32_t j = i;
+      while (j > s && order[j - 1] > k) {
+        order[j] = order[j - 1];
+        o.fx[j] = o.fx[j - 1];
+        o.fy[j] = o.fy[j - 1];
+        o.fz[j] = o.fz[j - 1];
+        o.wr[j] = o.wr[j - 1];
+        if (shape) o.wi[j] = o.wi[j - 1];
+        --j;
+      }
+      if (j != i) {
+        order[j] = k;
+        o.fx[j] = fx;
+        o.fy[j] = fy;
+        o.fz[j] = fz;
+        o.wr[j] = wr;
+        if (shape) o.wi[j] = wi;
+      }
     }
   }
 }
@@ -682,7 +691,8 @@ hipError_t launch_cell_scatter(const RawCat& c, const Geometry& g, double wscale
 template <typename T>
 hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* order, GObjSet<T> out, int shape,
                              hipStream_t st) {
-  cell_order_kernel<T><<<static_cast<unsigned>((ncell + 255) / 256), 256, 0, st>>>(starts, ncell, order, out, shape);
+  const int64_t threads = (ncell + kOrderCells - 1) / kOrderCells;
+  cell_order_kernel<T><<<static_cast<unsigned>((threads + 255) / 256), 256, 0, st>>>(starts, ncell, order, out, shape);
   return hipGetLastError();
 }
 

@@ -101,10 +101,10 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
     assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 8192, "gather_density": 8, "gather_shape": 4,
-                 "serial": 0}
+                 "serial": 0, "fft_streaming": 15}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
                 dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=5),
-                dict(serial=2)):
+                dict(serial=2), dict(fft_streaming=7), dict(fft_streaming=16)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
@@ -132,7 +132,7 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, "gather_density": 2,
-                              "gather_shape": 1, "serial": 0}
+                              "gather_shape": 1, "serial": 0, "fft_streaming": 15}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
 
