@@ -125,6 +125,17 @@ def strided_pass_bytes(pos, wl):
     return y_bytes, z_bytes
 
 
+def strided_kernel_name(n, tuning):
+    """The instantiation(s) of the FFT kernel that run the y and z passes:
+    <float, N, lines per workgroup, along-x = false, non-temporal accesses>."""
+    cols, st = tuning["fft_cols_yz"], tuning["fft_streaming"]
+    nt = [bool(st & 8 and st & b) for b in (2, 4)]
+    name = lambda f: "fft_zb_kernel<float, %d, %d, false, %s>" % (n, cols, "true" if f else "false")
+    if nt[0] == nt[1]:
+        return name(nt[0]) + " (y and z passes)"
+    return "%s (y pass), %s (z pass)" % (name(nt[0]), name(nt[1]))
+
+
 def committed_traffic():
     """Counter-measured HBM bytes per launch of the strided FFT pass at the C2
     workload, from the committed rocprofv3 summary, if it was taken on the
@@ -405,7 +416,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
-            "kernel": "fft_zb_kernel<float, %d, %d, false> (y and z passes)" % (n, plan.tuning()["fft_cols_yz"]),
+            "kernel": strided_kernel_name(n, plan.tuning()),
             "alg_bytes_per_launch": round(alg_bytes), "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "stage_ms_per_step": {k: round(v[0] / psteps, 3) for k, v in prof.items()},
             "stages_serial_ms_per_step": round(sum(v[0] for v in prof.values()) / psteps, 2)}

@@ -1068,7 +1068,7 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
   if (t.gather_density <= 0) t.gather_density = max_density_fields(p);
   if (t.gather_shape <= 0) t.gather_shape = max_shape_fields(p);
-  if (t.fft_streaming <= 0) t.fft_streaming = 8 | zb_default_streaming(N);
+  if (t.fft_streaming <= 0) t.fft_streaming = 8 | zb_default_streaming(N, f64, t.fft_cols_yz);
   return t;
 }
 

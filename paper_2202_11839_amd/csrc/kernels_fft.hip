@@ -429,16 +429,23 @@ bool zb_lines_supported(int N, bool fp64, int axis, int lines) {
   return lines * (N / 8) <= 1024 && lds <= 160 * 1024;
 }
 
-int zb_default_streaming(int N) {
-  (void)N;
-  return 7;
+// Non-temporal accesses pay off in a pass whose lines are read as runs of at
+// least 128 contiguous bytes (an L2 line): the x and z passes always, the y
+// pass when a workgroup holds two columns x (FP32, 16 lines) or runs of
+// 16-byte FP64 values.  With 64-byte runs the other half of each L2 line
+// belongs to the neighbouring workgroup, and the streaming hint lets it be
+// evicted before that workgroup reads it.
+int zb_default_streaming(int N, bool fp64, int lines_yz) {
+  if (lines_yz <= 0) lines_yz = zb_default_lines(N, fp64, 1);
+  const int run = (lines_yz / 8) * 8 * (fp64 ? 16 : 8);
+  return 1 | 4 | (run >= 128 ? 2 : 0);
 }
 
 template <typename T>
 hipError_t launch_fft_axis_zb(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st,
                               int lines, int streaming) {
   if (lines > 0 && !zb_lines_supported(N, sizeof(T) == 8, axis, lines)) return hipErrorInvalidValue;
-  if (streaming < 0) streaming = zb_default_streaming(N);
+  if (streaming < 0) streaming = zb_default_streaming(N, sizeof(T) == 8, axis == 0 ? 0 : lines);
   const int nt = (streaming >> axis) & 1;
   switch (N) {
     case 16:

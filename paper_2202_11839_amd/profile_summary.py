@@ -44,6 +44,30 @@ def kernel_table(db: str) -> list[tuple[str, int, float, float]]:
     return sorted(out, key=lambda r: -r[3])
 
 
+def fft_pass_split(db: str) -> list[tuple[str, int, float, float]]:
+    """Durations of the z-blocked FFT kernel by pass.  A transform launches
+    the x pass (the along-x instantiation) and then the y and z passes, so in
+    launch order the two launches after an x pass are its y and z passes."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    by = {"x": [], "y": [], "z": []}
+    last = None
+    for name, t0, t1 in rows:
+        name = _short(name)
+        if "fft_zb_kernel<" not in name:
+            continue
+        args = name[name.index("<") + 1:name.rindex(">")].split(", ")
+        d = (t1 - t0) / 1e6
+        if args[3] == "true":
+            last = "x"
+        elif last in ("x", "y"):
+            last = "y" if last == "x" else "z"
+        else:
+            continue
+        by[last].append(d)
+    return [(p, len(v), statistics.mean(v), statistics.median(v)) for p, v in by.items() if v]
+
+
 def counter(db: str, name: str) -> dict[str, list[float]]:
     con = sqlite3.connect(db)
     per: dict[str, list[float]] = {}
@@ -92,6 +116,12 @@ def main() -> None:
         for name, calls, avg, tot in rows[: args.top]:
             print(f"{name[:70]:70s} {calls:6d} {avg:9.4f} {tot:10.2f} {100 * tot / total:5.1f}%")
         print(f"{'all kernels':70s} {sum(r[1] for r in rows):6d} {'':9s} {total:10.2f}")
+        split = fft_pass_split(args.db)
+        if split:
+            print("# fft_zb_kernel launches split by pass (launch order x, y, z per transform): "
+                  "pass, launches, mean ms, median ms")
+            for p, n, mean, med in split:
+                print(f"#   {p} {n} {mean:.4f} {med:.4f}")
         return
 
     fs, ws = scale(args.copy_fetch_db, "FETCH_SIZE"), scale(args.copy_write_db, "WRITE_SIZE")

@@ -110,10 +110,20 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
         assert plan.tuning() == t
     plan.set_tuning(fft_cols_yz=8, gather_density=2)
     assert plan.tuning()["fft_cols_yz"] == 8 and plan.tuning()["gather_density"] == 2
+    # the y pass streams by default only when its runs fill 128-byte lines:
+    # not with 8 FP32 lines (64-byte runs), always in FP64 (0 = the default)
+    assert plan.tuning()["fft_streaming"] == 15
+    plan.set_tuning(fft_streaming=0)
+    assert plan.tuning()["fft_streaming"] == 8 | 1 | 4
+    plan.set_tuning(fft_streaming=8 | 2)
+    assert plan.tuning()["fft_streaming"] == 10
     # FP64: the default strided block holds one z-group of one column; more
     # lines than 1024 threads or one CU's LDS allow are refused
     p64 = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f64", lmax=4, n_kbins=50)
     assert p64.tuning()["fft_cols_yz"] == 8 and p64.tuning()["fft_rows_x"] == 8
+    assert p64.tuning()["fft_streaming"] == 15
+    assert pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4,
+                    n_kbins=50).tuning()["fft_streaming"] == 13
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_cols_yz=16)
     with pytest.raises(pkg.LppError):
@@ -132,7 +142,7 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, "gather_density": 2,
-                              "gather_shape": 1, "serial": 0, "fft_streaming": 15}
+                              "gather_shape": 1, "serial": 0, "fft_streaming": 13}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
 
