@@ -94,6 +94,12 @@ typedef struct {
   int32_t n_kbins;         /* number of k-shells, 1..256                           */
   int32_t dn_num, dn_den;  /* bin width dn_num/dn_den in units of kf; both 0 for
                               the default N/(2 n_kbins)                            */
+  int32_t global_los;      /* 0: each object's own line of sight xhat (the LPP
+                              estimator); 1: one line of sight los for every
+                              object, the global-plane-parallel estimator of
+                              Sec. II.C (shapes then in the basis of los; the
+                              observer is not used)                                */
+  double los[3];           /* global_los = 1: the line of sight, any length > 0    */
 } lpp_config;
 
 typedef struct {
@@ -166,7 +172,7 @@ lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 
 /* Multipoles of the window's auto-correlation (Sec. III.B, eqs. windowQ and
  * windowQ_ell), with the line of sight of the pair taken at its first point
- * (end point).  The window is alpha * sum_r w_r delta_D(x - x_r) (randoms
+ * (end point), or the plan's global line of sight when it has one.  The window is alpha * sum_r w_r delta_D(x - x_r) (randoms
  * weighted to the galaxy density; alpha = sum w_gal / sum w_ran of the data),
  * deposited, interlaced and compensated as the plan's density field, and
  * auto-correlated by FFT on the plan's periodic box, which should be at least

@@ -49,7 +49,8 @@ class Config(C.Structure):
     _fields_ = [("mesh_n", C.c_int32), ("box_size", C.c_double), ("box_origin", C.c_double * 3),
                 ("observer", C.c_double * 3), ("assignment", C.c_int32), ("interlacing", C.c_int32),
                 ("compensate", C.c_int32), ("precision", C.c_int32), ("lmax", C.c_int32),
-                ("spectra", C.c_uint32), ("n_kbins", C.c_int32), ("dn_num", C.c_int32), ("dn_den", C.c_int32)]
+                ("spectra", C.c_uint32), ("n_kbins", C.c_int32), ("dn_num", C.c_int32), ("dn_den", C.c_int32),
+                ("global_los", C.c_int32), ("los", C.c_double * 3)]
 
 
 class CatalogStruct(C.Structure):
@@ -149,11 +150,14 @@ class _Cols:
 
 
 class Plan:
-    """One estimator configuration (mesh, box, observer, assignment, multipoles, bins)."""
+    """One estimator configuration (mesh, box, observer, assignment, multipoles, bins).
+
+    ``los``: None for each object's own line of sight (the LPP estimator), or
+    a vector: one line of sight for every object (global plane-parallel)."""
 
     def __init__(self, mesh_n: int, box_size: float, box_origin, observer=(0.0, 0.0, 0.0), assignment: int = 3,
                  interlacing: int = 1, compensate: int = 1, precision: str = "f32", lmax: int = 4,
-                 spectra: int = LPP_ALL, n_kbins: int = 16, dn=None):
+                 spectra: int = LPP_ALL, n_kbins: int = 16, dn=None, los=None):
         self.lib = load()
         cfg = Config()
         cfg.mesh_n = mesh_n
@@ -168,6 +172,8 @@ class Plan:
         cfg.spectra = spectra
         cfg.n_kbins = n_kbins
         cfg.dn_num, cfg.dn_den = (0, 0) if dn is None else dn
+        cfg.global_los = 0 if los is None else 1
+        cfg.los = (C.c_double * 3)(*((0.0, 0.0, 0.0) if los is None else los))
         self.cfg = cfg
         self.precision = cfg.precision
         h = C.c_void_p()

@@ -1281,6 +1281,20 @@ lpp_status lpp_plan_create(const lpp_config* cfg_in, lpp_plan* out) {
   if (cfg.dn_num <= 0 || cfg.dn_den <= 0) return LPP_E_INVALID;
   // the last edge must not pass the Nyquist frequency: n_kbins * num / den <= N/2
   if (static_cast<int64_t>(cfg.n_kbins) * cfg.dn_num * 2 > static_cast<int64_t>(N) * cfg.dn_den) return LPP_E_INVALID;
+  double los_norm = 0.0;
+  if (cfg.global_los != 0 && cfg.global_los != 1) return LPP_E_INVALID;
+  double los_unit[3] = {0.0, 0.0, 0.0};
+  if (cfg.global_los) {
+    double m = 0.0;  // scale by the largest component: no overflow or underflow
+    for (int i = 0; i < 3; ++i) {
+      if (!std::isfinite(cfg.los[i])) return LPP_E_INVALID;
+      m = std::max(m, std::fabs(cfg.los[i]));
+    }
+    if (!(m > 0.0)) return LPP_E_INVALID;
+    for (int i = 0; i < 3; ++i) los_norm += (cfg.los[i] / m) * (cfg.los[i] / m);
+    los_norm = std::sqrt(los_norm);
+    for (int i = 0; i < 3; ++i) los_unit[i] = (cfg.los[i] / m) / los_norm;
+  }
   // a spectrum needs its multipoles: GD needs lmax >= 2, MINUS needs lmax >= 4
   if ((cfg.spectra & LPP_GD) && cfg.lmax < 2) return LPP_E_INVALID;
   if ((cfg.spectra & LPP_MINUS) && cfg.lmax < 4) return LPP_E_INVALID;
@@ -1294,9 +1308,12 @@ lpp_status lpp_plan_create(const lpp_config* cfg_in, lpp_plan* out) {
   p->geo.H = cfg.box_size / N;
   p->geo.box = cfg.box_size;
   load_tuning_cache(p, std::getenv("LPP_AUTOTUNE_CACHE"));
+  p->geo.global_los = cfg.global_los;
+  p->geo.los_h = cfg.global_los ? 0.0 : p->geo.H;
   for (int i = 0; i < 3; ++i) {
     p->geo.origin[i] = cfg.box_origin[i];
     p->geo.rel[i] = cfg.box_origin[i] - cfg.observer[i];
+    p->geo.los_rel[i] = cfg.global_los ? los_unit[i] : p->geo.rel[i];
   }
   *out = p;
   return LPP_OK;

@@ -572,8 +572,9 @@ __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, 
 template <typename T, int K, int NF>
 hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
                     const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
-  const T H = static_cast<T>(g.H), rx = static_cast<T>(g.rel[0]), ry = static_cast<T>(g.rel[1]),
-          rz = static_cast<T>(g.rel[2]);
+  // the line of sight of an object in cell c at fraction f: rel + (c + f) H
+  const T H = static_cast<T>(g.los_h), rx = static_cast<T>(g.los_rel[0]), ry = static_cast<T>(g.los_rel[1]),
+          rz = static_cast<T>(g.los_rel[2]);
   SpecSet<T, NF> fs;
   for (int q = 0; q < NF; ++q) fs.f[q] = to_spec<T>(specs[q]);
   MeshSet<T> ms{};

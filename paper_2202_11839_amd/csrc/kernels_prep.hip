@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(kSumThreads) catalog_sums_kernel(RawCat c, Geo
     const double ux = (x - g.origin[0]) / g.H, uy = (y - g.origin[1]) / g.H, uz = (z - g.origin[2]) / g.H;
     if (!(ux >= 0.0 && ux < g.N && uy >= 0.0 && uy < g.N && uz >= 0.0 && uz < g.N)) acc[5] += 1.0;
     const double rx = x - g.origin[0] + g.rel[0], ry = y - g.origin[1] + g.rel[1], rz = z - g.origin[2] + g.rel[2];
-    if (rx * rx + ry * ry + rz * rz < minr2) acc[6] += 1.0;
+    if (!g.global_los && rx * rx + ry * ry + rz * rz < minr2) acc[6] += 1.0;
     acc[0] += w;
     acc[1] += w * w;
     acc[2] += w * w * nb;

@@ -100,6 +100,12 @@ struct Geometry {
   double origin[3];
   double rel[3];           // origin - observer
   double box;
+  // line of sight of node c + f: los_rel + (c + f) los_h.  The object's own
+  // direction (los_h = H, los_rel = rel), or one global direction (los_h = 0,
+  // los_rel = the unit line of sight)
+  int global_los;
+  double los_h;
+  double los_rel[3];
 };
 
 // ---- mesh layouts ----

@@ -203,6 +203,39 @@ def test_distant_observer_matches_global_plane_parallel(lpp, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_global_line_of_sight_matches_oracle_gpp(lpp, prec):
+    """The plan's global-line-of-sight mode against the oracle's
+    global-plane-parallel estimator (Sec. II.C), with the observer inside the
+    box and one galaxy placed exactly on it: the observer plays no part."""
+    nhat = np.array([2.0, -1.0, 2.0]) / 3.0
+    box, n = 120.0, 16
+    origin = (10.0, -20.0, 30.0)
+    g, r = _cats(23, 700, 2100, origin, box)
+    obs = np.asarray(origin) + box / 2
+    g.x[0], g.y[0], g.z[0] = obs
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=tuple(obs), assignment=3, interlacing=1,
+                   n_kbins=6, lmax=4)
+    ref = E.gpp(g, r, cfg, nhat)
+    plan = lpp.Plan(n, box, origin, tuple(obs), assignment=3, interlacing=1, precision=prec, lmax=4,
+                    n_kbins=6, los=tuple(3.0 * nhat))
+    got = plan.estimate(g, r)
+    assert got["series"][:len(ref["series"])] == ref["series"]
+    assert list(got["n_modes"]) == list(ref["n_modes"])
+    sc = _scales(ref)
+    sel = ref["n_modes"] > 0
+    tol = 1e-9 if prec == "f64" else 1e-4
+    for i, name in enumerate(ref["series"]):
+        for part in ("re", "im"):
+            err = np.abs(np.asarray(got[part][i]) - ref[part][i])[sel] / sc[i][sel]
+            assert err.max() <= tol, (name, part, err.max())
+    # the same catalogs with each object's own line of sight are refused (a galaxy at the observer)
+    local = lpp.Plan(n, box, origin, tuple(obs), assignment=3, interlacing=1, precision=prec, lmax=4, n_kbins=6)
+    with pytest.raises(lpp.LppError) as e:
+        local.estimate(g, r)
+    assert e.value.status == 4  # LPP_E_AT_OBSERVER
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("layout", ["wedge", "wrapped_slabs"])
 def test_estimate_compact_footprint(lpp, layout, prec):
     """Catalogs that cover a small part of the box, so that most node rows,

@@ -45,6 +45,8 @@ def _cfg(**kw):
     c.spectra = kw.get("spectra", 15)
     c.n_kbins = kw.get("n_kbins", 8)
     c.dn_num, c.dn_den = kw.get("dn", (0, 0))
+    c.global_los = kw.get("global_los", 0)
+    c.los = (C.c_double * 3)(*kw.get("los", (0.0, 0.0, 0.0)))
     return c
 
 
@@ -52,7 +54,8 @@ def _cfg(**kw):
                                  dict(assignment=4), dict(interlacing=2), dict(precision=3), dict(lmax=3),
                                  dict(lmax=10), dict(spectra=0), dict(spectra=16), dict(n_kbins=0),
                                  dict(dn=(17, 1), n_kbins=1), dict(dn=(-1, 2)), dict(lmax=2, spectra=8),
-                                 dict(lmax=0, spectra=2)])
+                                 dict(lmax=0, spectra=2), dict(global_los=2, los=(0.0, 0.0, 1.0)),
+                                 dict(global_los=1), dict(global_los=1, los=(0.0, float("nan"), 1.0))])
 def test_plan_validation(bad):
     pkg = _lib()
     lib = pkg.load()
@@ -60,6 +63,20 @@ def test_plan_validation(bad):
     st = lib.lpp_plan_create(C.byref(_cfg(**bad)), C.byref(h))
     assert st == 1  # LPP_E_INVALID
     assert not h.value
+
+
+def test_global_line_of_sight_config():
+    """A global line of sight of any positive length is accepted (and the
+    observer ignored); its series are those of the local-LOS plan."""
+    pkg = _lib()
+    lib = pkg.load()
+    for los in ((0.0, 0.0, 1.0), (3.0, -4.0, 12.0), (1e-200, 0.0, 0.0), (1e300, 1e300, 0.0)):
+        h = C.c_void_p()
+        assert lib.lpp_plan_create(C.byref(_cfg(global_los=1, los=los)), C.byref(h)) == 0
+        assert lib.lpp_plan_destroy(h) == 0
+    a = pkg.Plan(32, 100.0, (0.0, 0.0, 0.0), (-5.0, -5.0, -5.0), n_kbins=7)
+    b = pkg.Plan(32, 100.0, (0.0, 0.0, 0.0), (-5.0, -5.0, -5.0), n_kbins=7, los=(0.0, 1.0, 1.0))
+    assert a.series == b.series
 
 
 def test_plan_tables_match_oracle():
