@@ -112,8 +112,45 @@ __device__ __forceinline__ T window(T x) {
   return ax < static_cast<T>(0.5) ? inner : outer;
 }
 
+// w times the 1D window of the nodes at integer coordinates c, for an object
+// at coordinate u (w >= 0).  TSC: with i the node nearest to u and d = u - i
+// in [-1/2, 1/2], node c = i + e gets W(d - e); the quadratic
+//   f(e) = 3/4 - d^2 + e d/2 + e^2 (3 d^2/2 - 5/8)
+// takes the three values 1/2 (1/2 - d)^2, 3/4 - d^2, 1/2 (1/2 + d)^2 at
+// e = -1, 0, 1, and is <= 0 at every other integer e (its e^2 coefficient is
+// negative on |d| <= 1/2, and f(+-2) = -7/4 +- d + 5 d^2 <= 0 there), so
+// W = max(0, f(e)) on every node: two FMAs and a max per node instead of
+// the piecewise window.
+template <typename T, int P>
+struct AxisWeights {
+  T u, w, i, b, a1, a2;
+  __device__ __forceinline__ AxisWeights(T u_, T w_) {
+    if constexpr (P == 3) {
+      i = rint(u_);
+      const T d = u_ - i, dd = d * d;
+      b = w_ * (static_cast<T>(0.75) - dd);
+      a1 = w_ * (static_cast<T>(0.5) * d);
+      a2 = w_ * (static_cast<T>(1.5) * dd - static_cast<T>(0.625));
+    } else {
+      u = u_;
+      w = w_;
+    }
+  }
+  __device__ __forceinline__ T at(int c) const;
+};
+
 constexpr int TT = 8;          // tile edge (nodes)
 constexpr int R = TT + 3;      // region edge (cells t0-2 .. t0+TT)
+
+template <typename T, int P>
+__device__ __forceinline__ T AxisWeights<T, P>::at(int c) const {
+  if constexpr (P == 3) {
+    const T e = static_cast<T>(c) - i;
+    return fmax(static_cast<T>(0), fma(e, fma(e, a2, a1), b));
+  } else {
+    return w * window<T, P>(u - static_cast<T>(c));
+  }
+}
 constexpr int R2 = R * R;      // region rows (y, z)
 constexpr int kRows = TT * TT;          // x-rows of the tile
 constexpr int kParts = 4;               // threads per row: one z-offset of the stencil range each
@@ -335,11 +372,11 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
         T val[K * NF];
 #pragma unroll
         for (int q = 0; q < K * NF; ++q) val[q] = su[3 + q][d];
+        const AxisWeights<T, P> xw0(ux, w0), xw1(ux - half, w1);
 #pragma unroll
         for (int kx = 0; kx < TT; ++kx) {
-          const T xk = ux - static_cast<T>(kx + 2);
-          const T wx0 = w0 * window<T, P>(xk);
-          const T wx1 = w1 * window<T, P>(xk - half);
+          const T wx0 = xw0.at(kx + 2);  // node kx sits at region coordinate kx + 2
+          const T wx1 = xw1.at(kx + 2);
 #pragma unroll
           for (int q = 0; q < NF; ++q)
 #pragma unroll
