@@ -170,8 +170,8 @@ int streaming(const lpp_plan_s* p) { return p->tune.fft_streaming > 0 ? (p->tune
 struct Layout {
   size_t mesh[2];  // Bd, Bg
   size_t work[2][kWork];  // two sets: one pass deposits into a set while the other is transformed
-  size_t key_d, fx_d, fy_d, fz_d, wr_d;
-  size_t key_g, fx_g, fy_g, fz_g, wr_g, wi_g;
+  size_t pos_d, wr_d;
+  size_t pos_g, wr_g, wi_g;
   size_t cell_of, rank, order, starts_d, starts_g, bsum;
   size_t stage_gal, stage_ran;
   size_t sums_partial, sums_out;
@@ -202,15 +202,9 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
     for (int i = 0; i < work_meshes(p); ++i) L.work[s][i] = take(M);
   const size_t nd = static_cast<size_t>(ng + nr);
   const size_t gg = static_cast<size_t>(ng);
-  L.key_d = take(4 * nd);
-  L.fx_d = take(rs * nd);
-  L.fy_d = take(rs * nd);
-  L.fz_d = take(rs * nd);
+  L.pos_d = take(4 * rs * nd);  // ObjPos<T>: 4 values of the real type
   L.wr_d = take(rs * nd);
-  L.key_g = take(4 * gg);
-  L.fx_g = take(rs * gg);
-  L.fy_g = take(rs * gg);
-  L.fz_g = take(rs * gg);
+  L.pos_g = take(4 * rs * gg);
   L.wr_g = take(rs * gg);
   L.wi_g = take(rs * gg);
   L.cell_of = take(4 * nd);
@@ -392,17 +386,11 @@ template <typename T>
 GObjSet<T> objset(lpp_plan_s* p, const Layout& L, bool shape_set, int64_t n) {
   GObjSet<T> o{};
   if (shape_set) {
-    o.key = reinterpret_cast<uint32_t*>(wsp(p, L.key_g));
-    o.fx = reinterpret_cast<T*>(wsp(p, L.fx_g));
-    o.fy = reinterpret_cast<T*>(wsp(p, L.fy_g));
-    o.fz = reinterpret_cast<T*>(wsp(p, L.fz_g));
+    o.pos = reinterpret_cast<ObjPos<T>*>(wsp(p, L.pos_g));
     o.wr = reinterpret_cast<T*>(wsp(p, L.wr_g));
     o.wi = reinterpret_cast<T*>(wsp(p, L.wi_g));
   } else {
-    o.key = reinterpret_cast<uint32_t*>(wsp(p, L.key_d));
-    o.fx = reinterpret_cast<T*>(wsp(p, L.fx_d));
-    o.fy = reinterpret_cast<T*>(wsp(p, L.fy_d));
-    o.fz = reinterpret_cast<T*>(wsp(p, L.fz_d));
+    o.pos = reinterpret_cast<ObjPos<T>*>(wsp(p, L.pos_d));
     o.wr = reinterpret_cast<T*>(wsp(p, L.wr_d));
     o.wi = nullptr;
   }

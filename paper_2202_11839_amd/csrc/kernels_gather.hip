@@ -325,12 +325,13 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
       const int r = lo;
       const uint32_t j = k - roff[r];
       const uint32_t src = j < seg_cnt[r] ? seg_beg[r][0] + j : seg_beg[r][1] + (j - seg_cnt[r]);
-      const uint32_t key = o.key[src];
+      const ObjPos<T> rec = o.pos[src];
+      const uint32_t key = rec.key;
       const int cx = static_cast<int>(key & mask);
       const int cy = static_cast<int>((key >> lgN) & mask);
       const int cz = static_cast<int>(key >> (2 * lgN));
       const int lx = (cx - t0x + 2) & mask, ly = r % R, lz = r / R;
-      const T fx = o.fx[src], fy = o.fy[src], fz = o.fz[src];
+      const T fx = rec.fx, fy = rec.fy, fz = rec.fz;
       const uint32_t d = k - c0;
       su[0][d] = static_cast<T>(lx) + fx;
       su[1][d] = static_cast<T>(ly) + fy;
@@ -479,11 +480,13 @@ __global__ void cell_scatter_kernel(RawCat c, Geometry g, double wscale, const d
   const int cx = cell_of(ux, N), cy = cell_of(uy, N), cz = cell_of(uz, N);
   const uint32_t cell = cell_of_obj[i];
   const int64_t d = static_cast<int64_t>(starts[cell]) + rank[i];
-  out.key[d] = cell;
+  ObjPos<T> rec;
+  rec.key = cell;
+  rec.fx = static_cast<T>(ux - cx);
+  rec.fy = static_cast<T>(uy - cy);
+  rec.fz = static_cast<T>(uz - cz);
+  out.pos[d] = rec;
   order[d] = index_base + static_cast<uint32_t>(i);
-  out.fx[d] = static_cast<T>(ux - cx);
-  out.fy[d] = static_cast<T>(uy - cy);
-  out.fz[d] = static_cast<T>(uz - cz);
   const double w = c.w ? ldc(c.w, i, c.dtype) : 1.0;
   if (shape) {
     out.wr[d] = static_cast<T>(w * ldc(c.g1, i, c.dtype));
@@ -515,23 +518,20 @@ __global__ void cell_order_kernel(const uint32_t* __restrict__ starts, int64_t n
     if (e - s < 2) continue;
     for (uint32_t i = s + 1; i < e; ++i) {
       const uint32_t k = order[i];
-      const T fx = o.fx[i], fy = o.fy[i], fz = o.fz[i], wr = o.wr[i];
+      const ObjPos<T> rec = o.pos[i];
+      const T wr = o.wr[i];
       const T wi = shape ? o.wi[i] : static_cast<T>(0);
       uint32_t j = i;
       while (j > s && order[j - 1] > k) {
         order[j] = order[j - 1];
-        o.fx[j] = o.fx[j - 1];
-        o.fy[j] = o.fy[j - 1];
-        o.fz[j] = o.fz[j - 1];
+        o.pos[j] = o.pos[j - 1];
         o.wr[j] = o.wr[j - 1];
         if (shape) o.wi[j] = o.wi[j - 1];
         --j;
       }
       if (j != i) {
         order[j] = k;
-        o.fx[j] = fx;
-        o.fy[j] = fy;
-        o.fz[j] = fz;
+        o.pos[j] = rec;
         o.wr[j] = wr;
         if (shape) o.wi[j] = wi;
       }
@@ -544,27 +544,51 @@ constexpr int kScanT = 1024;
 constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanT * kScanPer;
 
+// exclusive scan of one value per thread across the block: a scan within
+// each wavefront (shuffles), then a scan of the wavefront totals.  sh holds
+// kScanT / 64 + 1 values.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
-  sh[threadIdx.x] = v;
+  constexpr int kWaves = kScanT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) sh[wave] = inc;
   __syncthreads();
-  for (int o = 1; o < kScanT; o <<= 1) {
-    const uint32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
+  if (wave == 0) {
+    const uint32_t t = lane < kWaves ? sh[lane] : 0u;
+    const uint32_t ti = wave_inclusive_scan(t);
+    if (lane < kWaves) sh[lane] = ti - t;
+    if (lane == kWaves - 1) sh[kWaves] = ti;
   }
-  total = sh[kScanT - 1];
-  const uint32_t r = sh[threadIdx.x] - v;
   __syncthreads();
+  total = sh[kWaves];
+  const uint32_t r = sh[wave] + inc - v;
+  __syncthreads();  // sh may be reused on return
   return r;
 }
 
+// the kScanPer values of one thread (zeros past n); 16-byte loads when the
+// whole run is in range (base is a multiple of kScanPer)
+__device__ __forceinline__ void scan_load(const uint32_t* in, int64_t base, int64_t n, uint32_t* v) {
+  static_assert(kScanPer == 8, "two 16-byte loads per thread");
+  if (base + kScanPer <= n) {
+    const uint4 a = *reinterpret_cast<const uint4*>(in + base);
+    const uint4 b = *reinterpret_cast<const uint4*>(in + base + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = base + k < n ? in[base + k] : 0u;
+  }
+}
+
 __global__ void __launch_bounds__(kScanT) scan_reduce_kernel(const uint32_t* in, int64_t n, uint32_t* bsum) {
-  __shared__ uint32_t sh[kScanT];
+  __shared__ uint32_t sh[kScanT / 64 + 1];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk + static_cast<int64_t>(threadIdx.x) * kScanPer;
+  uint32_t v[kScanPer];
+  scan_load(in, base, n, v);
   uint32_t s = 0;
-  for (int k = 0; k < kScanPer; ++k)
-    if (base + k < n) s += in[base + k];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) s += v[k];
   uint32_t tot;
   block_exclusive_scan(s, sh, tot);
   if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -572,7 +596,7 @@ __global__ void __launch_bounds__(kScanT) scan_reduce_kernel(const uint32_t* in,
 
 __global__ void __launch_bounds__(kScanT) scan_blocks_kernel(uint32_t* bsum, int nb) {
   // single block: exclusive scan of nb block sums in place; bsum[nb] = grand total
-  __shared__ uint32_t sh[kScanT];
+  __shared__ uint32_t sh[kScanT / 64 + 1];
   const int per = (nb + kScanT - 1) / kScanT;
   const int lo = threadIdx.x * per, hi = min(nb, lo + per);
   uint32_t s = 0;
@@ -589,19 +613,28 @@ __global__ void __launch_bounds__(kScanT) scan_blocks_kernel(uint32_t* bsum, int
 
 __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, int64_t n, const uint32_t* bsum,
                                                             int nb, uint32_t* out) {
-  __shared__ uint32_t sh[kScanT];
+  __shared__ uint32_t sh[kScanT / 64 + 1];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk + static_cast<int64_t>(threadIdx.x) * kScanPer;
   uint32_t v[kScanPer];
+  scan_load(in, base, n, v);
   uint32_t s = 0;
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0u;
-    s += v[k];
-  }
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) s += v[k];
   uint32_t tot;
   uint32_t run = block_exclusive_scan(s, sh, tot) + bsum[blockIdx.x];
+  uint32_t o[kScanPer];
+#pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < n) out[base + k] = run;
+    o[k] = run;
     run += v[k];
+  }
+  if (base + kScanPer <= n) {  // (in and out may be the same buffer: this thread's values are read above)
+    *reinterpret_cast<uint4*>(out + base) = uint4{o[0], o[1], o[2], o[3]};
+    *reinterpret_cast<uint4*>(out + base + 4) = uint4{o[4], o[5], o[6], o[7]};
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+      if (base + k < n) out[base + k] = o[k];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
 }

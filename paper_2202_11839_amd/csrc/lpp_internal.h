@@ -67,13 +67,18 @@ double prefactor(int m, int L);                 // (2L+1)(L-m)!/(L+m)!
 double cmap_minus_to_legendre(int l, int L);    // (2l+1) int dmu/2 L^4_L L_l
 
 // ---------------------------------------------------------------------------
-// Cell-sorted object records for the gather deposit (structure of arrays).
+// Cell-sorted objects for the gather deposit: the cell and the position in
+// it as one aligned record (one access to store or load), the weights as
+// separate columns.
+template <typename T>
+struct __align__(4 * sizeof(T)) ObjPos {
+  uint32_t key;            // cell index cx + N (cy + N cz)
+  T fx, fy, fz;            // fractional position in the cell, [0, 1)
+};
+
 template <typename T>
 struct GObjSet {
-  uint32_t* key;           // cell index cx + N (cy + N cz)
-  T* fx;                   // fractional position in the cell, [0, 1)
-  T* fy;
-  T* fz;
+  ObjPos<T>* pos;          // one 16-byte (FP32) or 32-byte (FP64) record per object
   T* wr;                   // weight (density set) or w*g1 (shape set)
   T* wi;                   // w*g2 (shape set), unused for the density set
   int64_t n;

@@ -283,6 +283,48 @@ def test_c1_workload_fp64_and_fp32(lpp):
         print(f"c1 {prec}: worst rel err {worst:.2e}")
 
 
+def _series_errors(got, ref):
+    """Largest |GPU - oracle| / scale of each series over the shells with modes (re and im)."""
+    sc = _scales(ref)
+    sel = ref["n_modes"] > 0
+    return {name: float(max((np.abs(np.asarray(got[part][i]) - ref[part][i])[sel] / sc[i][sel]).max()
+                            for part in ("re", "im")))
+            for i, name in enumerate(ref["series"])}
+
+
+def test_per_multipole_error_table(lpp):
+    """The error of every multipole against the oracle, per precision, on the
+    32^3 workload and the 64^3 wedge: each within its tolerance (FP64 1e-9,
+    FP32 1e-4).  The table is printed (pytest -s) and, if LPP_ERROR_TABLE
+    names a file, written there as JSON."""
+    import json
+    import os
+    from synth import WORKLOADS, make_catalogs
+    wl = WORKLOADS["c1"]
+    g, r = make_catalogs(wl, mock=0)
+    cfg = E.Config(mesh=wl["mesh"], box=wl["box"], origin=wl["origin"], observer=wl["observer"],
+                   assignment=wl["assignment"], interlacing=wl["interlacing"], lmax=4, n_kbins=wl["n_kbins"])
+    cases = {"c1": (g, r, dict(mesh_n=wl["mesh"], box_size=wl["box"], box_origin=wl["origin"],
+                               observer=wl["observer"], assignment=wl["assignment"], interlacing=wl["interlacing"],
+                               lmax=4, n_kbins=wl["n_kbins"]), E.mesh64(g, r, cfg))}
+    cases["wedge64"] = _footprint_case("wedge")
+    table = {}
+    for case, (gc, rc, kw, ref) in cases.items():
+        for prec, tol in (("f64", 1e-9), ("f32", 1e-4)):
+            errs = _series_errors(lpp.Plan(precision=prec, **kw).estimate(gc, rc), ref)
+            table[f"{case}_{prec}"] = errs
+            worst = max(errs, key=errs.get)
+            assert errs[worst] <= tol, (case, prec, worst, errs[worst])
+    cols = list(table)
+    print("\n| series | " + " | ".join(cols) + " |")
+    for name in table[cols[0]]:
+        print(f"| {name} | " + " | ".join(f"{table[c][name]:.1e}" for c in cols) + " |")
+    out = os.environ.get("LPP_ERROR_TABLE")
+    if out:
+        with open(out, "w") as f:
+            json.dump(table, f, indent=1)
+
+
 def test_device_catalogs_and_reuse(lpp):
     """Device-resident catalogs (torch tensors) give the same result as host ones, and a
     plan can be reused for catalogs of different sizes (workspace regrowth)."""
