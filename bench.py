@@ -360,7 +360,7 @@ def main():
     SERIAL = args.serial
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the field-parallel sharding is a design note, not code); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

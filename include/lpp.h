@@ -70,7 +70,7 @@ typedef enum {
   LPP_E_WORKSPACE = 6,    /* caller workspace smaller than lpp_workspace_size     */
   LPP_E_NOMEM = 7,        /* device or host allocation failed                     */
   LPP_E_DEVICE = 8,       /* HIP runtime error or no device                       */
-  LPP_E_UNSUPPORTED = 9   /* valid request outside what this build supports       */
+  LPP_E_UNSUPPORTED = 9   /* valid request outside what the library supports      */
 } lpp_status;
 
 enum { LPP_F32 = 0, LPP_F64 = 1 };
