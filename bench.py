@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--emulator", type=int, default=1,
                     help="1: window multipoles of the 512^3 randoms, the plain template path over the 22,000-point "
                          "design and the emulator trained on 20,000 of them (accuracy on the other 2,000, speedup)")
-    ap.add_argument("--emu-epochs", type=int, default=1000)
+    ap.add_argument("--emu-epochs", type=int, default=1500)
     ap.add_argument("--serial", type=int, default=0,
                     help="1: run each estimate's deposits and transforms on one stream (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
