@@ -744,6 +744,103 @@ def test_full_size_512_workload_sampled_outputs(lpp):
         assert np.max(np.abs(g - ref) / scale) <= 1e-4, name
 
 
+def _device_catalog(c, torch, dtype=None):
+    return Catalog(*[None if v is None else torch.tensor(v, device="cuda", dtype=dtype)
+                     for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+
+
+def _rounded_f32(c):
+    """The catalog as the device sees FP32 columns (each value rounded to FP32)."""
+    return Catalog(*[None if v is None else np.asarray(v, dtype=np.float32).astype(np.float64)
+                     for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
+
+
+def _series_scale(r):
+    """Each series' scale (the auto power of its fields before shot-noise
+    subtraction) from a result of the library."""
+    s = r["series"]
+    dd = np.abs(np.asarray(r["re"][s.index("DD_l0")]) + r["shot_dd"])
+    pp = np.abs(np.asarray(r["re"][s.index("PLUS_l0")]) + r["shot_plus"])
+    return [dd if n.startswith("DD") else (np.sqrt(dd * pp) if n.startswith("GD") else pp) for n in s]
+
+
+def test_full_size_1024_workload_counts_scalars_and_precisions(lpp):
+    """The 1024^3 workload (10M galaxies + 50M randoms, TSC + interlacing, 80
+    shells) in the launch configuration bench.py times for it (device-resident
+    FP32 catalogs): mode counts bit-exact and the scalars at 1e-10 against the
+    oracle (on the same FP32 columns), and every multipole of the FP32 path within 1e-4 of its scale of
+    the FP64 path on the same catalogs (the oracle's own FP64 transforms at
+    this size are beyond a test's time)."""
+    import gc
+    import torch
+    from oracle import mesh as OM
+    from synth import WORKLOADS, make_catalogs
+    wl = WORKLOADS["c4"]
+    print(f"[1024^3] generating catalogs", flush=True)
+    gal, ran = make_catalogs(wl, mock=0, grf_mesh=512)
+    dg, dr = _device_catalog(gal, torch, torch.float32), _device_catalog(ran, torch, torch.float32)
+    mk = lambda prec: lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                               interlacing=wl["interlacing"], precision=prec, lmax=4, n_kbins=wl["n_kbins"])
+    res = {}
+    for prec in ("f32", "f64"):
+        print(f"[1024^3] estimate {prec}", flush=True)
+        plan = mk(prec)
+        res[prec] = plan.estimate(dg, dr)
+        del plan
+        gc.collect()
+        torch.cuda.empty_cache()
+    sc = E.scalars(_rounded_f32(gal), _rounded_f32(ran))  # the columns the device read
+    for prec in ("f32", "f64"):
+        for k in ("alpha", "norm_I", "shot_dd", "shot_plus", "sum_w_gal", "sum_w_ran"):
+            assert abs(res[prec][k] - sc[k]) <= 1e-10 * abs(sc[k]), (prec, k)
+    print(f"[1024^3] oracle mode counts", flush=True)
+    num, den = OM.default_dn(wl["mesh"], wl["n_kbins"])
+    counts = OM.mode_counts(wl["mesh"], wl["n_kbins"], num, den)
+    for prec in ("f32", "f64"):
+        assert list(res[prec]["n_modes"]) == list(counts), prec
+    r32, r64 = res["f32"], res["f64"]
+    assert r32["series"] == r64["series"]
+    sel = counts > 0
+    for i, (name, sc_i) in enumerate(zip(r64["series"], _series_scale(r64))):
+        for part in ("re", "im"):
+            err = np.abs(np.asarray(r32[part][i]) - np.asarray(r64[part][i]))[sel] / sc_i[sel]
+            assert err.max() <= 1e-4, (name, part, err.max())
+
+
+def test_full_size_256_batch_matches_single_estimates(lpp):
+    """bench.py's batch at 256^3 (8 of the 64 mocks over the 0.2M-2M galaxy
+    ladder, 10x randoms, device-resident FP32) through one captured graph:
+    each mock's scalars at 1e-10 and mode counts bit-exactly against the
+    oracle, and every multipole equal to the same mock's single estimate
+    within 1e-6 of its scale (the two differ only in where the randoms'
+    weight scale is read)."""
+    import torch
+    from oracle import mesh as OM
+    from synth import WORKLOADS, c3_sizes, make_catalogs
+    wl = WORKLOADS["c3"]
+    ladder = c3_sizes(64)
+    pick = sorted(set(int(round(x)) for x in np.linspace(0, 63, 8)))
+    cats = [make_catalogs(wl, mock=i, n_gal=ladder[i], n_ran=10 * ladder[i]) for i in pick]
+    dev = [(_device_catalog(g, torch, torch.float32), _device_catalog(r, torch, torch.float32)) for g, r in cats]
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision="f32", lmax=4, n_kbins=wl["n_kbins"])
+    outs = plan.estimate_batch([d[0] for d in dev], [d[1] for d in dev])
+    num, den = OM.default_dn(wl["mesh"], wl["n_kbins"])
+    counts = OM.mode_counts(wl["mesh"], wl["n_kbins"], num, den)
+    sel = counts > 0
+    for (g, r), (dg, dr), o in zip(cats, dev, outs):
+        assert not isinstance(o, Exception), o
+        sc = E.scalars(_rounded_f32(g), _rounded_f32(r))  # the columns the device read
+        for k in ("alpha", "norm_I", "shot_dd", "shot_plus", "sum_w_gal", "sum_w_ran"):
+            assert abs(o[k] - sc[k]) <= 1e-10 * abs(sc[k]), k
+        assert list(o["n_modes"]) == list(counts)
+        single = plan.estimate(dg, dr)
+        for i, (name, sc_i) in enumerate(zip(single["series"], _series_scale(single))):
+            for part in ("re", "im"):
+                err = np.abs(np.asarray(o[part][i]) - np.asarray(single[part][i]))[sel] / sc_i[sel]
+                assert err.max() <= 1e-6, (name, part, err.max())
+
+
 def test_known_spectrum_recovery_on_the_gpu(lpp):
     """The GPU estimator against the paper's closed forms rather than the
     oracle: lattice catalogs of a Gaussian field with tidal shapes
