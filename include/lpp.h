@@ -231,7 +231,10 @@ lpp_status lpp_template_plain(const double* pfid, double k_min, double k_max, in
  * squared error with Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Every matrix
  * product runs on the matrix cores with BF16 operands and FP32 accumulation;
  * parameters, gradients and moments are FP32, and a BF16 copy of the
- * parameters (round to nearest even) feeds the products.  Parameter layout
+ * parameters (round to nearest even) feeds the products.  In the forward
+ * pass each layer input a enters as two BF16 operands, hi = bf16(a) and
+ * lo = bf16(a - hi) (two products into one accumulator); the backward
+ * products use the hi halves.  Parameter layout
  * (lpp_mlp_get_params): for each layer l, W_l [widths[l+1]][widths[l]]
  * row-major (y = x W^T + b), then b_l.  Initial values: uniform in
  * +-1/sqrt(fan-in) from a splitmix64 stream of `seed`.  All device arrays are

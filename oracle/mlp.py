@@ -6,9 +6,12 @@ hidden layers, output y = z_{L-1}; loss = mean over batch and outputs of
 (y - t)^2; gradients by the chain rule written out layer by layer; Adam
 (Kingma & Ba 2015) with beta1 0.9, beta2 0.999, eps 1e-8 and bias correction.
 
-With ``bf16=True`` the operands of every matrix product are rounded to BF16
-(round to nearest even, as the device does) while all sums stay FP64: the
-weights, the layer inputs and the back-propagated deltas.
+With ``bf16=True`` the operands of the matrix products are BF16 (round to
+nearest even, as the device does) while all sums stay FP64: the weights and
+the back-propagated deltas are rounded to BF16; in the forward pass each
+layer input a enters as the sum of two BF16 values, hi = bf16(a) and
+lo = bf16(a - hi) (about 16 significant bits); the weight gradients use the
+hi halves.
 """
 from __future__ import annotations
 
@@ -21,6 +24,12 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def bf16_split(x: np.ndarray) -> np.ndarray:
+    """hi + lo with hi = bf16(x), lo = bf16(x - hi)."""
+    hi = bf16_round(x)
+    return hi + bf16_round(np.asarray(x, dtype=np.float64) - hi)
 
 
 def unpack(params: np.ndarray, widths):
@@ -42,12 +51,13 @@ def _sigmoid(z):
 
 def forward(params, widths, X, bf16=False, keep=False):
     rnd = bf16_round if bf16 else (lambda v: v)
+    split = bf16_split if bf16 else (lambda v: v)
     layers = unpack(np.asarray(params, dtype=np.float64), widths)
     a = np.asarray(X, dtype=np.float64)
     acts, pres = [], []
     for l, (W, b) in enumerate(layers):
         acts.append(a)
-        z = rnd(a) @ rnd(W).T + b
+        z = split(a) @ rnd(W).T + b
         pres.append(z)
         a = z * _sigmoid(z) if l + 1 < len(layers) else z
     return (a, acts, pres) if keep else a

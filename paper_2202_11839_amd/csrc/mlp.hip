@@ -3,7 +3,12 @@
 // mean-squared-error loss and Adam.  Every matrix product runs on the
 // matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
 // accumulation); parameters, gradients and Adam moments are FP32, with a
-// BF16 copy of the weights refreshed by every update.
+// BF16 copy of the weights refreshed by every update.  In the forward pass
+// each layer input a is carried as two BF16 values, hi = bf16(a) and
+// lo = bf16(a - hi), and multiplied by the BF16 weights with two MFMAs
+// (hi, then lo, into the same FP32 accumulator): the inputs keep about 16
+// significant bits instead of 8, which is what the emulator's output
+// precision is limited by.  The backward products use the hi halves.
 //
 // Layouts: activations row-major [batch][width]; weights W_l [w_{l+1}][w_l]
 // (y = x W^T + b).  One 256-thread workgroup computes a 32 x 32 tile of the
@@ -33,7 +38,8 @@ struct lpp_mlp_s {
   float* G = nullptr;      // gradients
   float* M1 = nullptr;     // Adam first moments
   float* M2 = nullptr;     // Adam second moments
-  uint16_t* A[9] = {nullptr};  // BF16 layer inputs [max_batch][w_l], l = 0..nl-1
+  uint16_t* A[9] = {nullptr};  // BF16 layer inputs [max_batch][w_l], l = 0..nl-1 (hi halves)
+  uint16_t* Alo[9] = {nullptr};  // their lo halves (forward only)
   float* Z[8] = {nullptr};     // FP32 pre-activations [max_batch][w_{l+1}]
   float* D[8] = {nullptr};     // FP32 deltas dL/dZ_l
   uint16_t* Db[8] = {nullptr}; // BF16 copies of the deltas
@@ -58,6 +64,12 @@ __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
   u += 0x7FFFu + ((u >> 16) & 1u);
   return static_cast<uint16_t>(u >> 16);
 }
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+// x = hi + lo to about 16 significant bits (x - hi is exact in FP32)
+__device__ __forceinline__ void f2bf_split(float x, uint16_t& hi, uint16_t& lo) {
+  hi = f2bf(x);
+  lo = f2bf(x - bf2f(hi));
+}
 __device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 enum Epi { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DELTA = 2, EPI_PLAIN = 3 };
@@ -65,31 +77,57 @@ enum Epi { EPI_HIDDEN = 0, EPI_OUT = 1, EPI_DELTA = 2, EPI_PLAIN = 3 };
 struct EpiArgs {
   const float* bias;     // HIDDEN / OUT
   float* zout;           // HIDDEN: pre-activation; OUT: output; DELTA: delta; PLAIN: result
-  uint16_t* bout;        // HIDDEN: activation (bf16); DELTA: delta (bf16)
+  uint16_t* bout;        // HIDDEN: activation (bf16 hi half); DELTA: delta (bf16)
+  uint16_t* blo;         // HIDDEN: activation (bf16 lo half)
   const float* zprev;    // DELTA: pre-activation of the layer the delta belongs to
   int64_t ld;            // row stride of zout / bout / zprev
 };
 
-// C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
+// C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak] (+ Alo[m sam + k sak]
+// when Alo is not null), B(k, n) = B[k sbk + n sbn]
 template <int EPI>
-__global__ void __launch_bounds__(kT) gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int64_t sam,
-                                                     int64_t sak, const uint16_t* __restrict__ B, int64_t sbk,
-                                                     int64_t sbn, EpiArgs e) {
+__global__ void __launch_bounds__(kT) gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A,
+                                                     const uint16_t* __restrict__ Alo, int64_t sam, int64_t sak,
+                                                     const uint16_t* __restrict__ B, int64_t sbk, int64_t sbn,
+                                                     EpiArgs e) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.x * 32 + (wave >> 1) * 16, n0 = blockIdx.y * 32 + (wave & 1) * 16;
   const int am = m0 + (lane & 15), bn = n0 + (lane & 15), kq = (lane >> 4) * 8;
   f32x4 c = {0.f, 0.f, 0.f, 0.f};
+  const bool split = Alo != nullptr;
+  // the 8 k-values of a lane are contiguous and 16-byte aligned when the
+  // operand runs along k from a 16-byte aligned base with a row stride that
+  // is a multiple of 8: one 16-byte load instead of eight
+  const auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const bool avec = sak == 1 && sam % 8 == 0 && al16(A) && (!split || al16(Alo));
+  const bool bvec = sbk == 1 && sbn % 8 == 0 && al16(B);
   for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 a, b;
+    bf16x8 a, al, b;
+    const bool kfull = k0 + kq + 8 <= K;
+    if (avec && kfull && am < M) {
+      const int64_t o = am * sam + k0 + kq;
+      a = *reinterpret_cast<const bf16x8*>(A + o);
+      if (split) al = *reinterpret_cast<const bf16x8*>(Alo + o);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + kq + i;
-      const uint16_t av = (am < M && k < K) ? A[am * sam + k * sak] : 0;
-      const uint16_t bv = (bn < N && k < K) ? B[k * sbk + bn * sbn] : 0;
-      a[i] = __builtin_bit_cast(__bf16, av);
-      b[i] = __builtin_bit_cast(__bf16, bv);
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        const bool in = am < M && k < K;
+        a[i] = __builtin_bit_cast(__bf16, in ? A[am * sam + k * sak] : static_cast<uint16_t>(0));
+        al[i] = __builtin_bit_cast(__bf16, (in && split) ? Alo[am * sam + k * sak] : static_cast<uint16_t>(0));
+      }
+    }
+    if (bvec && kfull && bn < N) {
+      b = *reinterpret_cast<const bf16x8*>(B + bn * sbn + k0 + kq);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + kq + i;
+        b[i] = __builtin_bit_cast(__bf16, (bn < N && k < K) ? B[k * sbk + bn * sbn] : static_cast<uint16_t>(0));
+      }
     }
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    if (split) c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, c, 0, 0, 0);
   }
   const int col = n0 + (lane & 15);
 #pragma unroll
@@ -101,7 +139,7 @@ __global__ void __launch_bounds__(kT) gemm_bf16_kernel(int M, int N, int K, cons
     if (EPI == EPI_HIDDEN) {
       v += e.bias[col];
       e.zout[o] = v;
-      e.bout[o] = f2bf(v * sigm(v));
+      f2bf_split(v * sigm(v), e.bout[o], e.blo[o]);
     } else if (EPI == EPI_OUT) {
       e.zout[o] = v + e.bias[col];
     } else if (EPI == EPI_DELTA) {
@@ -115,11 +153,12 @@ __global__ void __launch_bounds__(kT) gemm_bf16_kernel(int M, int N, int K, cons
   }
 }
 
-// rows of X (FP32, [n][w]) -> BF16 copies
-__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y) {
+// rows of X (FP32, [n][w]) -> BF16 hi and lo halves
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t* __restrict__ y,
+                               uint16_t* __restrict__ ylo) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    y[i] = f2bf(x[i]);
+    f2bf_split(x[i], y[i], ylo[i]);
 }
 
 // loss = mean (Y - T)^2, dY = 2 (Y - T) / (B w); one block, FP64 sum in fixed order
@@ -184,7 +223,8 @@ __global__ void bump_kernel(int* step) {
 // batch0 = (*step - step_base) * B
 __global__ void gather_rows_kernel(const float* __restrict__ X, const float* __restrict__ T, int win, int wout,
                                    const int* __restrict__ perm, const int* __restrict__ step, int step_base, int B,
-                                   float* __restrict__ Xb, uint16_t* __restrict__ Ab, float* __restrict__ Tb) {
+                                   float* __restrict__ Xb, uint16_t* __restrict__ Ab, uint16_t* __restrict__ Alo,
+                                   float* __restrict__ Tb) {
   const int64_t b0 = static_cast<int64_t>(*step - step_base) * B;
   const int64_t nx = static_cast<int64_t>(B) * win, nt = static_cast<int64_t>(B) * wout;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nx + nt;
@@ -193,7 +233,7 @@ __global__ void gather_rows_kernel(const float* __restrict__ X, const float* __r
       const int64_t r = i / win, c = i % win;
       const float v = X[static_cast<int64_t>(perm[b0 + r]) * win + c];
       Xb[i] = v;
-      Ab[i] = f2bf(v);
+      f2bf_split(v, Ab[i], Alo[i]);
     } else {
       const int64_t j = i - nx, r = j / wout, c = j % wout;
       Tb[j] = T[static_cast<int64_t>(perm[b0 + r]) * wout + c];
@@ -302,10 +342,10 @@ __global__ void emu_outputs_kernel(EmuArgs a, const double* __restrict__ params,
 }
 
 template <int EPI>
-hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
-                int64_t sbk, int64_t sbn, const EpiArgs& e) {
+hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, const uint16_t* Alo, int64_t sam, int64_t sak,
+                const uint16_t* B, int64_t sbk, int64_t sbn, const EpiArgs& e) {
   dim3 grid((M + 31) / 32, (N + 31) / 32);
-  gemm_bf16_kernel<EPI><<<grid, kT, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, e);
+  gemm_bf16_kernel<EPI><<<grid, kT, 0, st>>>(M, N, K, A, Alo, sam, sak, B, sbk, sbn, e);
   return hipGetLastError();
 }
 
@@ -321,10 +361,11 @@ hipError_t forward(lpp_mlp_s* m, int B, float* Y) {
     if (l + 1 < m->nl) {
       a.zout = m->Z[l];
       a.bout = m->A[l + 1];
-      e = gemm<EPI_HIDDEN>(m->stream, B, out, in, m->A[l], in, 1, W, 1, in, a);
+      a.blo = m->Alo[l + 1];
+      e = gemm<EPI_HIDDEN>(m->stream, B, out, in, m->A[l], m->Alo[l], in, 1, W, 1, in, a);
     } else {
       a.zout = Y ? Y : m->Z[l];
-      e = gemm<EPI_OUT>(m->stream, B, out, in, m->A[l], in, 1, W, 1, in, a);
+      e = gemm<EPI_OUT>(m->stream, B, out, in, m->A[l], m->Alo[l], in, 1, W, 1, in, a);
     }
   }
   return e;
@@ -346,7 +387,7 @@ hipError_t train_step(lpp_mlp_s* m, int B, const float* T, const float* lr_sched
     EpiArgs g{};
     g.zout = m->G + m->off_w[l];
     g.ld = in;
-    e = gemm<EPI_PLAIN>(m->stream, out, in, B, m->Db[l], 1, out, m->A[l], in, 1, g);
+    e = gemm<EPI_PLAIN>(m->stream, out, in, B, m->Db[l], nullptr, 1, out, m->A[l], in, 1, g);
     if (e != hipSuccess) break;
     bias_grad_kernel<<<(out + 255) / 256, 256, 0, m->stream>>>(m->D[l], B, out, m->G + m->off_b[l]);
     e = hipGetLastError();
@@ -357,7 +398,7 @@ hipError_t train_step(lpp_mlp_s* m, int B, const float* T, const float* lr_sched
       d.bout = m->Db[l - 1];
       d.zprev = m->Z[l - 1];
       d.ld = in;
-      e = gemm<EPI_DELTA>(m->stream, B, in, out, m->Db[l], out, 1, m->Pb + m->off_w[l], in, 1, d);
+      e = gemm<EPI_DELTA>(m->stream, B, in, out, m->Db[l], nullptr, out, 1, m->Pb + m->off_w[l], in, 1, d);
     }
   }
   if (e == hipSuccess) {
@@ -431,7 +472,8 @@ lpp_status lpp_mlp_create(const int32_t* widths, int32_t n_layers, int64_t max_b
   bool ok = dalloc(m, &m->P, off) && dalloc(m, &m->Pb, off) && dalloc(m, &m->G, off) && dalloc(m, &m->M1, off) &&
             dalloc(m, &m->M2, off) && dalloc(m, &m->loss, 1) && dalloc(m, &m->step, 1);
   for (int l = 0; l < n_layers && ok; ++l) {
-    ok = dalloc(m, &m->A[l], max_batch * widths[l]) && dalloc(m, &m->Z[l], max_batch * widths[l + 1]) &&
+    ok = dalloc(m, &m->A[l], max_batch * widths[l]) && dalloc(m, &m->Alo[l], max_batch * widths[l]) &&
+         dalloc(m, &m->Z[l], max_batch * widths[l + 1]) &&
          dalloc(m, &m->D[l], max_batch * widths[l + 1]) && dalloc(m, &m->Db[l], max_batch * widths[l + 1]);
   }
   ok = ok && dalloc(m, &m->Xb, max_batch * widths[0]) && dalloc(m, &m->Tb, max_batch * widths[n_layers]);
@@ -507,7 +549,7 @@ lpp_status lpp_mlp_forward(lpp_mlp m, const float* X, int64_t B, float* Y) {
   if (!m || !X || !Y || B < 0 || B > m->max_batch) return LPP_E_INVALID;
   if (B == 0) return LPP_OK;
   const int64_t n = B * m->w[0];
-  to_bf16_kernel<<<blocks_for(n), kT, 0, m->stream>>>(X, n, m->A[0]);
+  to_bf16_kernel<<<blocks_for(n), kT, 0, m->stream>>>(X, n, m->A[0], m->Alo[0]);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = forward(m, static_cast<int>(B), Y);
   return status_of(e);
@@ -516,7 +558,7 @@ lpp_status lpp_mlp_forward(lpp_mlp m, const float* X, int64_t B, float* Y) {
 lpp_status lpp_mlp_train_step(lpp_mlp m, const float* X, const float* T, int64_t B, float lr, float* loss_host) {
   if (!m || !X || !T || B < 1 || B > m->max_batch || !(lr >= 0.0f)) return LPP_E_INVALID;
   const int64_t n = B * m->w[0];
-  to_bf16_kernel<<<blocks_for(n), kT, 0, m->stream>>>(X, n, m->A[0]);
+  to_bf16_kernel<<<blocks_for(n), kT, 0, m->stream>>>(X, n, m->A[0], m->Alo[0]);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = train_step(m, static_cast<int>(B), T, nullptr, lr);
   if (e == hipSuccess && loss_host) {
@@ -570,7 +612,7 @@ lpp_status lpp_emulator_predict(lpp_mlp m, const double* params, int64_t n, int3
     emu_inputs_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(a, params + 5 * r0, B, m->Xb);
     e = hipGetLastError();
     if (e != hipSuccess) break;
-    to_bf16_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(m->Xb, 5 * B, m->A[0]);
+    to_bf16_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(m->Xb, 5 * B, m->A[0], m->Alo[0]);
     e = forward(m, static_cast<int>(B), nullptr);
     if (e != hipSuccess) break;
     emu_outputs_kernel<<<blocks_for(B * 5 * n_k), kT, 0, m->stream>>>(a, params + 5 * r0, m->Z[m->nl - 1], B, mean,
@@ -627,7 +669,7 @@ lpp_status lpp_mlp_fit(lpp_mlp m, const float* X, const float* T, int64_t n, int
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       gather_rows_kernel<<<blocks_for(static_cast<int64_t>(batch) * (m->w[0] + m->w[m->nl])), kT, 0, cap>>>(
-          X, T, m->w[0], m->w[m->nl], m->perm, m->step, base, batch, m->Xb, m->A[0], m->Tb);
+          X, T, m->w[0], m->w[m->nl], m->perm, m->step, base, batch, m->Xb, m->A[0], m->Alo[0], m->Tb);
       e = hipGetLastError();
       if (e == hipSuccess) e = train_step(m, batch, m->Tb, m->lr, 0.0f);
       const hipError_t e2 = hipStreamEndCapture(cap, &g);

@@ -13,6 +13,18 @@ def test_bf16_round_to_nearest_even():
     assert abs(got[6] - 1e-30) <= 2 ** -8 * 1e-30
 
 
+def test_bf16_split_carries_sixteen_bits():
+    """hi + lo reproduces values of up to 16 significant bits exactly and
+    every FP32 value to within 2^-16 of its magnitude."""
+    x = np.array([1 + 2.0 ** -8 + 2.0 ** -12, 3.0 + 2.0 ** -14, -0.7 * (1 + 2.0 ** -15)])
+    exact = np.array([1 + 2.0 ** -8 + 2.0 ** -12, 3.0 + 2.0 ** -14])
+    assert np.array_equal(O.bf16_split(exact), exact)
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal(10000).astype(np.float32).astype(np.float64) * 10.0 ** rng.integers(-3, 4, 10000)
+    assert np.all(np.abs(O.bf16_split(y) - y) <= 2.0 ** -16 * np.abs(y))
+    assert np.abs(O.bf16_split(x) - x).max() <= 2.0 ** -16
+
+
 def test_gradients_match_finite_differences():
     rng = np.random.default_rng(4)
     widths = [3, 5, 4, 2]
