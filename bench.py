@@ -128,12 +128,13 @@ def strided_pass_bytes(pos, wl):
 def strided_kernel_name(n, tuning):
     """The instantiation(s) of the FFT kernel that run the y and z passes:
     <float, N, lines per workgroup, along-x = false, non-temporal accesses>."""
-    cols, st = tuning["fft_cols_yz"], tuning["fft_streaming"]
-    nt = [bool(st & 8 and st & b) for b in (2, 4)]
-    name = lambda f: "fft_zb_kernel<float, %d, %d, false, %s>" % (n, cols, "true" if f else "false")
-    if nt[0] == nt[1]:
-        return name(nt[0]) + " (y and z passes)"
-    return "%s (y pass), %s (z pass)" % (name(nt[0]), name(nt[1]))
+    st = tuning["fft_streaming"]
+    y = (tuning["fft_cols_y"], bool(st & 8 and st & 2))
+    z = (tuning["fft_cols_z"], bool(st & 8 and st & 4))
+    name = lambda c: "fft_zb_kernel<float, %d, %d, false, %s>" % (n, c[0], "true" if c[1] else "false")
+    if y == z:
+        return name(y) + " (y and z passes)"
+    return "%s (y pass), %s (z pass)" % (name(y), name(z))
 
 
 def committed_traffic():

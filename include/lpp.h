@@ -285,7 +285,8 @@ lpp_status lpp_emulator_predict(lpp_mlp mlp, const double* params, int64_t n, in
  * sums (the transforms and the deposit are unchanged bit for bit). */
 typedef struct {
   int32_t fft_rows_x;      /* x pass: lines per workgroup, 8 or 16 (8 z-values of 1 or 2 y) */
-  int32_t fft_cols_yz;     /* y and z passes: lines per workgroup, 8 or 16                  */
+  int32_t fft_cols_y;      /* y pass: lines per workgroup, 8 or 16 (8 z-values of 1 or 2 x) */
+  int32_t fft_cols_z;      /* z pass: lines per workgroup, 8 or 16 (columns x of one y)     */
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
   int32_t gather_density;  /* density fields per deposit pass, 1 .. 8 (FP64: 1 .. 4)        */
   int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64: 1 .. 2)          */
@@ -296,7 +297,7 @@ typedef struct {
   int32_t fft_streaming;   /* 8 + a bit mask of the passes of the 3D transform (1 x, 2 y, 4 z)
                               that use non-temporal loads and stores; 0 = the default
                               (x and z; y too when its workgroups read runs of 128 bytes
-                              or more: FP32 with 16 lines, or FP64)                       */
+                              or more: FP32 with 16 y lines, or FP64)                     */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

@@ -29,7 +29,7 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_mlp_create",
            "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
            "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit", "lpp_emulator_encode", "lpp_emulator_predict"]
-TUNING_FIELDS = ["fft_rows_x", "fft_cols_yz", "bin_blocks", "gather_density", "gather_shape", "serial",
+TUNING_FIELDS = ["fft_rows_x", "fft_cols_y", "fft_cols_z", "bin_blocks", "gather_density", "gather_shape", "serial",
                  "fft_streaming"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 

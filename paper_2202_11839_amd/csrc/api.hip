@@ -573,8 +573,8 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
     if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x, streaming(p));
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_yz, streaming(p));
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_yz, streaming(p));
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_y, streaming(p));
+    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_z, streaming(p));
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
     return e;
   };
@@ -866,7 +866,8 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
   auto fft = [&](void* m, const FftPrune& pr) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int axis = 0; axis < 3 && e == hipSuccess; ++axis)
-      e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st, axis == 0 ? p->tune.fft_rows_x : p->tune.fft_cols_yz,
+      e = launch_fft_axis_zb<T>(m, N, p->d_tw, axis, pr, st,
+                                axis == 0 ? p->tune.fft_rows_x : (axis == 1 ? p->tune.fft_cols_y : p->tune.fft_cols_z),
                                 streaming(p));
     return e;
   };
@@ -1052,11 +1053,12 @@ lpp_tuning resolved_tuning(const lpp_plan_s* p) {
   const bool f64 = p->cfg.precision == LPP_F64;
   lpp_tuning t = p->tune;
   if (t.fft_rows_x <= 0) t.fft_rows_x = zb_default_lines(N, f64, 0);
-  if (t.fft_cols_yz <= 0) t.fft_cols_yz = zb_default_lines(N, f64, 1);
+  if (t.fft_cols_y <= 0) t.fft_cols_y = zb_default_lines(N, f64, 1);
+  if (t.fft_cols_z <= 0) t.fft_cols_z = zb_default_lines(N, f64, 2);
   if (t.bin_blocks <= 0) t.bin_blocks = bin_blocks(N);
   if (t.gather_density <= 0) t.gather_density = max_density_fields(p);
   if (t.gather_shape <= 0) t.gather_shape = max_shape_fields(p);
-  if (t.fft_streaming <= 0) t.fft_streaming = 8 | zb_default_streaming(N, f64, t.fft_cols_yz);
+  if (t.fft_streaming <= 0) t.fft_streaming = 8 | zb_default_streaming(N, f64, t.fft_cols_y);
   return t;
 }
 
@@ -1064,7 +1066,8 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   const int N = p->cfg.mesh_n;
   const bool f64 = p->cfg.precision == LPP_F64;
   if (t.fft_rows_x != 0 && !zb_lines_supported(N, f64, 0, t.fft_rows_x)) return false;
-  if (t.fft_cols_yz != 0 && !zb_lines_supported(N, f64, 1, t.fft_cols_yz)) return false;
+  if (t.fft_cols_y != 0 && !zb_lines_supported(N, f64, 1, t.fft_cols_y)) return false;
+  if (t.fft_cols_z != 0 && !zb_lines_supported(N, f64, 2, t.fft_cols_z)) return false;
   if (t.bin_blocks != 0 && (t.bin_blocks < kMinBinBlocks || t.bin_blocks > kMaxBinBlocks)) return false;
   if (t.gather_density < 0 || t.gather_density > max_density_fields(p)) return false;
   if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
@@ -1080,7 +1083,7 @@ std::string tuning_key(const lpp_plan_s* p) {
   return k;
 }
 
-// One JSON object per line: {"key": "...", "fft_rows_x": a, "fft_cols_yz": b, ...}
+// One JSON object per line: {"key": "...", "fft_rows_x": a, "fft_cols_y": b, "fft_cols_z": c, ...}
 bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t) {
   auto field = [&](const char* name, int32_t& v) {
     const std::string pat = std::string("\"") + name + "\":";
@@ -1098,18 +1101,20 @@ bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t)
   key = line.substr(i + 1, j - i - 1);
   if (!field("serial", t.serial)) t.serial = 0;  // optional
   if (!field("fft_streaming", t.fft_streaming)) t.fft_streaming = 0;
-  return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_yz", t.fft_cols_yz) &&
+  if (!field("fft_cols_z", t.fft_cols_z)) t.fft_cols_z = 0;
+  return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_y", t.fft_cols_y) &&
          field("bin_blocks", t.bin_blocks) && field("gather_density", t.gather_density) &&
          field("gather_shape", t.gather_shape);
 }
 
 std::string tuning_line(const std::string& key, const lpp_tuning& t) {
-  char b[256];
+  char b[320];
   std::snprintf(b, sizeof b,
-                "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_yz\": %d, \"bin_blocks\": %d, "
-                "\"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d, \"fft_streaming\": %d}",
-                key.c_str(), t.fft_rows_x, t.fft_cols_yz, t.bin_blocks, t.gather_density, t.gather_shape, t.serial,
-                t.fft_streaming);
+                "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_y\": %d, \"fft_cols_z\": %d, "
+                "\"bin_blocks\": %d, \"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d, "
+                "\"fft_streaming\": %d}",
+                key.c_str(), t.fft_rows_x, t.fft_cols_y, t.fft_cols_z, t.bin_blocks, t.gather_density, t.gather_shape,
+                t.serial, t.fft_streaming);
   return b;
 }
 
@@ -1200,7 +1205,8 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
     return LPP_OK;
   };
   s = search(&lpp_tuning::fft_rows_x, {8, 16}, {LPP_STAGE_FFT_X});
-  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_yz, {8, 16}, {LPP_STAGE_FFT_YZ});
+  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_y, {8, 16}, {LPP_STAGE_FFT_YZ});
+  if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_z, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});

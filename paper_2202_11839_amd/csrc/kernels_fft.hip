@@ -417,8 +417,12 @@ hipError_t launch_fft_axis(void* mesh, int N, const void* tw, int axis, const Ff
   }
 }
 
+// x pass 8 lines (8 z-values of one row y); y pass 16 in FP32 up to N = 512
+// (two columns x: 128-byte runs), else 8; z pass 8 (runs of 8 x-columns of
+// 64 bytes each are already 512 contiguous bytes, and 8 lines leave four
+// workgroups per CU instead of two).
 int zb_default_lines(int N, bool fp64, int axis) {
-  if (axis == 0 || fp64) return 8;
+  if (axis != 1 || fp64) return 8;
   return N <= 512 ? 16 : 8;
 }
 
@@ -435,9 +439,9 @@ bool zb_lines_supported(int N, bool fp64, int axis, int lines) {
 // 16-byte FP64 values.  With 64-byte runs the other half of each L2 line
 // belongs to the neighbouring workgroup, and the streaming hint lets it be
 // evicted before that workgroup reads it.
-int zb_default_streaming(int N, bool fp64, int lines_yz) {
-  if (lines_yz <= 0) lines_yz = zb_default_lines(N, fp64, 1);
-  const int run = (lines_yz / 8) * 8 * (fp64 ? 16 : 8);
+int zb_default_streaming(int N, bool fp64, int lines_y) {
+  if (lines_y <= 0) lines_y = zb_default_lines(N, fp64, 1);
+  const int run = (lines_y / 8) * 8 * (fp64 ? 16 : 8);
   return 1 | 4 | (run >= 128 ? 2 : 0);
 }
 
@@ -445,7 +449,7 @@ template <typename T>
 hipError_t launch_fft_axis_zb(void* mesh, int N, const void* tw, int axis, const FftPrune& pr, hipStream_t st,
                               int lines, int streaming) {
   if (lines > 0 && !zb_lines_supported(N, sizeof(T) == 8, axis, lines)) return hipErrorInvalidValue;
-  if (streaming < 0) streaming = zb_default_streaming(N, sizeof(T) == 8, axis == 0 ? 0 : lines);
+  if (streaming < 0) streaming = zb_default_streaming(N, sizeof(T) == 8, axis == 1 ? lines : 0);
   const int nt = (streaming >> axis) & 1;
   switch (N) {
     case 16:

@@ -218,12 +218,12 @@ bool fft_lines_supported(int N, bool fp64, int axis, int lines);
 // zb_default_lines): x pass, 8 z-values of 1 or 2 rows y; y pass, 8 z-values
 // of 1 or 2 columns x; z pass, 8 or 16 columns x of one row y.
 // streaming: bit a set = non-temporal loads and stores in pass a (x, y, z);
-// < 0 = zb_default_streaming(N, fp64, lines of the y and z passes)
+// < 0 = zb_default_streaming(N, fp64, lines of the y pass)
 template <typename T>
 hipError_t launch_fft_axis_zb(void* mesh, int N, const void* twiddles, int axis, const FftPrune& pr, hipStream_t st,
                               int lines, int streaming);
 int zb_default_lines(int N, bool fp64, int axis);
-int zb_default_streaming(int N, bool fp64, int lines_yz);
+int zb_default_streaming(int N, bool fp64, int lines_y);
 bool zb_lines_supported(int N, bool fp64, int axis, int lines);
 
 // Binning.  Tables: twiddles (N complex, exp(-2 pi i m/N)), phase (3N+1

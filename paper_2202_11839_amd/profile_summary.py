@@ -4,8 +4,8 @@
     Per-kernel launch count, average and total duration from a
     ``--kernel-trace`` SQLite database (rocprofv3's ``*_results.db``).
 
-``traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB [--kernel PATTERN]``
-    HBM bytes per launch of the kernels whose name contains PATTERN, from a
+``traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB [--kernel REGEX]``
+    HBM bytes per launch of the kernels whose name matches REGEX, from a
     ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the same program.
     Both counters are scaled by what they read for a plain device copy of
     known size (``bench.py --copy-calibration``: 1 GiB read and 1 GiB written
@@ -143,8 +143,9 @@ def main() -> None:
         for r in sorted(rows, key=lambda r: -r[1] * r[4])[:25]:
             print(f"{r[0][:60]:60s} {r[1]:6d} {r[2]:9.3f} {r[3]:9.3f} {r[4]:13.4f}")
         return
-    fetch = [v for n, vs in counter(args.fetch_db, "FETCH_SIZE").items() if args.kernel in n for v in vs]
-    write = [v for n, vs in counter(args.write_db, "WRITE_SIZE").items() if args.kernel in n for v in vs]
+    pat = re.compile(args.kernel)
+    fetch = [v for n, vs in counter(args.fetch_db, "FETCH_SIZE").items() if pat.search(_short(n)) for v in vs]
+    write = [v for n, vs in counter(args.write_db, "WRITE_SIZE").items() if pat.search(_short(n)) for v in vs]
     if not fetch or not write:
         raise SystemExit(f"no launches of {args.kernel!r}")
     sources = args.source or TRAFFIC_SOURCES

@@ -456,7 +456,7 @@ def test_tuning_variants_match_oracle(lpp, prec):
     g, r, kw, ref = _footprint_case("wedge")
     plan = lpp.Plan(precision=prec, **kw)
     tol = 1e-9 if prec == "f64" else 1e-4
-    variants = [dict(fft_rows_x=16), dict(fft_cols_yz=8), dict(fft_cols_yz=16),
+    variants = [dict(fft_rows_x=16), dict(fft_cols_y=8), dict(fft_cols_y=16), dict(fft_cols_z=8), dict(fft_cols_z=16),
                 dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
                 dict(gather_shape=1), dict(gather_shape=2), dict(serial=1), dict(fft_streaming=8),
                 dict(fft_streaming=13)]

@@ -117,16 +117,16 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
-    assert t == {"fft_rows_x": 8, "fft_cols_yz": 16, "bin_blocks": 8192, "gather_density": 8, "gather_shape": 4,
-                 "serial": 0, "fft_streaming": 15}
-    for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_yz=32),
+    assert t == {"fft_rows_x": 8, "fft_cols_y": 16, "fft_cols_z": 8, "bin_blocks": 8192, "gather_density": 8,
+                 "gather_shape": 4, "serial": 0, "fft_streaming": 15}
+    for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_y=32), dict(fft_cols_z=4),
                 dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=5),
                 dict(serial=2), dict(fft_streaming=7), dict(fft_streaming=16)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
-    plan.set_tuning(fft_cols_yz=8, gather_density=2)
-    assert plan.tuning()["fft_cols_yz"] == 8 and plan.tuning()["gather_density"] == 2
+    plan.set_tuning(fft_cols_y=8, gather_density=2)
+    assert plan.tuning()["fft_cols_y"] == 8 and plan.tuning()["gather_density"] == 2
     # the y pass streams by default only when its runs fill 128-byte lines:
     # not with 8 FP32 lines (64-byte runs), always in FP64 (0 = the default)
     assert plan.tuning()["fft_streaming"] == 15
@@ -137,12 +137,13 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     # FP64: the default strided block holds one z-group of one column; more
     # lines than 1024 threads or one CU's LDS allow are refused
     p64 = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f64", lmax=4, n_kbins=50)
-    assert p64.tuning()["fft_cols_yz"] == 8 and p64.tuning()["fft_rows_x"] == 8
+    assert p64.tuning()["fft_cols_y"] == 8 and p64.tuning()["fft_cols_z"] == 8 and p64.tuning()["fft_rows_x"] == 8
     assert p64.tuning()["fft_streaming"] == 15
     assert pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4,
                     n_kbins=50).tuning()["fft_streaming"] == 13
-    with pytest.raises(pkg.LppError):
-        p64.set_tuning(fft_cols_yz=16)
+    for bad in (dict(fft_cols_y=16), dict(fft_cols_z=16)):
+        with pytest.raises(pkg.LppError):
+            p64.set_tuning(**bad)
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_rows_x=16)
     # FP64: at most four density and two shape fields per deposit pass
@@ -152,14 +153,15 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     with pytest.raises(pkg.LppError):
         p64.set_tuning(gather_density=5)
     cache = tmp_path / "tune.jsonl"
-    cache.write_text('{"key": "N256_f32_p3_il1", "fft_rows_x": 8, "fft_cols_yz": 8, "bin_blocks": 1024, '
+    cache.write_text('{"key": "N256_f32_p3_il1", "fft_rows_x": 8, "fft_cols_y": 8, "bin_blocks": 1024, '
                      '"gather_density": 3, "gather_shape": 1}\n'
-                     '{"key": "N512_f32_p3_il1", "fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, '
+                     '{"key": "N512_f32_p3_il1", "fft_rows_x": 16, "fft_cols_y": 8, "fft_cols_z": 16, '
+                     '"bin_blocks": 4096, '
                      '"gather_density": 2, "gather_shape": 1}\n')
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
-    assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_yz": 8, "bin_blocks": 4096, "gather_density": 2,
-                              "gather_shape": 1, "serial": 0, "fft_streaming": 13}
+    assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_y": 8, "fft_cols_z": 16, "bin_blocks": 4096,
+                              "gather_density": 2, "gather_shape": 1, "serial": 0, "fft_streaming": 13}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
 
