@@ -2,12 +2,12 @@
 //
 // Objects are counting-sorted by mesh cell (cell_start[c] .. cell_start[c+1]
 // are the objects whose position lies in cell c).  One workgroup owns a tile
-// of TT^3 mesh nodes; the nodes of the tile can only receive weight from
-// objects in the (TT+3)^3 cells [t0-2, t0+TT] on each axis (the TSC stencil
+// of TX x TT x TT mesh nodes; the nodes of the tile can only receive weight from
+// objects in the cells [t0-2, t0+TX] (x) and [t0-2, t0+TT] (y, z) (the TSC stencil
 // of the grid reaches nodes c-1..c+2 of an object in cell c, the interlaced
 // grid nodes c-1..c+1).  The workgroup stages those objects in LDS (in
 // chunks of CAP objects), computing each object's line-of-sight weighted
-// value once, and every thread then sums the contributions to one x-row of TT
+// value once, and every thread then sums the contributions to one x-row of TX
 // nodes in registers, in a fixed order.  Every node of the mesh is written
 // exactly once with a plain store: no atomics, no separate clearing pass, and
 // the result is bitwise reproducible.
@@ -139,8 +139,8 @@ struct AxisWeights {
   __device__ __forceinline__ T at(int c) const;
 };
 
-constexpr int TT = 8;          // tile edge (nodes)
-constexpr int R = TT + 3;      // region edge (cells t0-2 .. t0+TT)
+constexpr int TT = 8;          // tile edge in y and z (nodes); in x a kernel parameter TX (4 or 8)
+constexpr int R = TT + 3;      // region edge in y and z (cells t0-2 .. t0+TT)
 
 template <typename T, int P>
 __device__ __forceinline__ T AxisWeights<T, P>::at(int c) const {
@@ -174,11 +174,22 @@ constexpr int rows_of() {
   return 3 + K * NF;
 }
 
-template <typename T, int K, int NF>
+// accumulators per thread ([f][copy][component][x]) and per reduction round
+template <int K, int NF, int TX>
+constexpr int nacc_of() {
+  return NF * 2 * K * TX;
+}
+template <int K, int NF, int TX>
+constexpr int round_of() {
+  return nacc_of<K, NF, TX>() % 16 == 0 ? 16 : 8;
+}
+
+template <typename T, int K, int NF, int TX>
 constexpr int cap_of() {
   // the staging buffer must also hold the cross-part reduction rounds and the output rows
-  constexpr int need = (kParts - 1) * kRows * (16 + 1) + 2 * (TT + 1) * kRows;
-  constexpr int base = sizeof(T) == 4 ? 1024 : 640;
+  constexpr int need = (kParts - 1) * kRows * (round_of<K, NF, TX>() + 1) + 2 * (TX + 1) * kRows;
+  // (a 4-node x edge reaches 7 cells of objects in x instead of 11: smaller chunks)
+  constexpr int base = TX == 4 ? (sizeof(T) == 4 ? 640 : 400) : (sizeof(T) == 4 ? 1024 : 640);
   constexpr int rows = rows_of<T, K, NF>();
   return base * rows >= need ? base : (need + rows - 1) / rows;
 }
@@ -199,16 +210,17 @@ __device__ __forceinline__ int64_t node_at(int x, int y, int z, int N, int zbloc
   return zblocked ? zb_index(x, y, z, N) : x + static_cast<int64_t>(N) * (y + static_cast<int64_t>(N) * z);
 }
 // The i-th node that a workgroup stores: node (kx, r % TT, r / TT) of the
-// tile, in memory order, so that consecutive lanes write consecutive
-// addresses: x fastest in the plain layout, z fastest and then x when
-// z-blocked (a tile is TT = 8 runs of 64 contiguous nodes there).
+// tile (kx < TX), in memory order, so that consecutive lanes write
+// consecutive addresses: x fastest in the plain layout, z fastest and then x
+// when z-blocked (a tile is TT runs of 8 TX contiguous nodes there).
+template <int TX>
 __device__ __forceinline__ void store_order(int i, int zblocked, int& kx, int& r) {
   if (zblocked) {
-    kx = (i / TT) % TT;
-    r = (i / (TT * TT)) + TT * (i % TT);
+    kx = (i / TT) % TX;
+    r = (i / (TT * TX)) + TT * (i % TT);
   } else {
-    kx = i % TT;
-    r = i / TT;
+    kx = i % TX;
+    r = i / TX;
   }
 }
 
@@ -216,17 +228,21 @@ __device__ __forceinline__ void store_order(int i, int zblocked, int& kx, int& r
 //        grid -> .y of mesh f (.y is zero without interlacing).
 // K = 2: NF complex (shape) fields; with interlacing grid -> mesh 2f and
 //        interlaced grid -> mesh 2f+1, without it grid -> mesh f.
-template <typename T, int P, int K, int NF>
+// The tile is TX x TT x TT nodes (x, y, z); a 4-node x edge halves the
+// accumulators per thread and the window work per object (most of the 8 x
+// nodes of a row are out of an object's reach) for more tiles.
+template <typename T, int P, int K, int NF, int TX>
 __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
                                                           int N, int lgN, int interlace, T H, T relx, T rely, T relz,
                                                           SpecSet<T, NF> fs, MeshSet<T> out,
                                                           const uint8_t* __restrict__ tile_flags, int zblocked) {
   using T2 = typename V2<T>::type;
-  constexpr int CAP = cap_of<T, K, NF>();
+  constexpr int CAP = cap_of<T, K, NF, TX>();
   constexpr int ROWS = rows_of<T, K, NF>();
-  constexpr int NACC = NF * 2 * K * TT;  // accumulators per thread: [f][copy][component][x]
-  static_assert(NACC % 16 == 0, "reduction rounds of 16");
-  // each region row (cells x in [t0x-2, t0x+TT] at fixed y, z) is at most two
+  constexpr int NACC = nacc_of<K, NF, TX>();  // accumulators per thread: [f][copy][component][x]
+  constexpr int RW = round_of<K, NF, TX>();
+  static_assert(TX == 4 || TX == TT, "x edge of 4 or 8 nodes");
+  // each region row (cells x in [t0x-2, t0x+TX] at fixed y, z) is at most two
   // contiguous ranges of the cell-sorted objects (two when the row wraps)
   __shared__ uint32_t seg_beg[R2][2];
   __shared__ uint32_t seg_cnt[R2];   // objects in the first range
@@ -236,7 +252,7 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   const int copies = (K == 2 && interlace) ? 2 : 1;
   const int nmesh = NF * copies;
 
-  const int nt = N / TT;
+  const int nt = N / TT, ntx = N / TX;
   const int mask = N - 1;
   const int tid = threadIdx.x;
   // Workgroups are dispatched round-robin over the XCDs, each with its own L2.
@@ -246,12 +262,13 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   // gets an even share of the footprint (plain order when nt^2 is not a
   // multiple of kXcds, i.e. N = 16).
   const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-  const int tile = (nt * nt) % kXcds == 0 ? ((local / nt) * kXcds + xcd) * nt + local % nt
+  const int tile = (nt * nt) % kXcds == 0 ? ((local / ntx) * kXcds + xcd) * ntx + local % ntx
                                            : static_cast<int>(blockIdx.x);
-  const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
-  const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
-  // outside the footprint: every node of the tile is zero and is never read
-  if (tile_flags != nullptr && tile_flags[tile] == 0) return;
+  const int tx = tile % ntx, ty = (tile / ntx) % nt, tz = tile / (ntx * nt);
+  const int t0x = tx * TX, t0y = ty * TT, t0z = tz * TT;
+  // outside the footprint (flags of the TT^3 cubes): every node of the tile
+  // is zero and is never read
+  if (tile_flags != nullptr && tile_flags[t0x / TT + nt * (ty + nt * tz)] == 0) return;
 
   if (tid < 64) {
     uint32_t cnt[2];
@@ -263,7 +280,7 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
         const int ly = r % R, lz = r / R;
         const int gy = (t0y - 2 + ly) & mask, gz = (t0z - 2 + lz) & mask;
         const int64_t rowbase = static_cast<int64_t>(N) * (gy + static_cast<int64_t>(N) * gz);
-        const int xa = t0x - 2, xb = t0x + TT;  // inclusive cell range
+        const int xa = t0x - 2, xb = t0x + TX;  // inclusive cell range
         int a0, a1, b0, b1;                       // [a0, a1) and [b0, b1) in x
         if (xa < 0) {
           a0 = N + xa; a1 = N; b0 = 0; b1 = xb + 1;
@@ -295,16 +312,16 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
 
   // empty region: the tile is zero in every output mesh
   if (total == 0) {
-    for (int i = tid; i < kRows * TT; i += kThreads) {
+    for (int i = tid; i < kRows * TX; i += kThreads) {
       int kx, r;
-      store_order(i, zblocked, kx, r);
+      store_order<TX>(i, zblocked, kx, r);
       const int64_t idx = node_at(t0x + kx, t0y + r % TT, t0z + r / TT, N, zblocked);
       for (int m = 0; m < nmesh; ++m) out.m[m][idx] = T2{0, 0};
     }
     return;
   }
 
-  // this thread's node row: (t0x + k, t0y + ny, t0z + nz), k = 0..TT-1.  The kParts threads of a
+  // this thread's node row: (t0x + k, t0y + ny, t0z + nz), k = 0..TX-1.  The kParts threads of a
   // row take one z-offset dz each: region rows y in [ny, ny+3] at z = nz + dz are contiguous.
   const int rowid = tid % kRows, part = tid / kRows;
   const int ny = rowid % TT, nz = rowid / TT;
@@ -375,42 +392,42 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
         for (int q = 0; q < K * NF; ++q) val[q] = su[3 + q][d];
         const AxisWeights<T, P> xw0(ux, w0), xw1(ux - half, w1);
 #pragma unroll
-        for (int kx = 0; kx < TT; ++kx) {
+        for (int kx = 0; kx < TX; ++kx) {
           const T wx0 = xw0.at(kx + 2);  // node kx sits at region coordinate kx + 2
           const T wx1 = xw1.at(kx + 2);
 #pragma unroll
           for (int q = 0; q < NF; ++q)
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-              acc[((q * 2 + 0) * K + c) * TT + kx] += val[q * K + c] * wx0;
-              acc[((q * 2 + 1) * K + c) * TT + kx] += val[q * K + c] * wx1;
+              acc[((q * 2 + 0) * K + c) * TX + kx] += val[q * K + c] * wx0;
+              acc[((q * 2 + 1) * K + c) * TX + kx] += val[q * K + c] * wx1;
             }
         }
       }
     }
     __syncthreads();
   }
-  // combine the kParts partial rows in a fixed order, 16 accumulators per round
-  constexpr int RS = 16 + 1;  // padded against LDS bank conflicts
+  // combine the kParts partial rows in a fixed order, RW accumulators per round
+  constexpr int RS = RW + 1;  // padded against LDS bank conflicts
   T* red = &su[0][0];
 #pragma unroll
-  for (int r0 = 0; r0 < NACC; r0 += 16) {
+  for (int r0 = 0; r0 < NACC; r0 += RW) {
     if (part > 0) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) red[((part - 1) * kRows + rowid) * RS + i] = acc[r0 + i];
+      for (int i = 0; i < RW; ++i) red[((part - 1) * kRows + rowid) * RS + i] = acc[r0 + i];
     }
     __syncthreads();
     if (part == 0) {
 #pragma unroll
       for (int q = 1; q < kParts; ++q)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[r0 + i] += red[((q - 1) * kRows + rowid) * RS + i];
+        for (int i = 0; i < RW; ++i) acc[r0 + i] += red[((q - 1) * kRows + rowid) * RS + i];
     }
     __syncthreads();
   }
   // store each output mesh through LDS: consecutive lanes write consecutive nodes (store_order)
   T2* stage = reinterpret_cast<T2*>(red);
-  static_assert(ROWS * CAP >= 2 * (TT + 1) * kRows, "output staging fits");
+  static_assert(ROWS * CAP >= 2 * (TX + 1) * kRows, "output staging fits");
   // (the loops over fields and copies are unrolled: acc[] is only ever indexed
   // with compile-time constants, which keeps it in registers)
 #pragma unroll
@@ -421,21 +438,21 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
       const int m = K == 1 ? q : q * copies + cpy;
       if (part == 0) {
 #pragma unroll
-        for (int kx = 0; kx < TT; ++kx) {
+        for (int kx = 0; kx < TX; ++kx) {
           T2 v;
           if (K == 1)  // field q: (grid, interlaced grid)
-            v = T2{acc[(q * 2 + 0) * TT + kx], acc[(q * 2 + 1) * TT + kx]};
+            v = T2{acc[(q * 2 + 0) * TX + kx], acc[(q * 2 + 1) * TX + kx]};
           else         // field q, copy cpy: (re, im)
-            v = T2{acc[((q * 2 + cpy) * K + 0) * TT + kx], acc[((q * 2 + cpy) * K + 1) * TT + kx]};
-          stage[rowid * (TT + 1) + kx] = v;
+            v = T2{acc[((q * 2 + cpy) * K + 0) * TX + kx], acc[((q * 2 + cpy) * K + 1) * TX + kx]};
+          stage[rowid * (TX + 1) + kx] = v;
         }
       }
       __syncthreads();
       T2* __restrict__ dst = out.m[m];
-      for (int i = tid; i < kRows * TT; i += kThreads) {
+      for (int i = tid; i < kRows * TX; i += kThreads) {
         int kx, r;
-        store_order(i, zblocked, kx, r);
-        dst[node_at(t0x + kx, t0y + r % TT, t0z + r / TT, N, zblocked)] = stage[r * (TT + 1) + kx];
+        store_order<TX>(i, zblocked, kx, r);
+        dst[node_at(t0x + kx, t0y + r % TT, t0z + r / TT, N, zblocked)] = stage[r * (TX + 1) + kx];
       }
       __syncthreads();
     }
@@ -639,8 +656,18 @@ __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, 
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
 }
 
+// x edge of the deposit tile.  Density passes (K = 1: the randoms, many
+// objects per tile, bound by the row sums) take 4 nodes: half the
+// accumulators and of the window work per object, more workgroups per CU.
+// Shape passes (K = 2: the galaxies only, few objects per tile, bound by the
+// per-tile chain of loads) keep 8, since halving the tile doubles the tiles.
+template <int K>
+constexpr int tile_x() {
+  return K == 1 ? 4 : TT;
+}
+
 template <typename T, int K, int NF>
-hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
+hipError_t dispatch(int p, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
                     const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
   // the line of sight of an object in cell c at fraction f: rel + (c + f) H
   const T H = static_cast<T>(g.los_h), rx = static_cast<T>(g.los_rel[0]), ry = static_cast<T>(g.los_rel[1]),
@@ -652,15 +679,21 @@ hipError_t dispatch(int p, dim3 grid, const GObjSet<T>& o, const uint32_t* start
   for (int m = 0; m < nm; ++m) ms.m[m] = static_cast<typename V2<T>::type*>(meshes[m]);
   int lg = 0;
   while ((1 << lg) < g.N) ++lg;
+  constexpr int TX = tile_x<K>();
+  const int nt = g.N / TT;
+  const dim3 grid(static_cast<unsigned>(g.N / TX) * nt * nt);
   switch (p) {
     case 1:
-      gather_kernel<T, 1, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
+      gather_kernel<T, 1, K, NF, TX><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                                 tiles, zb);
       break;
     case 2:
-      gather_kernel<T, 2, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
+      gather_kernel<T, 2, K, NF, TX><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                                 tiles, zb);
       break;
     default:
-      gather_kernel<T, 3, K, NF><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms, tiles, zb);
+      gather_kernel<T, 3, K, NF, TX><<<grid, kThreads, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                                 tiles, zb);
       break;
   }
   return hipGetLastError();
@@ -774,28 +807,26 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
   static_assert(TT == kTile && TT == kZb, "footprint tiles are gather tiles and z-groups");
   const int zb = zblocked ? 1 : 0;
   if (g.N % TT != 0) return hipErrorInvalidValue;
-  const int nt = g.N / TT;
-  dim3 grid(static_cast<unsigned>(nt) * nt * nt);
   if (!complex_fields) {
     switch (nf) {
       case 1:
-        return dispatch<T, 1, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        return dispatch<T, 1, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 2:
-        return dispatch<T, 1, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        return dispatch<T, 1, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 3:
-        return dispatch<T, 1, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        return dispatch<T, 1, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       case 4:
-        return dispatch<T, 1, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        return dispatch<T, 1, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
       default:
         break;
     }
     if constexpr (sizeof(T) == 4) {
       static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 4, "real passes of 5 to 8 fields in FP32");
       switch (nf) {
-        case 5: return dispatch<T, 1, 5>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 6: return dispatch<T, 1, 6>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 7: return dispatch<T, 1, 7>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 8: return dispatch<T, 1, 8>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 5: return dispatch<T, 1, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 6: return dispatch<T, 1, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 7: return dispatch<T, 1, 7>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+        case 8: return dispatch<T, 1, 8>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
         default: break;
       }
     }
@@ -803,16 +834,16 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
   }
   switch (nf) {
     case 1:
-      return dispatch<T, 2, 1>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+      return dispatch<T, 2, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
     case 2:
-      return dispatch<T, 2, 2>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+      return dispatch<T, 2, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
     default:
       break;
   }
   if constexpr (sizeof(T) == 4) {
     static_assert(kGatherMaxComplex == 4 && kGatherMaxComplexF64 == 2, "complex passes of 3 and 4 fields in FP32");
-    if (nf == 3) return dispatch<T, 2, 3>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    if (nf == 4) return dispatch<T, 2, 4>(g.p, grid, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    if (nf == 3) return dispatch<T, 2, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    if (nf == 4) return dispatch<T, 2, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
   }
   return hipErrorInvalidValue;
 }
