@@ -288,8 +288,10 @@ typedef struct {
   int32_t fft_cols_y;      /* y pass: lines per workgroup, 8 or 16 (8 z-values of 1 or 2 x) */
   int32_t fft_cols_z;      /* z pass: lines per workgroup, 8 or 16 (columns x of one y)     */
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
-  int32_t gather_density;  /* density fields per deposit pass, 1 .. 8 (FP64: 1 .. 4)        */
-  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64: 1 .. 2)          */
+  int32_t gather_density;  /* density fields per deposit pass, 1 .. 8 (FP64 at N = 1024:
+                              1 .. 4)                                                      */
+  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64 at N = 1024:
+                              1 .. 2)                                                      */
   int32_t serial;          /* 1: deposits and transforms on the plan's stream one after the
                               other; 0: the next pass's deposit runs on a second stream of the
                               plan while the current pass is transformed (profiling with

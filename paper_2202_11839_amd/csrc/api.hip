@@ -150,18 +150,22 @@ int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size(
 
 // Work meshes: one gather pass deposits up to kGatherMaxReal density fields
 // (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per
-// grid): kWork in FP32, kWorkF64 in FP64 (at most kGatherMaxComplexF64 shape
-// fields per pass there).
+// grid) into one of two sets of kWork meshes.  FP64 at N >= 1024 keeps sets
+// of kWorkF64Large (two sets of eight 17 GB meshes and the bases would not
+// fit the device), and with them at most four density and two shape fields
+// per pass.
 constexpr int kWork = 8;
-constexpr int kWorkF64 = 4;
+constexpr int kWorkF64Large = 4;
 static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
-static_assert(kWorkF64 >= kGatherMaxRealF64 && kWorkF64 >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
-int work_meshes(const lpp_plan_s* p) { return p->cfg.precision == LPP_F64 ? kWorkF64 : kWork; }
+static_assert(kWork >= kGatherMaxRealF64 && kWork >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+int work_meshes(const lpp_plan_s* p) {
+  return (p->cfg.precision == LPP_F64 && p->cfg.mesh_n >= 1024) ? kWorkF64Large : kWork;
+}
 int max_density_fields(const lpp_plan_s* p) {
-  return p->cfg.precision == LPP_F64 ? kGatherMaxRealF64 : kGatherMaxReal;
+  return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxRealF64 : kGatherMaxReal, work_meshes(p));
 }
 int max_shape_fields(const lpp_plan_s* p) {
-  return p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex;
+  return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex, work_meshes(p) / 2);
 }
 lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
 // passes of the 3D transform with non-temporal accesses (bit a for pass a), -1 = default

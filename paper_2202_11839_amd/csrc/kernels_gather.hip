@@ -659,11 +659,13 @@ __global__ void __launch_bounds__(kScanT) scan_apply_kernel(const uint32_t* in, 
 // x edge of the deposit tile.  Density passes (K = 1: the randoms, many
 // objects per tile, bound by the row sums) take 4 nodes: half the
 // accumulators and of the window work per object, more workgroups per CU.
-// Shape passes (K = 2: the galaxies only, few objects per tile, bound by the
-// per-tile chain of loads) keep 8, since halving the tile doubles the tiles.
-template <int K>
+// FP32 shape passes (K = 2: the galaxies only, few objects per tile, bound
+// by the per-tile chain of loads) keep 8, since halving the tile doubles the
+// tiles; FP64 shape passes take 4, which leaves registers for four fields
+// per pass instead of two (half the passes).
+template <typename T, int K>
 constexpr int tile_x() {
-  return K == 1 ? 4 : TT;
+  return (K == 1 || sizeof(T) == 8) ? 4 : TT;
 }
 
 template <typename T, int K, int NF>
@@ -679,7 +681,7 @@ hipError_t dispatch(int p, const GObjSet<T>& o, const uint32_t* starts, const Ge
   for (int m = 0; m < nm; ++m) ms.m[m] = static_cast<typename V2<T>::type*>(meshes[m]);
   int lg = 0;
   while ((1 << lg) < g.N) ++lg;
-  constexpr int TX = tile_x<K>();
+  constexpr int TX = tile_x<T, K>();
   const int nt = g.N / TT;
   const dim3 grid(static_cast<unsigned>(g.N / TX) * nt * nt);
   switch (p) {
@@ -820,8 +822,8 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
       default:
         break;
     }
-    if constexpr (sizeof(T) == 4) {
-      static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 4, "real passes of 5 to 8 fields in FP32");
+    {
+      static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 8, "real passes of 5 to 8 fields");
       switch (nf) {
         case 5: return dispatch<T, 1, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
         case 6: return dispatch<T, 1, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
@@ -840,11 +842,9 @@ hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const 
     default:
       break;
   }
-  if constexpr (sizeof(T) == 4) {
-    static_assert(kGatherMaxComplex == 4 && kGatherMaxComplexF64 == 2, "complex passes of 3 and 4 fields in FP32");
-    if (nf == 3) return dispatch<T, 2, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    if (nf == 4) return dispatch<T, 2, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-  }
+  static_assert(kGatherMaxComplex == 4 && kGatherMaxComplexF64 == 4, "complex passes of 3 and 4 fields");
+  if (nf == 3) return dispatch<T, 2, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+  if (nf == 4) return dispatch<T, 2, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
   return hipErrorInvalidValue;
 }
 

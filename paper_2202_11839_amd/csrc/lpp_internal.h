@@ -178,14 +178,14 @@ hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hip
 // cube flags) the tiles that are not flagged are skipped and left unwritten.  Real fields (complex_fields = 0,
 // nf <= kGatherMaxReal, kGatherMaxRealF64 in FP64): mesh q holds field q
 // packed (grid -> real part, interlaced grid -> imaginary part).  Complex
-// fields (nf <= kGatherMaxComplex, kGatherMaxComplexF64 in FP64, whose
-// accumulators take twice the registers):
+// fields (nf <= kGatherMaxComplex, kGatherMaxComplexF64 in FP64, where the
+// tiles are 4 nodes wide in x so that the FP64 accumulators fit):
 // with interlacing mesh 2q holds field q on the grid and mesh 2q+1 on the
 // interlaced grid, without it mesh q holds field q.
 constexpr int kGatherMaxReal = 8;
-constexpr int kGatherMaxRealF64 = 4;
+constexpr int kGatherMaxRealF64 = 8;
 constexpr int kGatherMaxComplex = 4;
-constexpr int kGatherMaxComplexF64 = 2;
+constexpr int kGatherMaxComplexF64 = 4;
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
                          int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,

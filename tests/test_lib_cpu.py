@@ -146,8 +146,11 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
             p64.set_tuning(**bad)
     with pytest.raises(pkg.LppError):
         p64.set_tuning(fft_rows_x=16)
-    # FP64: at most four density and two shape fields per deposit pass
+    # FP64 at N = 1024: at most four density and two shape fields per deposit
+    # pass (two sets of four 17 GB work meshes); up to N = 512 eight and four
     assert p64.tuning()["gather_shape"] == 2 and p64.tuning()["gather_density"] == 4
+    p64s = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f64", lmax=4, n_kbins=50)
+    assert p64s.tuning()["gather_shape"] == 4 and p64s.tuning()["gather_density"] == 8
     with pytest.raises(pkg.LppError):
         p64.set_tuning(gather_shape=3)
     with pytest.raises(pkg.LppError):
