@@ -37,6 +37,18 @@ using dev::sgn_mode;
 using dev::shell_of;
 using dev::V2;
 
+// 1/sqrt(q) for the unit vector of a mode: the hardware reciprocal square
+// root in FP32 (1 ulp; the harmonic weights then carry a few ulp, far below
+// the FP32 path's rounding of the fields), the correctly rounded quotient in
+// FP64
+template <typename T>
+__device__ __forceinline__ T inv_sqrt(int q) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_amdgcn_rsqf(static_cast<float>(q));
+  else
+    return 1.0 / sqrt(static_cast<double>(q));
+}
+
 constexpr int kBinThreads = 256;
 constexpr int kRun = 8;
 constexpr int kMaxBins = 512;
@@ -345,7 +357,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
         const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
         const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
         const int q = nx * nx + ny * ny + nz * nz;
-        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+        const T rq = inv_sqrt<T>(q);
         const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
         if (b != cur[f]) {
           if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
@@ -431,7 +443,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
         const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
                                     wxy * iw[iz]);
         const int q = nx * nx + ny * ny + nz * nz;
-        const T rq = static_cast<T>(1) / sqrt(static_cast<T>(q));
+        const T rq = inv_sqrt<T>(q);
         const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
         const T2 p = KIND == 0 ? cmulc(F, bv[j]) : cmul(F, bv[j]);
         if (b != cur[f]) {
