@@ -125,28 +125,36 @@ def strided_pass_bytes(pos, wl):
     return y_bytes, z_bytes
 
 
-def strided_kernel_name(n, tuning):
+def strided_kernel_name(n, tuning, names_only=False):
     """The instantiation(s) of the FFT kernel that run the y and z passes:
     <float, N, lines per workgroup, along-x = false, non-temporal accesses>."""
     st = tuning["fft_streaming"]
     y = (tuning["fft_cols_y"], bool(st & 8 and st & 2))
     z = (tuning["fft_cols_z"], bool(st & 8 and st & 4))
     name = lambda c: "fft_zb_kernel<float, %d, %d, false, %s>" % (n, c[0], "true" if c[1] else "false")
+    if names_only:
+        return [name(y), name(z)]
     if y == z:
         return name(y) + " (y and z passes)"
     return "%s (y pass), %s (z pass)" % (name(y), name(z))
 
 
-def committed_traffic():
+def committed_traffic(kernel_names):
     """Counter-measured HBM bytes per launch of the strided FFT pass at the C2
     workload, from the committed rocprofv3 summary, if it was taken on the
     current sources (the SHA-256 of the kernel source and of the host code
-    that sequences its launches are recorded in the summary)."""
+    that sequences its launches are recorded in the summary) and on the
+    kernels being timed (every name matches the summary's kernel pattern, so
+    another mesh size or launch shape gets none)."""
     import hashlib
+    import re
     path = os.path.join(ROOT, "profiles", "fft_zb_strided_c2_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
+        pattern = rec.get("kernel")
+        if not pattern or not kernel_names or not all(re.fullmatch(pattern, k) for k in kernel_names):
+            return None
         digests = rec.get("sources_sha256") or {}
         if not digests:
             return None
@@ -413,7 +421,7 @@ def main():
     assert launches == n_strided * psteps, (launches, n_strided)
     alg_bytes = (nd_mesh * (yd + zd) + ns_mesh * (ys + zs)) / n_strided  # per launch
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = committed_traffic()
+    traffic = committed_traffic(strided_kernel_name(n, plan.tuning(), names_only=True))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
