@@ -253,9 +253,10 @@ def emulator_c5(lpp, torch, wl, ran, gal, rdev, epochs):
     t_plain = time.perf_counter() - t0
     out["plain_ms_22000"] = round(1e3 * t_plain, 1)
     t0 = time.perf_counter()
-    lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, P[20000:], kout, nbar, sig, out=Y[20000:])
+    for _ in range(5):
+        lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, P[20000:], kout, nbar, sig, out=Y[20000:])
     torch.cuda.synchronize()
-    t_plain2k = time.perf_counter() - t0
+    t_plain2k = (time.perf_counter() - t0) / 5
     emu = Emulator(EMU_RANGES, n_k=30, max_batch=4096, seed=1)
     t0 = time.perf_counter()
     loss = emu.fit(P[:20000], Y[:20000], nbar, sig, epochs=epochs, batch=128, lr0=5e-4, lr1=1e-5, seed=2)

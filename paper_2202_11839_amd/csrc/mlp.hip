@@ -162,13 +162,14 @@ __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t*
 }
 
 // loss = mean (Y - T)^2, dY = 2 (Y - T) / (B w); one block, FP64 sum in fixed order
-__global__ void __launch_bounds__(kT) mse_kernel(const float* __restrict__ Y, const float* __restrict__ T, int64_t n,
-                                               float* __restrict__ dY, uint16_t* __restrict__ dYb,
-                                               float* __restrict__ loss) {
-  __shared__ double sh[kT];
+constexpr int kMseT = 1024;
+__global__ void __launch_bounds__(kMseT) mse_kernel(const float* __restrict__ Y, const float* __restrict__ T, int64_t n,
+                                                  float* __restrict__ dY, uint16_t* __restrict__ dYb,
+                                                  float* __restrict__ loss) {
+  __shared__ double sh[kMseT];
   double s = 0.0;
   const float scale = 2.0f / static_cast<float>(n);
-  for (int64_t i = threadIdx.x; i < n; i += kT) {
+  for (int64_t i = threadIdx.x; i < n; i += kMseT) {
     const float r = Y[i] - T[i];
     s += static_cast<double>(r) * r;
     const float d = scale * r;
@@ -177,20 +178,37 @@ __global__ void __launch_bounds__(kT) mse_kernel(const float* __restrict__ Y, co
   }
   sh[threadIdx.x] = s;
   __syncthreads();
-  for (int o = kT / 2; o > 0; o >>= 1) {
+  for (int o = kMseT / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = static_cast<float>(sh[0] / static_cast<double>(n));
 }
 
-// db[o] = sum_b D[b][o], one thread per output (fixed order)
-__global__ void bias_grad_kernel(const float* __restrict__ D, int B, int W, float* __restrict__ db) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= W) return;
+// db[o] = sum_b D[b][o]: 64 outputs per workgroup, one per lane; each of the
+// kBiasGroups wavefronts sums a run of consecutive rows in row order, then
+// lane o of the first wavefront adds the runs' partials in run order (a fixed
+// order, independent of timing)
+constexpr int kBiasGroups = 8;
+__global__ void __launch_bounds__(64 * kBiasGroups)
+    bias_grad_kernel(const float* __restrict__ D, int B, int W, float* __restrict__ db) {
+  __shared__ float part[kBiasGroups][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + c;
+  const int per = (B + kBiasGroups - 1) / kBiasGroups;
+  const int b0 = g * per, b1 = min(B, b0 + per);
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += D[static_cast<int64_t>(b) * W + o];
-  db[o] = s;
+  if (o < W) {
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += D[static_cast<int64_t>(b) * W + o];
+  }
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && o < W) {
+    float t = part[0][c];
+    for (int j = 1; j < kBiasGroups; ++j) t += part[j][c];
+    db[o] = t;
+  }
 }
 
 // Adam (beta1 0.9, beta2 0.999, eps 1e-8) on every parameter; the step
@@ -377,7 +395,7 @@ hipError_t train_step(lpp_mlp_s* m, int B, const float* T, const float* lr_sched
   hipError_t e = forward(m, B, nullptr);
   const int wout = m->w[L];
   if (e == hipSuccess) {
-    mse_kernel<<<1, kT, 0, m->stream>>>(m->Z[L - 1], T, static_cast<int64_t>(B) * wout, m->D[L - 1], m->Db[L - 1],
+    mse_kernel<<<1, kMseT, 0, m->stream>>>(m->Z[L - 1], T, static_cast<int64_t>(B) * wout, m->D[L - 1], m->Db[L - 1],
                                         m->loss);
     e = hipGetLastError();
   }
@@ -389,7 +407,7 @@ hipError_t train_step(lpp_mlp_s* m, int B, const float* T, const float* lr_sched
     g.ld = in;
     e = gemm<EPI_PLAIN>(m->stream, out, in, B, m->Db[l], nullptr, 1, out, m->A[l], in, 1, g);
     if (e != hipSuccess) break;
-    bias_grad_kernel<<<(out + 255) / 256, 256, 0, m->stream>>>(m->D[l], B, out, m->G + m->off_b[l]);
+    bias_grad_kernel<<<(out + 63) / 64, 64 * kBiasGroups, 0, m->stream>>>(m->D[l], B, out, m->G + m->off_b[l]);
     e = hipGetLastError();
     if (l > 0 && e == hipSuccess) {
       // D_{l-1}[b][i] = (sum_o D_l[b][o] W_l[o][i]) silu'(Z_{l-1}[b][i])
