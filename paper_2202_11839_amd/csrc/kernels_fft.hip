@@ -210,7 +210,16 @@ __global__ void __launch_bounds__(NL* N / 8, (zb_min_waves<T, N, NL>())) fft_zb_
     col = tid % NL;
     t = tid / NL;
     swz = col & 15;
-    const int xc = blockIdx.x % (N / G), zg = blockIdx.x / (N / G);
+    int bid = blockIdx.x;
+    if constexpr (G == 1 && sizeof(T) == 4) {
+      // one FP32 column per workgroup reads 64-byte runs, and the columns
+      // x = 2p and 2p + 1 share every 128-byte line: both go to the same XCD
+      // (workgroups are dealt to the eight XCDs in turn, so blocks b and
+      // b + 8 of each 16 share one; the grid is a multiple of 16)
+      const int r = bid & 15;
+      bid = (bid & ~15) | ((r & 7) << 1) | (r >> 3);
+    }
+    const int xc = bid % (N / G), zg = bid / (N / G);
     const int x = xc * G + (col >> 3), z = zg * kZb + (col & 7);
     if (pr.plane) {
       int any = 0;
