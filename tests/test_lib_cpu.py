@@ -186,3 +186,28 @@ def test_window_coefficients_of_the_library_match_the_paper_and_the_oracle():
                 for lpp_ in range(0, 17, 2):
                     want = float(S.window_coef(mX, l, lp, lpp_))
                     assert abs(pkg.window_coefficient(mX, l, lp, lpp_) - want) < 1e-13, (mX, l, lp, lpp_)
+
+
+def test_bench_traffic_record_applies_only_to_its_kernels():
+    """The committed counter record of the strided FFT passes is attached to a
+    bench line only when the timed y and z kernels match its kernel pattern
+    (another mesh size or line count gets none) and its hashed sources are
+    the current ones."""
+    import hashlib
+    import json
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "fft_zb_strided_c2_traffic.json")))
+    default = bench.strided_kernel_name(512, {"fft_streaming": 15, "fft_cols_y": 16, "fft_cols_z": 8}, names_only=True)
+    assert default == ["fft_zb_kernel<float, 512, 16, false, true>", "fft_zb_kernel<float, 512, 8, false, true>"]
+    assert all(re.fullmatch(rec["kernel"], k) for k in default)
+    current = all(hashlib.sha256(open(os.path.join(ROOT, "paper_2202_11839_amd", "csrc", f), "rb").read()).hexdigest()
+                  == h for f, h in rec["sources_sha256"].items())
+    assert bench.committed_traffic(default) == (rec["bytes_per_launch"] if current else None)
+    for n, t in ((1024, {"fft_streaming": 13, "fft_cols_y": 8, "fft_cols_z": 8}),
+                 (512, {"fft_streaming": 13, "fft_cols_y": 8, "fft_cols_z": 8}),
+                 (256, {"fft_streaming": 15, "fft_cols_y": 16, "fft_cols_z": 8})):
+        assert bench.committed_traffic(bench.strided_kernel_name(n, t, names_only=True)) is None, (n, t)
+    assert bench.committed_traffic([]) is None
+    assert rec["bytes_per_launch"] == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
