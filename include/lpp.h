@@ -276,7 +276,10 @@ lpp_status lpp_emulator_encode(const double* params, const double* templates, in
                                double* mean, double* sd, void* hip_stream);
 /* The inverse map around the network: out[n][5][n_k] (device, FP64) for the
  * parameter points params[n][5] (device), with a network of widths 5 -> ... -> 5 n_k
- * trained on lpp_emulator_encode's (X, T); batches of the network's max_batch. */
+ * trained on lpp_emulator_encode's (X, T); batches of the network's max_batch.
+ * When no layer input is wider than 256 the network runs as one fused launch
+ * per batch (activations kept on chip); its outputs are the same bits as the
+ * layer-by-layer lpp_mlp_forward's. */
 lpp_status lpp_emulator_predict(lpp_mlp mlp, const double* params, int64_t n, int32_t n_k, const double* ranges,
                                 double nbar, double sigma_gamma, const double* mean, const double* sd, double* out);
 

@@ -367,6 +367,148 @@ hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, const ui
   return hipGetLastError();
 }
 
+// Inference of the whole network in one launch, 16 rows per workgroup: each
+// layer's BF16 hi/lo activations stay in LDS (two buffers, one read while the
+// next is written), the weights come from global memory (L2-resident at
+// these sizes).  Every output gets the layered path's MFMA sequence (k in
+// steps of 32, the hi then the lo product) and epilogue, so the results are
+// the same bits as gemm_bf16_kernel's layer by layer; pre-activations of the
+// hidden layers are not stored (nothing needs them outside training).
+constexpr int kInferRows = 16;
+constexpr int kInferMaxW = 256;  // widest layer input the fused path takes
+constexpr int kInferLd = kInferMaxW + 8;
+
+struct InferArgs {
+  int nl;
+  int w[9];
+  const uint16_t* W[8];
+  const float* bias[8];
+};
+
+// the emulator's encoding of its parameter points and decoding of the
+// network's outputs, done inside the fused launch (params null: plain rows
+// from A0 / A0lo in, FP32 rows to Y out); the same arithmetic as
+// emu_inputs_kernel + to_bf16_kernel and emu_outputs_kernel
+struct InferEmu {
+  const double* params;  // [M][5]
+  EmuArgs a;
+  const double* mean;
+  const double* sd;
+  double* out;  // [M][5 nk]
+};
+
+__global__ void __launch_bounds__(kT) mlp_infer_kernel(InferArgs g, int M, const uint16_t* __restrict__ A0,
+                                                       const uint16_t* __restrict__ A0lo, float* __restrict__ Y,
+                                                       InferEmu emu) {
+  __shared__ __align__(16) uint16_t act[2][2][kInferRows * kInferLd];  // [buffer][hi, lo][row][k]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * kInferRows;
+  const int w0 = g.w[0];
+  for (int i = threadIdx.x; i < kInferRows * w0; i += blockDim.x) {
+    const int r = i / w0, k = i % w0;
+    const bool in = r0 + r < M;
+    const int64_t o = static_cast<int64_t>(r0 + r) * w0 + k;
+    uint16_t h = 0, hl = 0;
+    if (in && emu.params) {
+      const float x = static_cast<float>(2.0 * (emu.params[o] - emu.a.lo[k]) / (emu.a.hi[k] - emu.a.lo[k]) - 1.0);
+      f2bf_split(x, h, hl);
+    } else if (in) {
+      h = A0[o];
+      hl = A0lo[o];
+    }
+    act[0][0][r * kInferLd + k] = h;
+    act[0][1][r * kInferLd + k] = hl;
+  }
+  __syncthreads();
+  const int ar = lane & 15, kq = (lane >> 4) * 8;
+  int cur = 0;
+  for (int l = 0; l < g.nl; ++l) {
+    const int K = g.w[l], N = g.w[l + 1];
+    const uint16_t* __restrict__ W = g.W[l];
+    const bool last = l + 1 == g.nl;
+    const uint16_t* ah = act[cur][0] + ar * kInferLd;
+    const uint16_t* alo = act[cur][1] + ar * kInferLd;
+    uint16_t* oh = act[cur ^ 1][0];
+    uint16_t* olo = act[cur ^ 1][1];
+    const bool bvec = K % 8 == 0 && (reinterpret_cast<uintptr_t>(W) & 15) == 0;
+    for (int n0 = wave * 16; n0 < N; n0 += 64) {
+      const int bn = n0 + (lane & 15);
+      f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a, al, b;
+        const bool kfull = k0 + kq + 8 <= K;
+        if (kfull) {
+          a = *reinterpret_cast<const bf16x8*>(ah + k0 + kq);
+          al = *reinterpret_cast<const bf16x8*>(alo + k0 + kq);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int k = k0 + kq + i;
+            a[i] = __builtin_bit_cast(__bf16, k < K ? ah[k] : static_cast<uint16_t>(0));
+            al[i] = __builtin_bit_cast(__bf16, k < K ? alo[k] : static_cast<uint16_t>(0));
+          }
+        }
+        if (bvec && kfull && bn < N) {
+          b = *reinterpret_cast<const bf16x8*>(W + static_cast<int64_t>(bn) * K + k0 + kq);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int k = k0 + kq + i;
+            b[i] = __builtin_bit_cast(__bf16, (bn < N && k < K) ? W[k + static_cast<int64_t>(bn) * K]
+                                                                 : static_cast<uint16_t>(0));
+          }
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b, c, 0, 0, 0);
+      }
+      if (bn < N) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = (lane >> 4) * 4 + i;
+          const float v = c[i] + g.bias[l][bn];
+          if (!last) {
+            f2bf_split(v * sigm(v), oh[row * kInferLd + bn], olo[row * kInferLd + bn]);
+          } else if (r0 + row < M) {
+            const int64_t r = r0 + row;
+            if (emu.params) {
+              const double* p = emu.params + 5 * r;
+              const int o = bn / emu.a.nk;
+              double d = (static_cast<double>(v) * emu.sd[bn] + emu.mean[bn]) * emu_prefactor(p, o);
+              if (o == 0) d += emu.a.shot * p[4];
+              emu.out[r * N + bn] = d;
+            } else {
+              Y[r * N + bn] = v;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+bool infer_fits(const lpp_mlp_s* m) {
+  if (m->nl < 1 || m->nl > 8) return false;
+  for (int l = 0; l < m->nl; ++l)
+    if (m->w[l] > kInferMaxW) return false;
+  return true;
+}
+
+// inference of B rows already in A[0], Alo[0] (BF16 hi/lo) into Y ([B][w_nl]),
+// or with emu.params set, of B parameter points into emu.out
+hipError_t forward_infer(lpp_mlp_s* m, int B, float* Y, const InferEmu& emu) {
+  InferArgs g{};
+  g.nl = m->nl;
+  for (int l = 0; l <= m->nl; ++l) g.w[l] = m->w[l];
+  for (int l = 0; l < m->nl; ++l) {
+    g.W[l] = m->Pb + m->off_w[l];
+    g.bias[l] = m->P + m->off_b[l];
+  }
+  mlp_infer_kernel<<<(B + kInferRows - 1) / kInferRows, kT, 0, m->stream>>>(g, B, m->A[0], m->Alo[0], Y, emu);
+  return hipGetLastError();
+}
+
 // forward of B rows already in A[0] (BF16); Y = Z[nl-1]
 hipError_t forward(lpp_mlp_s* m, int B, float* Y) {
   hipError_t e = hipSuccess;
@@ -625,8 +767,14 @@ lpp_status lpp_emulator_predict(lpp_mlp m, const double* params, int64_t n, int3
   a.shot = 2.0 * sigma_gamma * sigma_gamma / nbar;
   a.nk = n_k;
   hipError_t e = hipSuccess;
+  const bool fused = infer_fits(m);
   for (int64_t r0 = 0; r0 < n && e == hipSuccess; r0 += m->max_batch) {
     const int64_t B = std::min<int64_t>(m->max_batch, n - r0);
+    if (fused) {
+      const InferEmu ie{params + 5 * r0, a, mean, sd, out + r0 * 5 * n_k};
+      e = forward_infer(m, static_cast<int>(B), nullptr, ie);
+      continue;
+    }
     emu_inputs_kernel<<<blocks_for(5 * B), kT, 0, m->stream>>>(a, params + 5 * r0, B, m->Xb);
     e = hipGetLastError();
     if (e != hipSuccess) break;

@@ -903,3 +903,47 @@ def test_shot_noise_closed_form_on_the_gpu(lpp):
         m = v.mean()
         err = v.std(ddof=1) / np.sqrt(v.size)
         assert abs(m) < 4 * err + 1e-3 * npl, (k, m, err)
+
+
+def test_emulator_predict_fused_network_matches_layered_forward(lpp):
+    """lpp_emulator_predict runs the network as one fused launch per batch;
+    its outputs equal the layer-by-layer lpp_mlp_forward's (same bits) after
+    the same decoding, here on 700 points (ragged 16-row blocks, two batches
+    of at most 512) of an untrained network."""
+    import torch
+    from paper_2202_11839_amd.emulator import Emulator
+    from synth import EMU_RANGES, latin_hypercube
+    n, n_k = 700, 30
+    pts = latin_hypercube(n, EMU_RANGES, seed=11)
+    emu = Emulator(EMU_RANGES, n_k=n_k, max_batch=512, seed=5)
+    emu.nbar, emu.sigma_gamma = 1.4e-3, 0.2
+    rng = np.random.default_rng(3)
+    mean_h, sd_h = rng.normal(size=5 * n_k), 0.5 + rng.random(5 * n_k)
+    emu.mean = torch.tensor(mean_h, dtype=torch.float64, device="cuda")
+    emu.sd = torch.tensor(sd_h, dtype=torch.float64, device="cuda")
+    P = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    E = torch.zeros((n, 5, n_k), dtype=torch.float64, device="cuda")
+    emu.predict(P, E)
+    torch.cuda.synchronize()
+    lo = np.array([r[0] for r in EMU_RANGES]); hi = np.array([r[1] for r in EMU_RANGES])
+    X = (2.0 * (pts - lo) / (hi - lo) - 1.0).astype(np.float32)
+    Yl = np.zeros((n, 5 * n_k), dtype=np.float32)
+    for r0 in range(0, n, 512):
+        Xd = torch.tensor(X[r0:r0 + 512], device="cuda")
+        Yd = torch.zeros((Xd.shape[0], 5 * n_k), dtype=torch.float32, device="cuda")
+        emu.net.forward(Xd, Yd)
+        torch.cuda.synchronize()
+        Yl[r0:r0 + 512] = Yd.cpu().numpy()
+    assert np.all(np.isfinite(Yl))
+    pref = np.where(np.arange(5)[None, :] < 3, (pts[:, 0] ** 2 * pts[:, 3] ** 2)[:, None],
+                    (pts[:, 0] * pts[:, 3] ** 2)[:, None])
+    want = (Yl.astype(np.float64) * sd_h + mean_h).reshape(n, 5, n_k) * pref[:, :, None]
+    scale = np.abs(want)
+    shot = 2.0 * 0.2 ** 2 / 1.4e-3 * pts[:, 4][:, None]
+    want[:, 0, :] += shot
+    scale[:, 0, :] += np.abs(shot)
+    got = E.cpu().numpy()
+    # a one-ulp change of any FP32 network output moves its decoded value by
+    # about 6e-8 of its size; the decoding itself (FP64, device vs host,
+    # fused or separate roundings) by about 1e-16 of the terms' size
+    assert np.max(np.abs(got - want) / scale) < 1e-12
