@@ -664,7 +664,7 @@ def test_emulator_round_trip_on_template_design(lpp):
     few hundred epochs on 3,000 plain-path templates of a smooth window, its
     held-out predictions stay within 2 % of the plain path (the 1 % bar is
     measured on the full 20,000-point design by bench.py), and it evaluates
-    them faster than the plain path does (bench.py: about 130x at 2,000
+    them faster than the plain path does (bench.py times both at 2,000
     points; here at least 3x at 300, where launch latency weighs most)."""
     import torch
     from paper_2202_11839_amd.emulator import Emulator, accuracy
