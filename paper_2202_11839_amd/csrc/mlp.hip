@@ -367,7 +367,8 @@ hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, const ui
   return hipGetLastError();
 }
 
-// Inference of the whole network in one launch, 16 rows per workgroup: each
+// Inference of the whole network in one launch, 16 rows per workgroup (16
+// wavefronts, one 16-column output tile each at a time): each
 // layer's BF16 hi/lo activations stay in LDS (two buffers, one read while the
 // next is written), the weights come from global memory (L2-resident at
 // these sizes).  Every output gets the layered path's MFMA sequence (k in
@@ -377,6 +378,7 @@ hipError_t gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, const ui
 constexpr int kInferRows = 16;
 constexpr int kInferMaxW = 256;  // widest layer input the fused path takes
 constexpr int kInferLd = kInferMaxW + 8;
+constexpr int kInferT = 1024;  // 16 wavefronts: one 16-column tile each for a 256-wide layer
 
 struct InferArgs {
   int nl;
@@ -397,7 +399,7 @@ struct InferEmu {
   double* out;  // [M][5 nk]
 };
 
-__global__ void __launch_bounds__(kT) mlp_infer_kernel(InferArgs g, int M, const uint16_t* __restrict__ A0,
+__global__ void __launch_bounds__(kInferT) mlp_infer_kernel(InferArgs g, int M, const uint16_t* __restrict__ A0,
                                                        const uint16_t* __restrict__ A0lo, float* __restrict__ Y,
                                                        InferEmu emu) {
   __shared__ __align__(16) uint16_t act[2][2][kInferRows * kInferLd];  // [buffer][hi, lo][row][k]
@@ -431,7 +433,7 @@ __global__ void __launch_bounds__(kT) mlp_infer_kernel(InferArgs g, int M, const
     uint16_t* oh = act[cur ^ 1][0];
     uint16_t* olo = act[cur ^ 1][1];
     const bool bvec = K % 8 == 0 && (reinterpret_cast<uintptr_t>(W) & 15) == 0;
-    for (int n0 = wave * 16; n0 < N; n0 += 64) {
+    for (int n0 = wave * 16; n0 < N; n0 += 16 * (kInferT / 64)) {
       const int bn = n0 + (lane & 15);
       f32x4 c = {0.f, 0.f, 0.f, 0.f};
       for (int k0 = 0; k0 < K; k0 += 32) {
@@ -505,7 +507,7 @@ hipError_t forward_infer(lpp_mlp_s* m, int B, float* Y, const InferEmu& emu) {
     g.W[l] = m->Pb + m->off_w[l];
     g.bias[l] = m->P + m->off_b[l];
   }
-  mlp_infer_kernel<<<(B + kInferRows - 1) / kInferRows, kT, 0, m->stream>>>(g, B, m->A[0], m->Alo[0], Y, emu);
+  mlp_infer_kernel<<<(B + kInferRows - 1) / kInferRows, kInferT, 0, m->stream>>>(g, B, m->A[0], m->Alo[0], Y, emu);
   return hipGetLastError();
 }
 
