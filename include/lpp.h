@@ -225,6 +225,23 @@ lpp_status lpp_template_plain(const double* pfid, double k_min, double k_max, in
                               const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
                               int32_t device_io, void* stream);
 
+/* The same plain path for all four families of the estimator (Sec. IV.C,
+ * eq. all_convolutions and the leakage equations), with the density auto
+ * spectrum of the Kaiser model, P_dd = (b + f mu^2)^2 P_lin, whose multipoles
+ * are {b^2 + 2bf/3 + f^2/5, 4bf/3 + 4f^2/7, 8f^2/35} P_lin, and the minus
+ * shape spectrum of the same alignment model, P_- = P_+ = (A^2/4)(1-mu^2)^2 P_lin,
+ * whose only m=4 moment is P_-^(4) = A^2 P_lin / 420.  Window mixing with
+ * mX = 0 for dd and plus, 2 for gd and 4 for minus; everything else as for
+ * lpp_template_plain.  Output rows in the estimator's series order:
+ *   out[(p * 9 + o) * n_k + i], o = 0, 1, 2: P~_dd^(0,2,4) (P~^(2) is the leakage
+ *   moment of an isotropic model), o = 3, 4: P~_gd^(2,4), o = 5, 6, 7: P~_+^(0,2,4)
+ *   (with the shot-noise term on l = 0), o = 8: P~_-^(4).
+ * Allocates its own device scratch and synchronises the stream. */
+lpp_status lpp_template_multipoles(const double* pfid, double k_min, double k_max, int32_t n_log, const double* r_q,
+                                   const double* Q, int32_t n_q, const double* params, int64_t n_pts,
+                                   const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
+                                   int32_t device_io, void* stream);
+
 /* ---- Emulator network (the learned stand-in for lpp_template_plain) ----
  * A fully connected network widths[0] -> ... -> widths[n_layers] with SiLU
  * (x / (1 + exp(-x))) after every layer but the last, trained on the mean
@@ -270,6 +287,8 @@ lpp_status lpp_mlp_fit(lpp_mlp mlp, const float* X, const float* T, int64_t n, i
  *                 minus mean[c], over sd[c] (FP64 column statistics over the n rows, written
  *                 to the device arrays mean, sd [5 n_k]; sd = 1 for a column whose spread is
  *                 below 1e-9 of its mean, i.e. constant up to rounding).
+ * LPP_E_INVALID (nothing written) if a range has hi <= lo or a point's prefactor
+ * A^2 sigma8^2 or A sigma8^2 is zero or not finite (such a point has no shape).
  * Synchronises the stream; allocates an FP64 scratch of n * 5 n_k values. */
 lpp_status lpp_emulator_encode(const double* params, const double* templates, int64_t n, int32_t n_k,
                                const double* ranges, double nbar, double sigma_gamma, float* X, float* T,
@@ -279,7 +298,7 @@ lpp_status lpp_emulator_encode(const double* params, const double* templates, in
  * trained on lpp_emulator_encode's (X, T); batches of the network's max_batch.
  * When no layer input is wider than 256 the network runs as one fused launch
  * per batch (activations kept on chip); its outputs are the same bits as the
- * layer-by-layer lpp_mlp_forward's. */
+ * layer-by-layer lpp_mlp_forward's.  LPP_E_INVALID if a range has hi <= lo. */
 lpp_status lpp_emulator_predict(lpp_mlp mlp, const double* params, int64_t n, int32_t n_k, const double* ranges,
                                 double nbar, double sigma_gamma, const double* mean, const double* sd, double* out);
 

@@ -165,9 +165,9 @@ def _bin_sums(cfg: Config, bidx: np.ndarray, z: np.ndarray) -> np.ndarray:
 def _transform(cfg: Config, pos: np.ndarray, values: np.ndarray, comp: np.ndarray,
                phase: Optional[np.ndarray]) -> np.ndarray:
     n, p = cfg.mesh, cfg.assignment
-    F = np.fft.fftn(mesh.deposit(pos, values, n, cfg.box, cfg.origin, p))
+    F = mesh.fftn(mesh.deposit(pos, values, n, cfg.box, cfg.origin, p))
     if cfg.interlacing:
-        F2 = np.fft.fftn(mesh.deposit(pos, values, n, cfg.box, cfg.origin, p, shift=0.5))
+        F2 = mesh.fftn(mesh.deposit(pos, values, n, cfg.box, cfg.origin, p, shift=0.5))
         F = 0.5 * (F + phase * F2)
     return F / comp
 

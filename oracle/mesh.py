@@ -20,8 +20,10 @@ bin width dn = num/den in units of the fundamental frequency kf = 2 pi / box.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft as _sfft
 
 
 def stencil_1d(u: np.ndarray, p: int):
@@ -53,19 +55,30 @@ def deposit(pos: np.ndarray, values: np.ndarray, n: int, box: float, origin, p: 
         ci.append(np.mod(c, n))
         wi.append(w)
     cplx = np.iscomplexobj(values)
-    out_r = np.zeros(n ** 3)
-    out_i = np.zeros(n ** 3) if cplx else None
+    # every (object, stencil node) pair, then one sum per node
+    flats, vals = [], []
     for a in range(p):
         for b in range(p):
             for c in range(p):
-                flat = (ci[0][:, a] * n + ci[1][:, b]) * n + ci[2][:, c]
-                wt = wi[0][:, a] * wi[1][:, b] * wi[2][:, c]
-                v = wt * values
-                out_r += np.bincount(flat, weights=v.real if cplx else v, minlength=n ** 3)
-                if cplx:
-                    out_i += np.bincount(flat, weights=v.imag, minlength=n ** 3)
-    out = out_r if not cplx else out_r + 1j * out_i
+                flats.append((ci[0][:, a] * n + ci[1][:, b]) * n + ci[2][:, c])
+                vals.append(wi[0][:, a] * wi[1][:, b] * wi[2][:, c] * values)
+    flat = np.concatenate(flats)
+    v = np.concatenate(vals)
+    del flats, vals
+    out = np.bincount(flat, weights=v.real if cplx else v, minlength=n ** 3)
+    if cplx:
+        out = out + 1j * np.bincount(flat, weights=v.imag, minlength=n ** 3)
     return out.reshape(n, n, n)
+
+
+def fftn(a: np.ndarray) -> np.ndarray:
+    """Forward 3D DFT, exp(-2 pi i n.c/N) (scipy's FFT on every host core)."""
+    return _sfft.fftn(a, workers=os.cpu_count() or 1)
+
+
+def ifftn(a: np.ndarray) -> np.ndarray:
+    """Inverse 3D DFT with the 1/N^3 factor (scipy's FFT on every host core)."""
+    return _sfft.ifftn(a, workers=os.cpu_count() or 1)
 
 
 def signed_modes(n: int) -> np.ndarray:

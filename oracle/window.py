@@ -74,9 +74,9 @@ def window_multipoles(ran, alpha: float, n: int, box: float, origin, observer, a
     phase = mesh.interlace_phase(n) if interlacing else None
 
     def transform(values):
-        F = np.fft.fftn(mesh.deposit(pos, values, n, box, origin, assignment))
+        F = mesh.fftn(mesh.deposit(pos, values, n, box, origin, assignment))
         if interlacing:
-            F2 = np.fft.fftn(mesh.deposit(pos, values, n, box, origin, assignment, shift=0.5))
+            F2 = mesh.fftn(mesh.deposit(pos, values, n, box, origin, assignment, shift=0.5))
             F = 0.5 * (F + phase * F2)
         return F / comp
 
@@ -107,7 +107,7 @@ def window_multipoles(ran, alpha: float, n: int, box: float, origin, observer, a
             for a, mult in _multinomial_monomials(j).items():
                 if a not in cache:
                     Fa = transform(w * xh[:, 0] ** a[0] * xh[:, 1] ** a[1] * xh[:, 2] ** a[2])
-                    cache[a] = np.real(np.fft.ifftn(np.conj(Fa) * F0))
+                    cache[a] = np.real(mesh.ifftn(np.conj(Fa) * F0))
                 G += float(c) * mult * rh[0] ** a[0] * rh[1] ** a[1] * rh[2] ** a[2] * cache[a]
         s = np.bincount(bidx[sel], weights=G[sel], minlength=n_rbins)
         Q[i] = (2 * l + 1) * s / (np.where(counts > 0, counts, 1) * vcell * I)
@@ -170,11 +170,18 @@ def hankel(x: np.ndarray, fx: np.ndarray, l: int, inverse: bool, q: float = None
 # model, sigma8 and the plain template path
 
 PLUS_XI = {0: Fraction(2, 15), 2: Fraction(-4, 21), 4: Fraction(2, 35)}
+MINUS_XI = {4: Fraction(1, 420)}
 
 
 def gd_moments(b: float, f: float) -> Dict[int, float]:
     """m=2 moments of -(1/2)(1-mu^2)(b+f mu^2) (per unit A and P_lin)."""
     return {2: -(7.0 * b + f) / 42.0, 4: -f / 105.0}
+
+
+def dd_moments(b: float, f: float) -> Dict[int, float]:
+    """Legendre moments of the Kaiser spectrum (b + f mu^2)^2 (per unit P_lin)."""
+    return {0: b * b + 2.0 * b * f / 3.0 + f * f / 5.0, 2: 4.0 * b * f / 3.0 + 4.0 * f * f / 7.0,
+            4: 8.0 * f * f / 35.0}
 
 
 def sigma8(k: np.ndarray, pk: np.ndarray) -> float:
@@ -200,37 +207,63 @@ def interp_lnk(k: np.ndarray, v: np.ndarray, kout: np.ndarray) -> np.ndarray:
     return np.interp(np.log(kout), np.log(k), v)
 
 
-def template_plain(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.ndarray, params: np.ndarray,
-                   kout: np.ndarray, nbar: float, sigma_gamma: float, sigma8_fid: float = None) -> np.ndarray:
-    """Window-convolved P~_+^(0,2,4) and P~_Ed^(2,4) at kout for every
-    parameter point (A, b, f, sigma8, s_N): shape (n_pts, 5, n_k).
-    k: the log grid of pfid (also the FFTLog grid); Q: Q_0..Q_8 at r_q."""
+# (family, m of its window mixing, multipoles l of the output = model multipoles l')
+FAMILIES = {"dd": (0, (0, 2, 4)), "gd": (2, (2, 4)), "plus": (0, (0, 2, 4)), "minus": (4, (4,))}
+
+
+def template_families(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.ndarray, params: np.ndarray,
+                      kout: np.ndarray, nbar: float, sigma_gamma: float, families, sigma8_fid: float = None) -> np.ndarray:
+    """Window-convolved multipoles of the listed families at kout for every
+    parameter point (A, b, f, sigma8, s_N): shape (n_pts, rows, n_k), the rows
+    being each family's multipoles in order (dd l = 0, 2, 4; gd L = 2, 4;
+    plus l = 0, 2, 4; minus L = 4).  Model, with P_lin = (sigma8/sigma8_fid)^2
+    P_fid: P_dd = (b + f mu^2)^2 P_lin (Kaiser), P_gd = -(A/2)(1-mu^2)(b+f mu^2)
+    P_lin, P_+ = P_- = (A^2/4)(1-mu^2)^2 P_lin (no RSD on shapes).  For each
+    output multipole l of family X: xi^(l') = H^{-1}_{l'}[P_X^(l')] for each
+    model multipole l', times Q^X_{l l'}(r) (eq. def_of_Q_llp, m of the
+    family), summed, and H_l of the sum (eq. window_convolution_X_hankel),
+    interpolated linearly in ln k; the shot noise s_N 2 sigma_gamma^2 / nbar
+    is added to P~_+^(0).  k: the log grid of pfid (also the FFTLog grid);
+    Q: Q_0..Q_8 at r_q."""
     s8f = sigma8(k, pfid) if sigma8_fid is None else sigma8_fid
     r = 1.0 / k[::-1]
     Qg = q_on_grid(r_q, Q, r)
+    rows = [(X, l) for X in families for l in FAMILIES[X][1]]
     wc = {}
-    for X, mX, ls, lps in (("plus", 0, (0, 2, 4), (0, 2, 4)), ("gd", 2, (2, 4), (2, 4))):
-        for l in ls:
-            for lp in lps:
-                c = [float(special.window_coef(mX, l, lp, lpp)) for lpp in (0, 2, 4, 6, 8)]
-                wc[(X, l, lp)] = np.tensordot(np.array(c), Qg, axes=(0, 0))
-    out = np.zeros((params.shape[0], 5, kout.size))
+    for X, l in rows:
+        mX, lps = FAMILIES[X]
+        for lp in lps:
+            c = np.array([float(special.window_coef(mX, l, lp, lpp)) for lpp in (0, 2, 4, 6, 8)])
+            wc[(X, l, lp)] = np.tensordot(c, Qg, axes=(0, 0))
+    out = np.zeros((params.shape[0], len(rows), kout.size))
     damp = np.exp(-(k / 10.0) ** 2)  # keeps k^3 P(k) localised on the grid; negligible for k <= 0.3
     for p_i, (A, b, f, s8, sN) in enumerate(params):
         plin = (s8 / s8f) ** 2 * pfid * damp
-        xi_plus = {lp: hankel(k, A * A * float(PLUS_XI[lp]) * plin, lp, inverse=True)[1] for lp in (0, 2, 4)}
-        gm = gd_moments(b, f)
-        xi_gd = {Lp: hankel(k, A * gm[Lp] * plin, Lp, inverse=True)[1] for Lp in (2, 4)}
-        row = 0
-        for l in (0, 2, 4):
-            g = sum(wc[("plus", l, lp)] * xi_plus[lp] for lp in (0, 2, 4))
+        amp = {"dd": dd_moments(b, f), "gd": {L: A * v for L, v in gd_moments(b, f).items()},
+               "plus": {l: A * A * float(c) for l, c in PLUS_XI.items()},
+               "minus": {L: A * A * float(c) for L, c in MINUS_XI.items()}}
+        xi = {(X, lp): hankel(k, amp[X][lp] * plin, lp, inverse=True)[1] for X in families for lp in FAMILIES[X][1]}
+        for row, (X, l) in enumerate(rows):
+            g = np.zeros_like(r)
+            for lp in FAMILIES[X][1]:
+                g += wc[(X, l, lp)] * xi[(X, lp)]
             kk, P = hankel(r, g, l, inverse=False)
             out[p_i, row] = interp_lnk(kk, P, kout)
-            row += 1
-        for L in (2, 4):
-            g = sum(wc[("gd", L, Lp)] * xi_gd[Lp] for Lp in (2, 4))
-            kk, P = hankel(r, g, L, inverse=False)
-            out[p_i, row] = interp_lnk(kk, P, kout)
-            row += 1
-        out[p_i, 0] += sN * 2.0 * sigma_gamma ** 2 / nbar
+            if X == "plus" and l == 0:
+                out[p_i, row] += sN * 2.0 * sigma_gamma ** 2 / nbar
     return out
+
+
+def template_plain(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.ndarray, params: np.ndarray,
+                   kout: np.ndarray, nbar: float, sigma_gamma: float, sigma8_fid: float = None) -> np.ndarray:
+    """Window-convolved P~_+^(0,2,4) and P~_Ed^(2,4) at kout for every
+    parameter point (A, b, f, sigma8, s_N): shape (n_pts, 5, n_k)."""
+    return template_families(k, pfid, r_q, Q, params, kout, nbar, sigma_gamma, ("plus", "gd"), sigma8_fid)
+
+
+def template_multipoles(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.ndarray, params: np.ndarray,
+                        kout: np.ndarray, nbar: float, sigma_gamma: float, sigma8_fid: float = None) -> np.ndarray:
+    """All four families, rows DD_l0,2,4, GD_L2,4, PLUS_l0,2,4, MINUS_L4:
+    shape (n_pts, 9, n_k)."""
+    return template_families(k, pfid, r_q, Q, params, kout, nbar, sigma_gamma, ("dd", "gd", "plus", "minus"),
+                             sigma8_fid)

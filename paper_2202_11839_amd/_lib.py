@@ -26,7 +26,8 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
-           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_mlp_create",
+           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_template_multipoles",
+           "lpp_mlp_create",
            "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
            "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit", "lpp_emulator_encode", "lpp_emulator_predict"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_y", "fft_cols_z", "bin_blocks", "gather_density", "gather_shape", "serial",
@@ -415,15 +416,14 @@ def window_coefficient(mX: int, l: int, lp: int, lpp: int) -> float:
     return out.value
 
 
-def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float, sigma_gamma: float,
-                   out=None):
-    """The plain window-convolved template path on the GPU (lpp_template_plain).
+TEMPLATE_ROWS = {"lpp_template_plain": 5, "lpp_template_multipoles": 9}
+TEMPLATE_SERIES = ["DD_l0", "DD_l2", "DD_l4", "GD_L2", "GD_L4", "PLUS_l0", "PLUS_l2", "PLUS_l4", "MINUS_L4"]
 
-    ``params`` (n_pts, 5) and ``out`` (n_pts, 5, n_k) may be numpy arrays
-    (host) or float64 CUDA tensors (device, then ``out`` must be given); the
-    tables ``pfid`` (4096), ``r_q``, ``Q`` (5, n_q) and ``k_out`` are host arrays."""
+
+def _template(entry: str, pfid, k_min, k_max, r_q, Q, params, k_out, nbar, sigma_gamma, out):
     import numpy as np
     lib = load()
+    rows = TEMPLATE_ROWS[entry]
     dp = C.POINTER(C.c_double)
     pf = np.ascontiguousarray(pfid, dtype=np.float64)
     rq = np.ascontiguousarray(r_q, dtype=np.float64)
@@ -433,6 +433,7 @@ def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar
     if on_dev:
         import torch
         assert params.dtype == torch.float64 and params.is_contiguous() and out is not None
+        assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == params.shape[0] * rows * ko.size
         n_pts = params.shape[0]
         p_ptr = C.cast(C.c_void_p(params.data_ptr()), dp)
         o_ptr = C.cast(C.c_void_p(out.data_ptr()), dp)
@@ -441,14 +442,31 @@ def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar
         pr = np.ascontiguousarray(params, dtype=np.float64)
         n_pts = pr.shape[0]
         if out is None:
-            out = np.zeros((n_pts, 5, ko.size))
+            out = np.zeros((n_pts, rows, ko.size))
+        assert out.dtype == np.float64 and out.flags.c_contiguous and out.size == n_pts * rows * ko.size
         p_ptr, o_ptr, stream = pr.ctypes.data_as(dp), out.ctypes.data_as(dp), C.c_void_p(0)
-    _check(lib.lpp_template_plain(pf.ctypes.data_as(dp), C.c_double(k_min), C.c_double(k_max), C.c_int32(pf.size),
-                                  rq.ctypes.data_as(dp), qq.ctypes.data_as(dp), C.c_int32(rq.size), p_ptr,
-                                  C.c_int64(n_pts), ko.ctypes.data_as(dp), C.c_int32(ko.size), C.c_double(nbar),
-                                  C.c_double(sigma_gamma), o_ptr, C.c_int32(1 if on_dev else 0), stream),
-           "lpp_template_plain")
+    _check(getattr(lib, entry)(pf.ctypes.data_as(dp), C.c_double(k_min), C.c_double(k_max), C.c_int32(pf.size),
+                               rq.ctypes.data_as(dp), qq.ctypes.data_as(dp), C.c_int32(rq.size), p_ptr,
+                               C.c_int64(n_pts), ko.ctypes.data_as(dp), C.c_int32(ko.size), C.c_double(nbar),
+                               C.c_double(sigma_gamma), o_ptr, C.c_int32(1 if on_dev else 0), stream), entry)
     return out
+
+
+def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float, sigma_gamma: float,
+                   out=None):
+    """The plain window-convolved template path on the GPU (lpp_template_plain).
+
+    ``params`` (n_pts, 5) and ``out`` (n_pts, 5, n_k) may be numpy arrays
+    (host) or float64 CUDA tensors (device, then ``out`` must be given); the
+    tables ``pfid`` (4096), ``r_q``, ``Q`` (5, n_q) and ``k_out`` are host arrays."""
+    return _template("lpp_template_plain", pfid, k_min, k_max, r_q, Q, params, k_out, nbar, sigma_gamma, out)
+
+
+def template_multipoles(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float, sigma_gamma: float,
+                        out=None):
+    """All four families (lpp_template_multipoles): out (n_pts, 9, n_k) in the
+    order of TEMPLATE_SERIES."""
+    return _template("lpp_template_multipoles", pfid, k_min, k_max, r_q, Q, params, k_out, nbar, sigma_gamma, out)
 
 
 def version() -> str:

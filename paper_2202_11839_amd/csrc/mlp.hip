@@ -284,9 +284,11 @@ __global__ void emu_inputs_kernel(EmuArgs a, const double* __restrict__ params, 
   }
 }
 
-// shape-normalised outputs, FP64 [n][5 nk]
+// shape-normalised outputs, FP64 [n][5 nk]; *bad is set when a point's
+// prefactor is zero or not finite (its shapes would be inf/NaN and spoil the
+// column statistics of every point)
 __global__ void emu_shapes_kernel(EmuArgs a, const double* __restrict__ params, const double* __restrict__ templ,
-                                  int64_t n, double* __restrict__ shapes) {
+                                  int64_t n, double* __restrict__ shapes, int* __restrict__ bad) {
   const int w = 5 * a.nk;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n * w;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -295,7 +297,13 @@ __global__ void emu_shapes_kernel(EmuArgs a, const double* __restrict__ params, 
     const double* p = params + 5 * r;
     double v = templ[i];
     if (o == 0) v -= a.shot * p[4];
-    shapes[i] = v / emu_prefactor(p, o);
+    const double pf = emu_prefactor(p, o);
+    if (!(pf != 0.0) || !isfinite(pf)) {
+      *bad = 1;
+      shapes[i] = 0.0;
+    } else {
+      shapes[i] = v / pf;
+    }
   }
 }
 
@@ -745,12 +753,28 @@ lpp_status lpp_emulator_encode(const double* params, const double* templ, int64_
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const int w = 5 * n_k;
   double* shapes = nullptr;
-  if (hipMalloc(&shapes, 8 * static_cast<size_t>(n) * w) != hipSuccess) return LPP_E_NOMEM;
-  emu_inputs_kernel<<<blocks_for(5 * n), kT, 0, st>>>(a, params, n, X);
-  emu_shapes_kernel<<<blocks_for(n * w), kT, 0, st>>>(a, params, templ, n, shapes);
-  column_stats_kernel<<<w, kT, 0, st>>>(shapes, n, w, mean, sd);
-  standardise_kernel<<<blocks_for(n * w), kT, 0, st>>>(shapes, n, w, mean, sd, T);
-  hipError_t e = hipGetLastError();
+  // the shapes, then one flag word
+  if (hipMalloc(&shapes, 8 * (static_cast<size_t>(n) * w + 1)) != hipSuccess) return LPP_E_NOMEM;
+  int* bad = reinterpret_cast<int*>(shapes + static_cast<size_t>(n) * w);
+  int bad_host = 0;
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int), st);
+  if (e == hipSuccess) {
+    emu_shapes_kernel<<<blocks_for(n * w), kT, 0, st>>>(a, params, templ, n, shapes, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && bad_host) {
+    // A = 0 or sigma8 = 0 (or a non-finite value) in a training point: nothing is written
+    (void)hipFree(shapes);
+    return LPP_E_INVALID;
+  }
+  if (e == hipSuccess) {
+    emu_inputs_kernel<<<blocks_for(5 * n), kT, 0, st>>>(a, params, n, X);
+    column_stats_kernel<<<w, kT, 0, st>>>(shapes, n, w, mean, sd);
+    standardise_kernel<<<blocks_for(n * w), kT, 0, st>>>(shapes, n, w, mean, sd, T);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(shapes);
   return status_of(e);
@@ -765,6 +789,7 @@ lpp_status lpp_emulator_predict(lpp_mlp m, const double* params, int64_t n, int3
   for (int i = 0; i < 5; ++i) {
     a.lo[i] = ranges[2 * i];
     a.hi[i] = ranges[2 * i + 1];
+    if (!(a.hi[i] > a.lo[i])) return LPP_E_INVALID;
   }
   a.shot = 2.0 * sigma_gamma * sigma_gamma / nbar;
   a.nk = n_k;

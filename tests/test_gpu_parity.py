@@ -611,6 +611,32 @@ def test_template_plain_matches_oracle(lpp):
     assert np.array_equal(do.cpu().numpy(), got)
 
 
+def test_template_multipoles_matches_oracle(lpp):
+    """All four template families (density auto with its leakage quadrupole,
+    shape-density cross, plus, minus) on the GPU against the oracle's FFTLog
+    path, host I/O, and the plus and cross rows against lpp_template_plain
+    (same kernels per point)."""
+    from oracle import window as OW
+    k = OW.log_grid(1e-5, 1e3, 4096)
+    pfid = 2e4 * (k / 0.02) / (1 + (k / 0.02) ** 2) ** 1.4
+    r_q = np.linspace(5.0, 3000.0, 300)
+    Q = np.vstack([np.exp(-r_q / 900.0) * (1.0 if i == 0 else 0.3 * (-1) ** i / (i + 1)) *
+                   (1 + 0.2 * np.sin(r_q / 300.0 + i)) for i in range(5)])
+    kout = np.arange(1, 31) * 0.01
+    pars = np.array([[0.03, 2.0, 0.7, 0.8, 1.0], [-1.0, 1.0, 0.0, 0.9, 0.0], [0.045, 2.8, 0.55, 0.95, 1.8]])
+    ref = OW.template_multipoles(k, pfid, r_q, Q, pars, kout, nbar=1.4e-3, sigma_gamma=0.2)
+    got = lpp.template_multipoles(pfid, 1e-5, 1e3, r_q, Q, pars, kout, 1.4e-3, 0.2)
+    assert got.shape == (3, 9, 30)
+    for o in range(9):
+        scale = np.max(np.abs(ref[:, o]))
+        assert np.max(np.abs(got[:, o] - ref[:, o])) <= 1e-9 * scale, (lpp.TEMPLATE_SERIES[o],
+                                                                       np.max(np.abs(got[:, o] - ref[:, o])) / scale)
+    plain = lpp.template_plain(pfid, 1e-5, 1e3, r_q, Q, pars, kout, 1.4e-3, 0.2)
+    for o5, o9 in ((0, 5), (1, 6), (2, 7), (3, 3), (4, 4)):
+        scale = np.max(np.abs(plain[:, o5]))
+        assert np.max(np.abs(got[:, o9] - plain[:, o5])) <= 1e-13 * scale
+
+
 # ---------------------------------------------------------------------------
 # the emulator network
 
@@ -839,6 +865,40 @@ def test_full_size_512_workload_sampled_outputs(lpp):
         assert np.max(np.abs(g - ref) / scale) <= 1e-4, name
 
 
+def test_full_size_512_all_series_against_stored_oracle(lpp):
+    """Every series of the 512^3 wedge workload's estimator settings (TSC +
+    interlacing, compensation, l <= 4, 50 shells), FP32, device-resident
+    catalogs as bench.py times it, against the FP64 oracle (mesh64, the
+    paper's Cartesian-tensor FFT route) on a 60,000 + 600,000 subsample of the
+    workload, stored in tests/golden/c2_subsample_512.json by
+    tests/golden/make_c2_subsample.py (which calls only oracle/ and synth/):
+    all 15 series per shell at 1e-4 (of the scale and of the series' own
+    value), mode counts bit-exact, scalars at 1e-10."""
+    import json
+    import os
+    import sys
+    import torch
+    gold_path = os.path.join(os.path.dirname(__file__), "golden", "c2_subsample_512.json")
+    gold = json.load(open(gold_path))
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_c2_subsample as MK
+    g, r = MK.catalogs()
+    cs = MK.checksums(g, r)
+    for k, v in gold["checksums"].items():
+        assert abs(cs[k] - v) <= 1e-12 * max(1.0, abs(v)), ("the catalog generator changed", k, cs[k], v)
+    ref = dict(gold)
+    for k in ("n_modes", "k_eff", "k_lo", "re", "im"):
+        ref[k] = np.asarray(gold[k])
+    wl = MK.WORKLOADS["c2"]
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision="f32", lmax=4, n_kbins=wl["n_kbins"])
+    got = plan.estimate(_device_catalog(g, torch), _device_catalog(r, torch))
+    worst = _compare(got, ref, 1e-4)
+    own = _own_errors(got, ref)
+    print(f"\n512^3 subsample, FP32 vs FP64 oracle: worst {worst:.2e} of the scale; own-value "
+          + ", ".join(f"{k} {v:.1e}" for k, v in own.items()))
+
+
 def _device_catalog(c, torch, dtype=None):
     return Catalog(*[None if v is None else torch.tensor(v, device="cuda", dtype=dtype)
                      for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
@@ -1042,3 +1102,34 @@ def test_emulator_predict_fused_network_matches_layered_forward(lpp):
     # about 6e-8 of its size; the decoding itself (FP64, device vs host,
     # fused or separate roundings) by about 1e-16 of the terms' size
     assert np.max(np.abs(got - want) / scale) < 1e-12
+
+
+def test_emulator_rejects_degenerate_points_and_ranges(lpp):
+    """lpp_emulator_encode refuses a training point whose prefactor is zero
+    (A = 0 lies inside the amplitude range but has no shape to learn: its
+    standardised shapes would be inf/NaN and spoil every column's
+    statistics), and lpp_emulator_predict refuses a range with hi <= lo (the
+    encoding would divide by zero)."""
+    import torch
+    from paper_2202_11839_amd.emulator import Emulator
+    from synth import EMU_RANGES, latin_hypercube
+    n_k = 30
+    pts = latin_hypercube(64, EMU_RANGES, seed=2)
+    pts[17, 0] = 0.0
+    P = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    Y = torch.ones((64, 5, n_k), dtype=torch.float64, device="cuda")
+    emu = Emulator(EMU_RANGES, n_k=n_k, max_batch=64, seed=1)
+    with pytest.raises(lpp.LppError) as e:
+        emu.fit(P, Y, 1.4e-3, 0.2, epochs=1, batch=32)
+    assert e.value.status == 1
+    pts[17, 0] = 0.01
+    P = torch.tensor(pts, dtype=torch.float64, device="cuda")
+    emu.fit(P, Y, 1.4e-3, 0.2, epochs=1, batch=32)
+    out = torch.zeros((64, 5, n_k), dtype=torch.float64, device="cuda")
+    emu.predict(P, out)
+    bad = list(EMU_RANGES)
+    bad[2] = (1.0, 1.0)
+    emu.ranges = [float(v) for r in bad for v in r]
+    with pytest.raises(lpp.LppError) as e:
+        emu.predict(P, out)
+    assert e.value.status == 1

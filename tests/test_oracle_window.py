@@ -1,6 +1,7 @@
 """Pins of the window / template oracle (oracle/window.py) against closed
 forms, quadrature and geometry, independent of its own formulas."""
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -156,3 +157,67 @@ def test_template_is_linear_in_its_amplitudes():
     # the hexadecapole of the cross term depends on f only
     o4 = W.template_plain(K, pfid, r_q, Q, np.array([[0.02, 2.5, 0.6, 0.7, 0.0]]), kout, 1e-3, 0.2)[0]
     assert not np.allclose(o4[3], o1[3])
+
+
+@pytest.mark.parametrize("b,f", [(1.0, 0.0), (2.0, 0.7), (1.3, 0.95)])
+def test_density_and_minus_model_moments_by_quadrature(b, f):
+    """(2l+1) int dmu/2 (b + f mu^2)^2 L_l(mu) (Kaiser) with scipy's Legendre
+    polynomials, and the minus spectrum's m=4 moment of (1/4)(1-mu^2)^2:
+    (2L+1)(L-4)!/(L+4)! int dmu/2 (1/4)(1-mu^2)^2 L^4_L(mu) = 1/420 at L = 4
+    (eq. xi_relations_normalization_coefficients) and 0 at L = 6, 8."""
+    from scipy.special import lpmv
+    got = W.dd_moments(b, f)
+    for l in (0, 2, 4):
+        val = (2 * l + 1) * quad(lambda mu: (b + f * mu * mu) ** 2 * eval_legendre(l, mu), -1, 1,
+                                 epsabs=1e-15, epsrel=1e-13)[0] / 2.0
+        assert abs(got[l] - val) <= 1e-12 * max(1.0, abs(val)), (l, got[l], val)
+    for L in (4, 6, 8):
+        c = (2 * L + 1) * math.factorial(L - 4) / math.factorial(L + 4)
+        val = c * quad(lambda mu: 0.25 * (1 - mu * mu) ** 2 * lpmv(4, L, mu), -1, 1,
+                       epsabs=1e-16, epsrel=1e-13)[0] / 2.0
+        want = float(W.MINUS_XI.get(L, 0))
+        assert abs(val - want) <= 1e-12, (L, val, want)
+
+
+def test_all_families_follow_the_printed_convolutions():
+    """For the validation model of Sec. IV.C (b = 1, f = 0, shapes e_ij T_ij,
+    i.e. A = -1, sigma8 = sigma8_fid, no shot noise) every template row that
+    the paper prints (eq. all_convolutions and the leakage equations) equals
+    H_l of the printed combination: the xi relations (1/6, 2/15, -4/21, 2/35,
+    1/420) times xi^(l') = H^{-1}_{l'}[P], times the printed coefficients of
+    Q_0..Q_8 (tests/golden/window_coefficients.json)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "window_coefficients.json")))
+    xr = {k: float(Fraction(v)) for k, v in gold["xi_relations"].items() if k != "cite"}
+    pfid = 2e4 * (K / 0.02) / (1 + (K / 0.02) ** 2) ** 1.4
+    r_q = np.linspace(5, 3000, 300)
+    Q = np.vstack([np.exp(-r_q / 900.0) * (1.0 if i == 0 else 0.3 * (-1) ** i / (i + 1)) *
+                   (1 + 0.2 * np.sin(r_q / 300.0 + i)) for i in range(5)])
+    kout = np.arange(1, 31) * 0.01
+    s8f = W.sigma8(K, pfid)
+    got = W.template_multipoles(K, pfid, r_q, Q, np.array([[-1.0, 1.0, 0.0, s8f, 0.0]]), kout, 1e-3, 0.2,
+                                sigma8_fid=s8f)[0]
+    rows = ["dd_0", "dd_2", "dd_4", "gd_2", "gd_4", "plus_0", "plus_2", "plus_4", "minus_4"]
+    r = 1.0 / K[::-1]
+    Qg = W.q_on_grid(r_q, Q, r)
+    plin = pfid * np.exp(-(K / 10.0) ** 2)
+    xi = {lp: W.hankel(K, plin, lp, inverse=True)[1] for lp in (0, 2, 4)}
+    norm = {("dd", 0): 1.0, ("gd", 2): xr["gd_L2"], ("plus", 0): xr["plus_l0"], ("plus", 2): xr["plus_l2"],
+            ("plus", 4): xr["plus_l4"], ("minus", 4): xr["minus_L4"]}
+    seen = set()
+    for e in gold["entries"]:
+        seen.add((e["X"], e["l"]))
+    for X, l in sorted(seen):
+        g = np.zeros_like(r)
+        for e in gold["entries"]:
+            if e["X"] == X and e["l"] == l:
+                q = np.array([float(Fraction(v)) for v in e["q"]])
+                g += norm[(X, e["lp"])] * xi[e["lp"]] * np.tensordot(q, Qg, axes=(0, 0))
+        kk, P = W.hankel(r, g, l, inverse=False)
+        want = W.interp_lnk(kk, P, kout)
+        row = got[rows.index(f"{X}_{l}")]
+        assert np.max(np.abs(row - want)) <= 1e-10 * np.max(np.abs(want)), (X, l)
+    # the unprinted rows of this model: the density hexadecapole is leakage too,
+    # and with f = 0 every model multipole of dd and gd above the lowest is zero
+    assert np.max(np.abs(got[rows.index("dd_4")])) > 0
