@@ -242,6 +242,24 @@ lpp_status lpp_template_multipoles(const double* pfid, double k_min, double k_ma
                                    const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
                                    int32_t device_io, void* stream);
 
+/* lpp_template_plain for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, with the device memory of the
+ * call (tables, the xi of a chunk of points, host-I/O staging) taken from a
+ * static 24 MiB array that the library holds on each device it runs on
+ * until the process ends.  Points are processed in chunks that fit the
+ * array (about 135 points per pass, so any n_pts is accepted; large batches
+ * run slower than through lpp_template_plain, whose chunks are 2,048 points).
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (two streams, two threads) race and must be serialised by
+ * the caller; nothing in the array needs to start at zero.  Same errors as
+ * lpp_template_plain; LPP_E_DEVICE if the array's address cannot be
+ * obtained.  Allocates no device memory; synchronises the stream. */
+lpp_status lpp_template_plain_noalloc(const double* pfid, double k_min, double k_max, int32_t n_log,
+                                      const double* r_q, const double* Q, int32_t n_q, const double* params,
+                                      int64_t n_pts, const double* k_out, int32_t n_k, double nbar,
+                                      double sigma_gamma, double* out, int32_t device_io, void* stream);
+
 /* ---- Emulator network (the learned stand-in for lpp_template_plain) ----
  * A fully connected network widths[0] -> ... -> widths[n_layers] with SiLU
  * (x / (1 + exp(-x))) after every layer but the last, trained on the mean

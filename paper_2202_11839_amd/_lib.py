@@ -27,7 +27,7 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
            "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_template_multipoles",
-           "lpp_mlp_create",
+           "lpp_template_plain_noalloc", "lpp_mlp_create",
            "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
            "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit", "lpp_emulator_encode", "lpp_emulator_predict"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_y", "fft_cols_z", "bin_blocks", "gather_density", "gather_shape", "serial",
@@ -416,7 +416,7 @@ def window_coefficient(mX: int, l: int, lp: int, lpp: int) -> float:
     return out.value
 
 
-TEMPLATE_ROWS = {"lpp_template_plain": 5, "lpp_template_multipoles": 9}
+TEMPLATE_ROWS = {"lpp_template_plain": 5, "lpp_template_plain_noalloc": 5, "lpp_template_multipoles": 9}
 TEMPLATE_SERIES = ["DD_l0", "DD_l2", "DD_l4", "GD_L2", "GD_L4", "PLUS_l0", "PLUS_l2", "PLUS_l4", "MINUS_L4"]
 
 
@@ -460,6 +460,14 @@ def template_plain(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar
     (host) or float64 CUDA tensors (device, then ``out`` must be given); the
     tables ``pfid`` (4096), ``r_q``, ``Q`` (5, n_q) and ``k_out`` are host arrays."""
     return _template("lpp_template_plain", pfid, k_min, k_max, r_q, Q, params, k_out, nbar, sigma_gamma, out)
+
+
+def template_plain_noalloc(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float,
+                           sigma_gamma: float, out=None):
+    """lpp_template_plain_noalloc: template_plain with the library's static
+    device scratch instead of per-call device allocations."""
+    return _template("lpp_template_plain_noalloc", pfid, k_min, k_max, r_q, Q, params, k_out, nbar, sigma_gamma,
+                     out)
 
 
 def template_multipoles(pfid, k_min: float, k_max: float, r_q, Q, params, k_out, nbar: float, sigma_gamma: float,

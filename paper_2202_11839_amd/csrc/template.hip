@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -316,6 +317,36 @@ bool carve(double* base, size_t dbl, const Rows& R, int n_k, int64_t want_chunk,
   return o <= dbl;
 }
 
+}  // namespace
+
+// Device scratch of the allocation-free variant (lpp_template_plain_noalloc):
+// 24 MiB on every device the library runs on, held until the process ends.
+// In host code its name is a host-side stand-in, not a device address: the
+// address is looked up per device with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(24) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+lpp_status scratch_address(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return LPP_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return LPP_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LPP_OK;
+}
+
 lpp_status check_args(const double* pfid, double k_min, double k_max, int32_t n_log, const double* r_q,
                       const double* Q, int32_t n_q, const double* params, int64_t n_pts, const double* k_out,
                       int32_t n_k, double nbar, double sigma_gamma, const double* out) {
@@ -332,7 +363,7 @@ lpp_status check_args(const double* pfid, double k_min, double k_max, int32_t n_
 }
 
 // One call: host tables, upload into m, then the two kernels per chunk of
-// points.  `m` holds the device memory of the call.
+// points.  `m` is either freshly allocated or the static scratch.
 lpp_status run_template(const Rows& R, const TemplateMem& m, const double* pfid, double k_min, double k_max,
                         const double* r_q, const double* Q, int32_t n_q, const double* params, int64_t n_pts,
                         const double* k_out, int32_t n_k, double nbar, double sigma_gamma, double* out,
@@ -506,6 +537,27 @@ lpp_status lpp_template_multipoles(const double* pfid, double k_min, double k_ma
                                    int32_t device_io, void* stream) {
   return template_alloc(make_rows(kFamAll, 4), pfid, k_min, k_max, n_log, r_q, Q, n_q, params, n_pts, k_out, n_k,
                         nbar, sigma_gamma, out, device_io, stream);
+}
+
+lpp_status lpp_template_plain_noalloc(const double* pfid, double k_min, double k_max, int32_t n_log,
+                                      const double* r_q, const double* Q, int32_t n_q, const double* params,
+                                      int64_t n_pts, const double* k_out, int32_t n_k, double nbar,
+                                      double sigma_gamma, double* out, int32_t device_io, void* stream) {
+  const lpp_status s0 =
+      check_args(pfid, k_min, k_max, n_log, r_q, Q, n_q, params, n_pts, k_out, n_k, nbar, sigma_gamma, out);
+  if (s0 != LPP_OK) return s0;
+  double* base = nullptr;
+  const lpp_status s1 = scratch_address(&base);
+  if (s1 != LPP_OK || n_pts == 0) return s1;
+  try {
+    const Rows R = make_rows(kFamPlain, 2);
+    TemplateMem m{};
+    if (!carve(base, kScratchBytes / sizeof(double), R, n_k, kChunk, m)) return LPP_E_WORKSPACE;
+    return run_template(R, m, pfid, k_min, k_max, r_q, Q, n_q, params, n_pts, k_out, n_k, nbar, sigma_gamma, out,
+                        device_io, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return LPP_E_NOMEM;
+  }
 }
 
 }  // extern "C"
