@@ -191,6 +191,31 @@ lpp_status lpp_batch_stats(lpp_plan plan, int64_t* captures, int64_t* replays);
 lpp_status lpp_window_multipoles(lpp_plan plan, const lpp_catalog* ran, double alpha, int32_t lmax, int32_t n_rbins,
                                  double rmax, double* Q, double* r_eff, int64_t* counts, double* norm_I);
 
+/* The same window multipoles by direct pair counting of randoms, the
+ * paper's own route (Sec. III.B, eq. windowQ_ell; Sec. IV.C): over the
+ * ordered pairs (i, j), i != j, of the catalog `ran` (typically a random
+ * subsample of the randoms),
+ *   Q[i * n_rbins + b] = (4i+1) alpha^2 sum_{pairs in b} w_i w_j L_{2i}(rhat . dhat) / (V_b norm_I),
+ * V_b = (4 pi / 3)((b+1)^3 - b^3) dr^3, dr = rmax / n_rbins, shell b holding
+ * (b dr)^2 <= r^2 < ((b+1) dr)^2 with r^2 = dx*dx + dy*dy + dz*dz rounded in
+ * FP64 without fused multiply-adds (coincident points are in no shell), and
+ * the pair's line of sight dhat the direction from `observer` to the pair's
+ * midpoint (los = 1, the paper's "direction toward the pair") or to its
+ * first point (los = 0, the end point of the LPP estimator).  alpha weights
+ * the given catalog to the galaxy density (for a subsample of m of M
+ * randoms of equal weight: the full catalog's alpha times M/m) and norm_I
+ * is the estimator's I, so that Q_0 -> 1 as r -> 0.  Outputs as
+ * lpp_window_multipoles (host arrays): Q for l = 0, 2, .., lmax (even, <= 8),
+ * r_eff[b] the mean separation and counts[b] the number of ordered pairs
+ * (exact).  Columns host or device, FP32 or FP64 (summed in FP64); w NULL
+ * = 1; no object may sit at the observer; 2 <= n <= 2^26, 1 <= n_rbins <= 256.
+ * FP64 throughout, all n^2 pairs (about 1e10 pair terms per second);
+ * allocates its own device memory and synchronises `stream`.
+ * LPP_E_NONFINITE for a non-finite column value. */
+lpp_status lpp_window_pairs(const lpp_catalog* ran, double alpha, double norm_I, const double* observer, int32_t los,
+                            int32_t lmax, int32_t n_rbins, double rmax, double* Q, double* r_eff, int64_t* counts,
+                            void* stream);
+
 /* Coefficient of Q_{l''} in the window mixing Q^X_{l l'}(r) of eq.
  * def_of_Q_llp (Sec. III.B): (2l+1) sqrt((l-m)!/(l+m)! (l'+m)!/(l'-m)!)
  * (l'' l l'; 0 0 0)(l'' l l'; 0 m -m), m = mX (0 for delta-delta and plus, 2

@@ -71,14 +71,21 @@ def deposit(pos: np.ndarray, values: np.ndarray, n: int, box: float, origin, p: 
     return out.reshape(n, n, n)
 
 
+def workers() -> int:
+    """Host threads for the FFTs: OMP_NUM_THREADS if set (the share of the
+    host this process may use), else every core."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, int(v)) if v.isdigit() else (os.cpu_count() or 1)
+
+
 def fftn(a: np.ndarray) -> np.ndarray:
-    """Forward 3D DFT, exp(-2 pi i n.c/N) (scipy's FFT on every host core)."""
-    return _sfft.fftn(a, workers=os.cpu_count() or 1)
+    """Forward 3D DFT, exp(-2 pi i n.c/N) (scipy's FFT on workers() threads)."""
+    return _sfft.fftn(a, workers=workers())
 
 
 def ifftn(a: np.ndarray) -> np.ndarray:
-    """Inverse 3D DFT with the 1/N^3 factor (scipy's FFT on every host core)."""
-    return _sfft.ifftn(a, workers=os.cpu_count() or 1)
+    """Inverse 3D DFT with the 1/N^3 factor (scipy's FFT on workers() threads)."""
+    return _sfft.ifftn(a, workers=workers())
 
 
 def signed_modes(n: int) -> np.ndarray:

@@ -267,3 +267,55 @@ def template_multipoles(k: np.ndarray, pfid: np.ndarray, r_q: np.ndarray, Q: np.
     shape (n_pts, 9, n_k)."""
     return template_families(k, pfid, r_q, Q, params, kout, nbar, sigma_gamma, ("dd", "gd", "plus", "minus"),
                              sigma8_fid)
+
+
+# ---------------------------------------------------------------------------
+# window multipoles by pair counting
+
+
+def window_pairs(ran, alpha: float, norm_I: float, observer, los: str, lmax: int, n_rbins: int, rmax: float,
+                 chunk: int = 256) -> Dict:
+    """Q_l(r)/I of eq. windowQ_ell by a direct sum over the ordered pairs
+    (i, j), i != j, of the catalog: each pair separated by r = x_j - x_i adds
+    alpha^2 w_i w_j L_l(rhat . dhat) to the shell b with (b dr)^2 <= |r|^2 <
+    ((b+1) dr)^2, dr = rmax / n_rbins (|r|^2 = dx*dx + dy*dy + dz*dz in FP64;
+    r = 0 in no shell), and Q_l = (2l+1) * sum / (V_b I), V_b the shell's
+    volume.  The pair's line of sight dhat points from the observer to its
+    midpoint (los = "midpoint": the paper's direction toward the pair) or to
+    its first point x_i (los = "endpoint")."""
+    pos = ran.pos()
+    w = ran.w
+    obs = np.asarray(observer, dtype=np.float64)
+    n = pos.shape[0]
+    dr = rmax / n_rbins
+    T = np.array([(b * dr) * (b * dr) for b in range(n_rbins + 1)])
+    ells = list(range(0, lmax + 1, 2))
+    S = np.zeros((len(ells), n_rbins))
+    counts = np.zeros(n_rbins, dtype=np.int64)
+    rsum = np.zeros(n_rbins)
+    for i0 in range(0, n, chunk):
+        xi = pos[i0:i0 + chunk]
+        d = pos[None, :, :] - xi[:, None, :]                      # r = x_j - x_i
+        r2 = d[:, :, 0] * d[:, :, 0] + d[:, :, 1] * d[:, :, 1] + d[:, :, 2] * d[:, :, 2]
+        ii = np.arange(i0, i0 + xi.shape[0])
+        keep = (r2 < T[-1]) & (r2 > 0.0)
+        keep[np.arange(xi.shape[0]), ii] = False
+        b = np.searchsorted(T, r2, side="right") - 1
+        r = np.sqrt(r2)
+        if los == "midpoint":
+            dv = xi[:, None, :] + 0.5 * d - obs[None, None, :]
+        elif los == "endpoint":
+            dv = np.broadcast_to(xi[:, None, :] - obs[None, None, :], d.shape)
+        else:
+            raise ValueError("los must be 'midpoint' or 'endpoint'")
+        mu = np.einsum("ijk,ijk->ij", d, dv) / (np.where(r > 0, r, 1.0) * np.linalg.norm(dv, axis=2))
+        ww = (w[i0:i0 + chunk][:, None] * w[None, :])
+        bk = b[keep]
+        counts += np.bincount(bk, minlength=n_rbins)
+        rsum += np.bincount(bk, weights=r[keep], minlength=n_rbins)
+        for k, l in enumerate(ells):
+            S[k] += np.bincount(bk, weights=(ww * special.peval(special.legendre(l), mu))[keep], minlength=n_rbins)
+    vb = 4.0 * math.pi / 3.0 * np.array([((b + 1) ** 3 - b ** 3) * dr ** 3 for b in range(n_rbins)])
+    Q = np.array([(2 * l + 1) * alpha ** 2 * S[k] / (vb * norm_I) for k, l in enumerate(ells)])
+    r_eff = np.where(counts > 0, rsum / np.where(counts > 0, counts, 1), 0.0)
+    return dict(ells=ells, Q=Q, counts=counts, r_eff=r_eff)

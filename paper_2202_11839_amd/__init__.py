@@ -7,4 +7,4 @@ is its thin Python binding.  Importing it does not load the library; the first
 """
 from ._lib import (LPP_ALL, LPP_DD, LPP_F32, LPP_F64, LPP_GD, LPP_MINUS, LPP_PLUS, LppError, Plan,  # noqa: F401
                    load, version, EXPORTS, LIB_PATH, template_plain, template_plain_noalloc, template_multipoles,
-                   TEMPLATE_SERIES, window_coefficient, Mlp)
+                   TEMPLATE_SERIES, window_coefficient, window_pairs, Mlp)

@@ -26,7 +26,7 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
            "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
-           "lpp_window_multipoles", "lpp_window_coefficient", "lpp_template_plain", "lpp_template_multipoles",
+           "lpp_window_multipoles", "lpp_window_pairs", "lpp_window_coefficient", "lpp_template_plain", "lpp_template_multipoles",
            "lpp_template_plain_noalloc", "lpp_mlp_create",
            "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
            "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit", "lpp_emulator_encode", "lpp_emulator_predict"]
@@ -406,6 +406,34 @@ class Mlp:
                                     C.c_int32(batch), C.c_int32(epochs), C.c_float(lr0), C.c_float(lr1),
                                     C.c_uint64(seed), C.byref(loss)), "lpp_mlp_fit")
         return loss.value
+
+
+def window_pairs(ran, alpha: float, norm_I: float, observer=(0.0, 0.0, 0.0), los: str = "midpoint", lmax: int = 8,
+                 n_rbins: int = 100, rmax: float = 2000.0) -> Dict:
+    """Q_l(r)/I by pair counting of the catalog ``ran`` (lpp_window_pairs);
+    ``los`` "midpoint" (the pair's direction) or "endpoint" (its first point).
+    Columns: numpy arrays (FP64) or CUDA tensors of one dtype."""
+    import numpy as np
+    lib = load()
+    first = ran.x
+    dtype = LPP_F32 if (_is_torch(first) and str(first.dtype) == "torch.float32") else LPP_F64
+    keep: list = []
+    cr = _Cols(ran, dtype, keep)
+    nell = lmax // 2 + 1
+    Q = np.zeros(nell * n_rbins)
+    r_eff = np.zeros(n_rbins)
+    counts = np.zeros(n_rbins, dtype=np.int64)
+    dp = C.POINTER(C.c_double)
+    obs = (C.c_double * 3)(*[float(v) for v in observer])
+    stream = C.c_void_p(0)
+    if cr.struct.on_device:
+        import torch
+        stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(lib.lpp_window_pairs(C.byref(cr.struct), C.c_double(alpha), C.c_double(norm_I), obs,
+                                C.c_int32({"endpoint": 0, "midpoint": 1}[los]), C.c_int32(lmax), C.c_int32(n_rbins),
+                                C.c_double(rmax), Q.ctypes.data_as(dp), r_eff.ctypes.data_as(dp),
+                                counts.ctypes.data_as(C.POINTER(C.c_int64)), stream), "lpp_window_pairs")
+    return dict(ells=list(range(0, lmax + 1, 2)), Q=Q.reshape(nell, n_rbins), r_eff=r_eff, counts=counts)
 
 
 def window_coefficient(mX: int, l: int, lp: int, lpp: int) -> float:

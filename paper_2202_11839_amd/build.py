@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblpp.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["tables.cpp", "kernels_prep.hip", "kernels_gather.hip", "kernels_fft.hip", "kernels_bin.hip",
+SOURCES = ["tables.cpp", "kernels_prep.hip", "kernels_gather.hip", "kernels_fft.hip", "kernels_bin.hip", "kernels_pairs.hip",
            "kernels_window.hip", "template.hip", "mlp.hip", "api.hip"]
 
 ARCH = os.environ.get("LPP_OFFLOAD_ARCH", "gfx950")
