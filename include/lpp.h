@@ -392,6 +392,13 @@ lpp_status lpp_deposit_weights(lpp_plan plan, const lpp_catalog* cat, double sca
 /* In-place forward 3D DFT (exp(-2 pi i n.c/N)) of an N^3 complex device mesh. */
 lpp_status lpp_fft3d(lpp_plan plan, void* mesh);
 
+/* The estimator's own 3D transform on a mesh in its z-blocked order: node or
+ * mode (x, y, z) at ((z/8 N + y) N + x) 8 + z%8 (N^3 complex of the plan's
+ * precision, in place, exp(-2 pi i n.c/N)), with the x, y and z passes, line
+ * counts and non-temporal accesses of lpp_estimate but nothing pruned
+ * (every node read, every mode written). */
+lpp_status lpp_fft3d_zblocked(lpp_plan plan, void* mesh);
+
 /* Per-stage timing.  When on, the plan records a pair of HIP events on its
  * stream around every kernel group of lpp_estimate and accumulates the
  * elapsed milliseconds and kernel launches per stage (enum below) until

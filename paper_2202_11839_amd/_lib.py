@@ -24,7 +24,7 @@ STATUS = ["LPP_OK", "LPP_E_INVALID", "LPP_E_NONFINITE", "LPP_E_OUT_OF_BOX", "LPP
 
 EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set_workspace", "lpp_set_stream",
            "lpp_result_layout", "lpp_series_name", "lpp_estimate", "lpp_estimate_batch", "lpp_deposit_weights",
-           "lpp_fft3d", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
+           "lpp_fft3d", "lpp_fft3d_zblocked", "lpp_status_string", "lpp_version", "lpp_set_profiling", "lpp_get_profile",
            "lpp_reset_profile", "lpp_batch_stats", "lpp_get_tuning", "lpp_set_tuning", "lpp_autotune",
            "lpp_window_multipoles", "lpp_window_pairs", "lpp_window_coefficient", "lpp_template_plain", "lpp_template_multipoles",
            "lpp_template_plain_noalloc", "lpp_mlp_create",
@@ -321,6 +321,13 @@ class Plan:
         import torch
         self.lib.lpp_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
         _check(self.lib.lpp_fft3d(self.handle, C.c_void_p(mesh.data_ptr())), "lpp_fft3d")
+
+    def fft3d_zblocked(self, mesh) -> None:
+        """In-place forward 3D DFT of a contiguous complex torch tensor of N^3
+        values in the estimator's z-blocked order (lpp_fft3d_zblocked)."""
+        import torch
+        self.lib.lpp_set_stream(self.handle, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        _check(self.lib.lpp_fft3d_zblocked(self.handle, C.c_void_p(mesh.data_ptr())), "lpp_fft3d_zblocked")
 
     def set_profiling(self, on: bool) -> None:
         _check(self.lib.lpp_set_profiling(self.handle, 1 if on else 0), "lpp_set_profiling")

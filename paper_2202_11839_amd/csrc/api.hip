@@ -19,6 +19,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lpp_internal.h"
@@ -150,21 +151,28 @@ int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size(
 
 // Work meshes: one gather pass deposits up to kGatherMaxReal density fields
 // (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per
-// grid) into one of two sets of kWork meshes.  FP64 at N >= 1024 keeps sets
-// of kWorkF64Large (two sets of eight 17 GB meshes and the bases would not
-// fit the device), and with them at most four density and two shape fields
-// per pass.
-constexpr int kWork = 8;
+// grid) into one of two sets of kWorkRow meshes.  FP32 up to N = 512 deposits
+// the shape fields with the node-parallel kernel, kNodeFields per pass, into
+// two sets of kWork meshes (42 meshes of 1.07 GB at 512^3; at 1024^3 that
+// would not fit the device).  FP64 at N >= 1024 keeps sets of kWorkF64Large
+// (two sets of eight 17 GB meshes and the bases would not fit the device),
+// and with them at most four density and two shape fields per pass.
+constexpr int kWorkRow = 8;
+constexpr int kWork = 2 * kNodeFields;
 constexpr int kWorkF64Large = 4;
-static_assert(kWork >= kGatherMaxReal && kWork >= 2 * kGatherMaxComplex, "work meshes per gather pass");
-static_assert(kWork >= kGatherMaxRealF64 && kWork >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+static_assert(kWorkRow >= kGatherMaxReal && kWorkRow >= 2 * kGatherMaxComplex, "work meshes per gather pass");
+static_assert(kWorkRow >= kGatherMaxRealF64 && kWorkRow >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+static_assert(kWork >= kWorkRow, "work mesh slots");
+bool node_gather(const lpp_plan_s* p) { return p->cfg.precision == LPP_F32 && p->cfg.mesh_n <= 512; }
 int work_meshes(const lpp_plan_s* p) {
-  return (p->cfg.precision == LPP_F64 && p->cfg.mesh_n >= 1024) ? kWorkF64Large : kWork;
+  if (node_gather(p)) return kWork;
+  return (p->cfg.precision == LPP_F64 && p->cfg.mesh_n >= 1024) ? kWorkF64Large : kWorkRow;
 }
 int max_density_fields(const lpp_plan_s* p) {
   return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxRealF64 : kGatherMaxReal, work_meshes(p));
 }
 int max_shape_fields(const lpp_plan_s* p) {
+  if (node_gather(p)) return kNodeFields;
   return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex, work_meshes(p) / 2);
 }
 lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
@@ -565,7 +573,16 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
                      const Footprint& fp, void* const* W) -> hipError_t {
     hipError_t e = prof_begin(p);
-    if (e == hipSuccess) e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
+    if (e == hipSuccess) {
+      if constexpr (std::is_same<T, float>::value) {
+        if (cplx && node_gather(p))
+          e = launch_gather_nodes(set, starts, p->geo, specs, nf, W, fp.cube, true, gs);
+        else
+          e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
+      } else {
+        e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
+      }
+    }
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
     return e;
   };
@@ -1213,7 +1230,9 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_z, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
-  if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
+  if (s == LPP_OK)
+    s = node_gather(p) ? search(&lpp_tuning::gather_shape, {4, 6, 8, 10}, {LPP_STAGE_DEPOSIT})
+                       : search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;
   std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);
   std::copy(saved_l, saved_l + LPP_N_STAGES, p->prof_launches);
@@ -1473,6 +1492,22 @@ lpp_status lpp_fft3d(lpp_plan p, void* mesh) {
   if (s != LPP_OK) return s;
   const hipError_t e = p->cfg.precision == LPP_F64 ? launch_fft3d<double>(mesh, p->cfg.mesh_n, p->d_tw, p->stream)
                                                    : launch_fft3d<float>(mesh, p->cfg.mesh_n, p->d_tw, p->stream);
+  if (e != hipSuccess) return hip_status(e);
+  return hip_status(hipStreamSynchronize(p->stream));
+}
+
+lpp_status lpp_fft3d_zblocked(lpp_plan p, void* mesh) {
+  if (!p || !mesh) return LPP_E_INVALID;
+  lpp_status s = ensure_tables(p);
+  if (s != LPP_OK) return s;
+  const FftPrune full{nullptr, nullptr, nullptr, INT_MAX};
+  const int N = p->cfg.mesh_n;
+  const int lines[3] = {p->tune.fft_rows_x, p->tune.fft_cols_y, p->tune.fft_cols_z};
+  hipError_t e = hipSuccess;
+  for (int axis = 0; axis < 3 && e == hipSuccess; ++axis)
+    e = p->cfg.precision == LPP_F64
+            ? launch_fft_axis_zb<double>(mesh, N, p->d_tw, axis, full, p->stream, lines[axis], streaming(p))
+            : launch_fft_axis_zb<float>(mesh, N, p->d_tw, axis, full, p->stream, lines[axis], streaming(p));
   if (e != hipSuccess) return hip_status(e);
   return hip_status(hipStreamSynchronize(p->stream));
 }

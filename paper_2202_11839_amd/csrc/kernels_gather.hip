@@ -459,6 +459,214 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   }
 }
 
+// ---- node-parallel deposit of complex (shape) fields ----
+//
+// For the sparse shape set (galaxies only: a few tens of objects per tile
+// region) the row kernel above is bound by its per-tile chain and runs one
+// pass per four fields.  This kernel deposits up to kNodeFields complex
+// fields per pass: one thread per node of an 8^3 tile and all fields'
+// accumulators in its registers, so there is no cross-thread reduction.
+//   1. the tile region's 11^3 cells: per cell the object count, one exclusive
+//      scan over the region in (z, y, x) cell order, and each cell's first
+//      object in the sorted set;
+//   2. staging, in chunks of kNodeCap objects: region-local position, then
+//      one (object, field) pair per thread for the line-of-sight weights;
+//   3. every node sums, in a fixed order, the objects of the 4 x 4 x 4 cells
+//      that reach it (cells n-2 .. n+1 per axis): 16 runs of 4 consecutive
+//      cells in the staged order;
+//   4. one store per field and grid copy; a wavefront writes 64 consecutive
+//      nodes (one y row of a z-group in the z-blocked order).
+// The result is bitwise reproducible and equal, node by node, to a sum over
+// the same objects in another order (the row kernel's), up to rounding.
+
+constexpr int kNodeT = 512;         // threads: one per node of the 8^3 tile
+constexpr int kNodeCells = R * R * R;  // 11^3 region cells
+constexpr int kNodeCap = 256;       // staged objects per chunk
+
+template <typename T, int NF>
+struct SpecSetN {
+  SpecT<T> f[NF];
+};
+
+template <typename T>
+struct MeshSetN {
+  typename V2<T>::type* m[2 * kNodeFields];
+};
+
+// block-wide exclusive scan of one value per thread (512 threads, 8 wavefronts)
+__device__ __forceinline__ uint32_t block_scan512(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kNodeT / 64; ++i) {
+    const uint32_t s = sh[i];
+    base += i < w ? s : 0u;
+    tot += s;
+  }
+  total = tot;
+  __syncthreads();
+  return base + inc - v;
+}
+
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(kNodeT) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
+                                                              int N, int lgN, int interlace, T H, T relx, T rely,
+                                                              T relz, SpecSetN<T, NF> fs, MeshSetN<T> out,
+                                                              const uint8_t* __restrict__ tile_flags, int zblocked) {
+  using T2 = typename V2<T>::type;
+  constexpr int ROWS = 3 + 2 * NF;
+  __shared__ uint32_t coff[kNodeCells + 1];  // staged offset of each region cell (z, y, x order)
+  __shared__ uint32_t cbeg[kNodeCells];      // its first object in the sorted set
+  __shared__ uint32_t wsum[kNodeT / 64];
+  __shared__ __align__(16) T su[ROWS][kNodeCap];
+  __shared__ T trig[4][kNodeCap];            // cos theta, sin theta, cos phi, sin phi of the staged objects
+  __shared__ T amp[2][kNodeCap];             // w g1, w g2
+  const int copies = interlace ? 2 : 1;
+  const int nt = N / TT;
+  const int mask = N - 1;
+  const int tid = threadIdx.x;
+  // whole x tile-rows to the XCDs in turn, as in gather_kernel
+  const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const int tile = (nt * nt) % kXcds == 0 ? ((local / nt) * kXcds + xcd) * nt + local % nt
+                                           : static_cast<int>(blockIdx.x);
+  const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
+  const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
+  if (tile_flags != nullptr && tile_flags[tx + nt * (ty + nt * tz)] == 0) return;
+
+  // 1. region cells: counts, scan, first objects.  Thread t takes the three
+  //    consecutive cells 3t .. 3t+2 of the (z, y, x) order.
+  uint32_t cnt[3], beg[3];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int c = 3 * tid + u;
+    cnt[u] = 0;
+    beg[u] = 0;
+    if (c < kNodeCells) {
+      const int lx = c % R, ly = (c / R) % R, lz = c / (R * R);
+      const int gx = (t0x - 2 + lx) & mask, gy = (t0y - 2 + ly) & mask, gz = (t0z - 2 + lz) & mask;
+      const int64_t g = gx + static_cast<int64_t>(N) * (gy + static_cast<int64_t>(N) * gz);
+      const uint32_t a = cell_start[g], b = cell_start[g + 1];
+      beg[u] = a;
+      cnt[u] = b - a;
+    }
+    mine += cnt[u];
+  }
+  uint32_t total;
+  uint32_t run = block_scan512(mine, wsum, total);
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int c = 3 * tid + u;
+    if (c < kNodeCells) {
+      coff[c] = run;
+      cbeg[c] = beg[u];
+    }
+    run += cnt[u];
+  }
+  if (tid == 0) coff[kNodeCells] = total;
+  __syncthreads();
+
+  // this thread's node and its place in the stores
+  int kx, ky, kz;
+  if (zblocked) {
+    kz = tid & 7;
+    kx = (tid >> 3) & 7;
+    ky = tid >> 6;
+  } else {
+    kx = tid & 7;
+    ky = (tid >> 3) & 7;
+    kz = tid >> 6;
+  }
+  T acc[4 * NF];  // [field][copy][re, im]
+#pragma unroll
+  for (int i = 0; i < 4 * NF; ++i) acc[i] = 0;
+
+  const T half = static_cast<T>(0.5);
+  for (uint32_t c0 = 0; c0 < total; c0 += kNodeCap) {
+    const uint32_t c1 = min(total, c0 + static_cast<uint32_t>(kNodeCap));
+    const int nc = static_cast<int>(c1 - c0);
+    // 2a. positions, line-of-sight angles and weights of the chunk's objects
+    for (int d = tid; d < nc; d += kNodeT) {
+      const uint32_t k = c0 + d;
+      int lo = 0, hi = kNodeCells;  // coff[lo] <= k < coff[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (coff[mid] <= k) lo = mid; else hi = mid;
+      }
+      const uint32_t src = cbeg[lo] + (k - coff[lo]);
+      const ObjPos<T> rec = o.pos[src];
+      const uint32_t key = rec.key;
+      const int cx = static_cast<int>(key & mask);
+      const int cy = static_cast<int>((key >> lgN) & mask);
+      const int cz = static_cast<int>(key >> (2 * lgN));
+      const int lx = lo % R, ly = (lo / R) % R, lz = lo / (R * R);
+      su[0][d] = static_cast<T>(lx) + rec.fx;
+      su[1][d] = static_cast<T>(ly) + rec.fy;
+      su[2][d] = static_cast<T>(lz) + rec.fz;
+      const T px = relx + (static_cast<T>(cx) + rec.fx) * H;
+      const T py = rely + (static_cast<T>(cy) + rec.fy) * H;
+      const T pz = relz + (static_cast<T>(cz) + rec.fz) * H;
+      const T rinv = static_cast<T>(1) / sqrt(px * px + py * py + pz * pz);
+      const T xx = px * rinv, xy = py * rinv, xz = pz * rinv;
+      const T st = sqrt(xx * xx + xy * xy);
+      trig[0][d] = xz;
+      trig[1][d] = st;
+      trig[2][d] = st > 0 ? xx / st : static_cast<T>(1);
+      trig[3][d] = st > 0 ? xy / st : static_cast<T>(0);
+      amp[0][d] = o.wr[src];
+      amp[1][d] = o.wi[src];
+    }
+    __syncthreads();
+    // 2b. the line-of-sight weighted values, one (object, field) pair per thread
+    for (int i = tid; i < nc * NF; i += kNodeT) {
+      const int d = i / NF, q = i % NF;
+      const T ar = amp[0][d], ai = amp[1][d];
+      T gr = 1, gi = 0;
+#pragma unroll
+      for (int qq = 0; qq < NF; ++qq)
+        if (qq == q && (fs.f[qq].L > 0 || fs.f[qq].s > 0))
+          los_weight(fs.f[qq], trig[0][d], trig[1][d], trig[2][d], trig[3][d], gr, gi);
+      su[3 + 2 * q][d] = ar * gr - ai * gi;
+      su[4 + 2 * q][d] = ar * gi + ai * gr;
+    }
+    __syncthreads();
+    // 3. this node's sums: cells x in kx..kx+3, y in ky..ky+3, z in kz..kz+3 of the region
+    const T nxc = static_cast<T>(kx + 2), nyc = static_cast<T>(ky + 2), nzc = static_cast<T>(kz + 2);
+    for (int dz = 0; dz < 4; ++dz)
+      for (int dy = 0; dy < 4; ++dy) {
+        const int cell0 = kx + R * ((ky + dy) + R * (kz + dz));
+        const uint32_t lo = max(coff[cell0], c0), hi = min(coff[cell0 + 4], c1);
+        for (uint32_t k = lo; k < hi; ++k) {
+          const int d = static_cast<int>(k - c0);
+          const T ux = su[0][d], uy = su[1][d], uz = su[2][d];
+          const T w0 = window<T, P>(ux - nxc) * window<T, P>(uy - nyc) * window<T, P>(uz - nzc);
+          const T w1 = interlace ? window<T, P>(ux - nxc - half) * window<T, P>(uy - nyc - half) *
+                                       window<T, P>(uz - nzc - half)
+                                 : static_cast<T>(0);
+#pragma unroll
+          for (int q = 0; q < NF; ++q) {
+            const T vr = su[3 + 2 * q][d], vi = su[4 + 2 * q][d];
+            acc[4 * q + 0] += vr * w0;
+            acc[4 * q + 1] += vi * w0;
+            acc[4 * q + 2] += vr * w1;
+            acc[4 * q + 3] += vi * w1;
+          }
+        }
+      }
+    __syncthreads();
+  }
+  // 4. stores
+  const int64_t idx = node_at(t0x + kx, t0y + ky, t0z + kz, N, zblocked);
+#pragma unroll
+  for (int q = 0; q < NF; ++q) {
+    out.m[q * copies][idx] = T2{acc[4 * q + 0], acc[4 * q + 1]};
+    if (interlace) out.m[q * copies + 1][idx] = T2{acc[4 * q + 2], acc[4 * q + 3]};
+  }
+}
+
 // ---- counting sort of objects by cell ----
 
 __device__ __forceinline__ int cell_of(double u, int N) {
@@ -800,6 +1008,58 @@ hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* or
   const int64_t threads = (ncell + kOrderCells - 1) / kOrderCells;
   cell_order_kernel<T><<<static_cast<unsigned>((threads + 255) / 256), 256, 0, st>>>(starts, ncell, order, out, shape);
   return hipGetLastError();
+}
+
+template <typename T, int NF>
+hipError_t dispatch_nodes(int p, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
+                          const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
+  const T H = static_cast<T>(g.los_h), rx = static_cast<T>(g.los_rel[0]), ry = static_cast<T>(g.los_rel[1]),
+          rz = static_cast<T>(g.los_rel[2]);
+  SpecSetN<T, NF> fs;
+  for (int q = 0; q < NF; ++q) fs.f[q] = to_spec<T>(specs[q]);
+  MeshSetN<T> ms{};
+  const int nm = g.interlace ? 2 * NF : NF;
+  for (int m = 0; m < nm; ++m) ms.m[m] = static_cast<typename V2<T>::type*>(meshes[m]);
+  int lg = 0;
+  while ((1 << lg) < g.N) ++lg;
+  const int nt = g.N / TT;
+  const dim3 grid(static_cast<unsigned>(nt) * nt * nt);
+  switch (p) {
+    case 1:
+      gather_nodes_kernel<T, 1, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                              tiles, zb);
+      break;
+    case 2:
+      gather_nodes_kernel<T, 2, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                              tiles, zb);
+      break;
+    default:
+      gather_nodes_kernel<T, 3, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
+                                                              tiles, zb);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
+                               const FieldSpec* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
+                               bool zblocked, hipStream_t st) {
+  static_assert(kNodeFields == 10, "node passes of 1 to 10 fields");
+  const int zb = zblocked ? 1 : 0;
+  if (g.N % TT != 0) return hipErrorInvalidValue;
+  switch (nf) {
+    case 1: return dispatch_nodes<float, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 2: return dispatch_nodes<float, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 3: return dispatch_nodes<float, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 4: return dispatch_nodes<float, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 5: return dispatch_nodes<float, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 6: return dispatch_nodes<float, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 7: return dispatch_nodes<float, 7>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 8: return dispatch_nodes<float, 8>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 9: return dispatch_nodes<float, 9>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 10: return dispatch_nodes<float, 10>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>

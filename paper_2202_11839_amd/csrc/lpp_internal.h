@@ -186,10 +186,17 @@ constexpr int kGatherMaxReal = 8;
 constexpr int kGatherMaxRealF64 = 8;
 constexpr int kGatherMaxComplex = 4;
 constexpr int kGatherMaxComplexF64 = 4;
+// complex fields per pass of the node-parallel shape deposit (FP32)
+constexpr int kNodeFields = 10;
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
                          int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
                          hipStream_t st);
+// The same for nf <= kNodeFields complex FP32 fields with one thread per node
+// of each 8^3 tile (same mesh order and results up to the order of the sums).
+hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
+                               const FieldSpec* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
+                               bool zblocked, hipStream_t st);
 
 // plain-layout 3D transform (the public entry point)
 template <typename T>

@@ -117,10 +117,11 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.delenv("LPP_AUTOTUNE_CACHE", raising=False)
     plan = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     t = plan.tuning()
+    # FP32 up to N = 512: ten shape fields per pass (the node-parallel deposit)
     assert t == {"fft_rows_x": 8, "fft_cols_y": 16, "fft_cols_z": 8, "bin_blocks": 8192, "gather_density": 8,
-                 "gather_shape": 4, "serial": 0, "fft_streaming": 15}
+                 "gather_shape": 10, "serial": 0, "fft_streaming": 15}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_y=32), dict(fft_cols_z=4),
-                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=5),
+                dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=11),
                 dict(serial=2), dict(fft_streaming=7), dict(fft_streaming=16)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
@@ -139,8 +140,11 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     p64 = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f64", lmax=4, n_kbins=50)
     assert p64.tuning()["fft_cols_y"] == 8 and p64.tuning()["fft_cols_z"] == 8 and p64.tuning()["fft_rows_x"] == 8
     assert p64.tuning()["fft_streaming"] == 15
-    assert pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4,
-                    n_kbins=50).tuning()["fft_streaming"] == 13
+    p1k = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
+    assert p1k.tuning()["fft_streaming"] == 13
+    assert p1k.tuning()["gather_shape"] == 4   # the row deposit at 1024^3 (the node deposit's meshes would not fit)
+    with pytest.raises(pkg.LppError):
+        p1k.set_tuning(gather_shape=5)
     for bad in (dict(fft_cols_y=16), dict(fft_cols_z=16)):
         with pytest.raises(pkg.LppError):
             p64.set_tuning(**bad)
