@@ -512,7 +512,7 @@ __device__ __forceinline__ uint32_t block_scan512(uint32_t v, uint32_t* sh, uint
 }
 
 template <typename T, int P, int NF>
-__global__ void __launch_bounds__(kNodeT) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
+__global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
                                                               int N, int lgN, int interlace, T H, T relx, T rely,
                                                               T relz, SpecSetN<T, NF> fs, MeshSetN<T> out,
                                                               const uint8_t* __restrict__ tile_flags, int zblocked) {
@@ -524,6 +524,7 @@ __global__ void __launch_bounds__(kNodeT) gather_nodes_kernel(GObjSet<T> o, cons
   __shared__ __align__(16) T su[ROWS][kNodeCap];
   __shared__ T trig[4][kNodeCap];            // cos theta, sin theta, cos phi, sin phi of the staged objects
   __shared__ T amp[2][kNodeCap];             // w g1, w g2
+  __shared__ SpecT<T> sspec[NF];             // the fields' line-of-sight polynomials
   const int copies = interlace ? 2 : 1;
   const int nt = N / TT;
   const int mask = N - 1;
@@ -535,6 +536,9 @@ __global__ void __launch_bounds__(kNodeT) gather_nodes_kernel(GObjSet<T> o, cons
   const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
   const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
   if (tile_flags != nullptr && tile_flags[tx + nt * (ty + nt * tz)] == 0) return;
+#pragma unroll
+  for (int q = 0; q < NF; ++q)
+    if (tid == q) sspec[q] = fs.f[q];
 
   // 1. region cells: counts, scan, first objects.  Thread t takes the three
   //    consecutive cells 3t .. 3t+2 of the (z, y, x) order.
@@ -620,17 +624,22 @@ __global__ void __launch_bounds__(kNodeT) gather_nodes_kernel(GObjSet<T> o, cons
       amp[1][d] = o.wi[src];
     }
     __syncthreads();
-    // 2b. the line-of-sight weighted values, one (object, field) pair per thread
-    for (int i = tid; i < nc * NF; i += kNodeT) {
-      const int d = i / NF, q = i % NF;
-      const T ar = amp[0][d], ai = amp[1][d];
-      T gr = 1, gi = 0;
-#pragma unroll
-      for (int qq = 0; qq < NF; ++qq)
-        if (qq == q && (fs.f[qq].L > 0 || fs.f[qq].s > 0))
-          los_weight(fs.f[qq], trig[0][d], trig[1][d], trig[2][d], trig[3][d], gr, gi);
-      su[3 + 2 * q][d] = ar * gr - ai * gi;
-      su[4 + 2 * q][d] = ar * gi + ai * gr;
+    // 2b. the line-of-sight weighted values: wavefront w takes the fields
+    //     q = w, w + 8, .. (one polynomial per wavefront, so its lanes do not
+    //     diverge), its lanes the objects
+    {
+      const int wave = tid >> 6, lane = tid & 63;
+      for (int q = wave; q < NF; q += kNodeT / 64) {
+        const SpecT<T>& f = sspec[q];
+        const bool plain = f.L == 0 && f.s == 0;
+        for (int d = lane; d < nc; d += 64) {
+          const T ar = amp[0][d], ai = amp[1][d];
+          T gr = 1, gi = 0;
+          if (!plain) los_weight(f, trig[0][d], trig[1][d], trig[2][d], trig[3][d], gr, gi);
+          su[3 + 2 * q][d] = ar * gr - ai * gi;
+          su[4 + 2 * q][d] = ar * gi + ai * gr;
+        }
+      }
     }
     __syncthreads();
     // 3. this node's sums: cells x in kx..kx+3, y in ky..ky+3, z in kz..kz+3 of the region
