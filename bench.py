@@ -167,11 +167,45 @@ def committed_traffic(kernel_names):
     return rec.get("bytes_per_launch")
 
 
-def batch_c3(lpp, torch, k, reps):
-    """The 256^3 batch workload: k mocks spread over the 64-mock size ladder
-    N_i = round(0.2e6 10^(i/63)) galaxies (10x randoms), each with its own
-    GRF, device-resident in float32, through lpp_estimate_batch (one captured
-    graph, replayed) and, for comparison, through lpp_estimate one by one."""
+def model_bytes_c2(wl, n_gal, n_ran):
+    """The whole-estimate algorithmic byte model of the l <= 4 estimate: per
+    field and interlaced copy a deposit write (1 M_c), a two-pass transform
+    read and write (4 M_c) and a shell-sum read (1 M_c), plus one read of the
+    field's base (1 M_c), the real density fields at half: (38 x 13 +
+    15 x 6.5) M_c, M_c = N^3 x 8 B; plus one read of the FP64 catalog columns."""
+    mc = 8.0 * wl["mesh"] ** 3
+    return (38 * 13 + 15 * 6.5) * mc + 8.0 * (7 * n_gal + 5 * n_ran)
+
+
+def committed_estimate_traffic():
+    """Counter-measured HBM bytes of one whole estimate (every kernel's
+    FETCH_SIZE and WRITE_SIZE, scaled by the calibration copy) from the
+    committed record, if it was taken on the current kernel and host sources
+    (their SHA-256 are in the record)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "estimate_c2_fp32_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        digests = rec.get("sources_sha256") or {}
+        if not digests:
+            return None
+        for name, want in digests.items():
+            with open(os.path.join(ROOT, "paper_2202_11839_amd", "csrc", name), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != want:
+                    return None
+    except OSError:
+        return None
+    return rec.get("bytes_per_estimate")
+
+
+def batch_c3(lpp, torch, k, reps, tune_cache):
+    """The 256^3 batch workload: k mocks of the 64-mock size ladder
+    N_i = round(0.2e6 10^(i/63)) galaxies (10x randoms; k = 64 is the whole
+    ladder), each with its own GRF, device-resident in float32, through
+    lpp_estimate_batch (one captured graph, replayed) with the launch shapes
+    lpp_autotune picks on the largest mock (cached in tune_cache), and, for
+    comparison, through lpp_estimate one by one."""
     import numpy as np
     from synth import WORKLOADS, c3_sizes, make_catalogs
     wl = dict(WORKLOADS["c3"])
@@ -185,10 +219,17 @@ def batch_c3(lpp, torch, k, reps):
                                 for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
         gals.append(f(g))
         rans.append(f(r))
+        if len(gals) % 16 == 0:
+            log(f"batch: {len(gals)}/{len(pick)} mocks generated ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     ngal = sum(ladder[i] for i in pick)
     log(f"batch: {len(pick)} mocks generated in {time.perf_counter() - t0:.1f} s ({ngal} galaxies)")
     plan = plan_for(lpp, wl, "f32")
+    default_shapes = plan.tuning()
+    t0 = time.perf_counter()
+    tuned = plan.autotune(gals[-1], rans[-1], tune_cache)
+    t_tune = time.perf_counter() - t0
+    log(f"batch: autotuned on the largest mock in {t_tune:.1f} s: {tuned}")
     outs = plan.estimate_batch(gals, rans)  # capture
     assert all(isinstance(o, dict) for o in outs), outs
     torch.cuda.synchronize()
@@ -207,11 +248,17 @@ def batch_c3(lpp, torch, k, reps):
     torch.cuda.synchronize()
     de = time.perf_counter() - t0
     caps, launches = plan.batch_stats()
+    # the batch's algorithmic bytes per mock from the whole-estimate model (two-pass transforms)
+    mc = 8.0 * wl["mesh"] ** 3
+    model_bytes = (38 * 13 + 15 * 6.5) * mc
     log(f"batch: {len(pick)} mocks in {1e3 * dt:.1f} ms per batch (graph), {1e3 * de:.1f} ms one by one")
     return {"workload": f"{len(pick)} mocks of the 256^3 wedge batch (mock indices {pick[0]}..{pick[-1]} of the "
                         f"0.2M-2M galaxy ladder, 10x randoms)", "mocks": len(pick), "galaxies": ngal,
             "mocks_per_s": round(len(pick) / dt, 3), "ms_per_batch": round(1e3 * dt, 2),
-            "eager_mocks_per_s": round(len(pick) / de, 3), "graph_captures": caps, "graph_launches": launches}
+            "ms_per_mock": round(1e3 * dt / len(pick), 3),
+            "model_frac_per_mock": round(model_bytes / (dt / len(pick)) / 1e9 / HBM_PEAK_GBS, 4),
+            "eager_mocks_per_s": round(len(pick) / de, 3), "graph_captures": caps, "graph_launches": launches,
+            "autotune_s": round(t_tune, 1), "tuning": tuned, "default_tuning": default_shapes}
 
 
 def emulator_c5(lpp, torch, wl, ran, gal, rdev, epochs):
@@ -298,50 +345,248 @@ def emulator_c5(lpp, torch, wl, ran, gal, rdev, epochs):
     sep_rel, _ = accuracy(sepv.reshape(2000, 5, 30), Y[20000:].cpu().numpy())
     out["separable_ms_2000_host"] = round(1e3 * t_sep, 3)
     out["separable_max_rel_err"] = float(sep_rel.max())
+    # the same separable map as one device matrix product (4 basis rows, FP64)
+    coef_d = torch.tensor(coef, device="cuda")
+    basis_d = torch.tensor(basis, device="cuda")
+    (coef_d @ basis_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        sep_d = coef_d @ basis_d
+    torch.cuda.synchronize()
+    t_sep_d = (time.perf_counter() - t0) / 10
+    out["separable_ms_2000_device"] = round(1e3 * t_sep_d, 4)
+    out["speedup_vs_separable_host"] = round(t_sep / t_emu, 2)
+    out["speedup_vs_separable_device"] = round(t_sep_d / t_emu, 2)
+    del sep_d
     log(f"emulator: plain {1e3 * t_plain2k:.2f} ms / 2000 pts, emulator {1e3 * t_emu:.3f} ms, "
         f"max held-out err {rel.max():.4f}, separable {1e3 * t_sep:.3f} ms (err {sep_rel.max():.1e})")
     return out
 
 
-def cpu_baseline(wl, gal, ran):
-    """The FP64 oracle timed on a bounded sample of the same workload.
-
-    Sample: one interlaced copy of the oracle's unit of work at the full mesh,
-    i.e. (a) the FP64 deposit of the density set (galaxies and randoms), (b)
-    one numpy 3D FFT of the mesh and (c) the complex deposit of the shape
-    set.  The oracle's FFT route does 2 copies x (23 density-set + 59
-    shape-set) such transforms per estimate (its Cartesian-tensor count at
-    l <= 4: 1 + 22 density, 1 + 22 + 21 + 15 shape), so
-    t_estimate = 2 (23 (a + b) + 59 (c + b)); shell sums are not included,
-    which makes the baseline an upper bound on the oracle's rate."""
+def _shell_modes(n, n_kbins, dn):
+    """Per k-shell the distinct |n|^2 of its modes and their multiplicities
+    (the estimator's shells: T_b <= |n|^2 < T_{b+1}, T_b = ceil((b dn)^2),
+    n != 0, |n_i| < N/2)."""
     import numpy as np
-    from oracle import mesh as M
+    num, den = dn
+    T = [-((-(b * b * num * num)) // (den * den)) for b in range(n_kbins + 1)]
+    h = int(math.isqrt(T[-1])) + 1
+    m = np.arange(-h, h + 1)
+    q = (m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2).ravel()
+    cnt = np.bincount(q, minlength=T[-1] + 1)
+    out = []
+    for b in range(n_kbins):
+        qs = np.arange(max(T[b], 1), T[b + 1])
+        out.append((qs[cnt[qs] > 0], cnt[qs][cnt[qs] > 0]))
+    return out
+
+
+def validation_f2(lpp, torch, n_mocks):
+    """The paper's validation (Sec. IV.A-C) at field level on its own
+    geometry: Gaussian density fields on a 512^3 mesh of a 3000 Mpc/h periodic
+    box, the tidal field projected at every mesh node inside the BOSS-NGC-like
+    window (RA 120-260, Dec -5-70 deg, r 1000-1500 Mpc/h; 9.9M nodes) with
+    each node's own line of sight, measured with the LPP estimator (case (a)),
+    with the GPP estimator along the window's central direction (case (b),
+    inconsistent lines of sight), and the field projected along that
+    direction measured with GPP (case (c)).  The mean over the mocks is
+    compared with the window-convolved templates of eq. all_convolutions
+    (lpp_template_multipoles at A = -1, b = 1, f = 0, sigma8 = sigma8_fid:
+    P_gd = (1-mu^2)P/2, P_+ = P_- = (1-mu^2)^2 P/4, eq. power_for_validation)
+    averaged over each shell's modes, built from the window's Q_l: end-point
+    FFT route on a padded 6000 Mpc/h box whose 1024^3 nodes contain the
+    mock's (case (a)), midpoint and end-point pair counts of 200,000 random
+    points in the window (case (a), the paper's route), and the FFT route
+    about the global direction (case (c))."""
+    import numpy as np
+    from synth import power_spectrum
+    from synth.fieldmocks import FieldMocks
+    t0 = time.perf_counter()
+    fm = FieldMocks()
+    log(f"validation: {fm.count} window nodes ({time.perf_counter() - t0:.1f} s set-up)")
+    n, box, nb, dn = 512, 3000.0, 24, (4, 1)
+    common = dict(assignment=1, interlacing=0, compensate=0, precision="f32", lmax=4, n_kbins=nb, dn=dn)
+    plan_l = lpp.Plan(n, box, tuple(fm.origin), tuple(fm.observer), **common)
+    plan_g = lpp.Plan(n, box, tuple(fm.origin), tuple(fm.observer), los=tuple(fm.nhat), **common)
+    series = plan_l.series
+    sums = {c: [] for c in "abc"}
+    kinfo = None
+    t0 = time.perf_counter()
+    t_est = 0.0
+    for mock in range(n_mocks):
+        gl, gg, ran = fm.realise(mock)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for case, plan, gal in (("a", plan_l, gl), ("b", plan_g, gl), ("c", plan_g, gg)):
+            r = plan.estimate(gal, ran)
+            v = np.array(r["re"])
+            # field-level mocks carry no Poisson noise: add back what the estimator subtracted
+            v[series.index("DD_l0")] += r["shot_dd"]
+            v[series.index("PLUS_l0")] += r["shot_plus"]
+            for name in ("EE_l0", "BB_l0"):
+                v[series.index(name)] += 0.5 * r["shot_plus"]
+            sums[case].append(v)
+            kinfo = r
+        t_est += time.perf_counter() - ts
+        if (mock + 1) % 16 == 0:
+            log(f"validation: {mock + 1}/{n_mocks} mocks ({time.perf_counter() - t0:.1f} s)")
+    del plan_l, plan_g
+    torch.cuda.empty_cache()
+    # window multipoles
+    alpha = 1.0
+    wplan = lpp.Plan(1024, 2 * box, tuple(fm.origin - box / 2), tuple(fm.observer), assignment=1, interlacing=0,
+                     compensate=0, precision="f32", lmax=4, n_kbins=8)
+    win_a = wplan.window_multipoles(ran, alpha, lmax=8, n_rbins=250, rmax=box)
+    del wplan
+    torch.cuda.empty_cache()
+    wplan = lpp.Plan(1024, 2 * box, tuple(fm.origin - box / 2), tuple(fm.observer), assignment=1, interlacing=0,
+                     compensate=0, precision="f32", lmax=4, n_kbins=8, los=tuple(fm.nhat))
+    win_c = wplan.window_multipoles(ran, alpha, lmax=8, n_rbins=250, rmax=box)
+    del wplan
+    torch.cuda.empty_cache()
+    # pair counts of random points drawn uniformly in the window (the paper's
+    # route): W = n W_window with n = 1/H^3 the nodes' density, so each of the
+    # m points carries alpha = V_window / (m H^3)
+    from synth import Catalog, seed_seq, wedge_uniform, wedge_volume
+    from synth.fieldmocks import PAPER_WINDOW
+    m_pts = 200_000
+    rp = wedge_uniform(m_pts, seed_seq(6, 0, 3), PAPER_WINDOW["ra"], PAPER_WINDOW["dec"], PAPER_WINDOW["r"]) + \
+        fm.observer[None, :]
+    pts = Catalog(rp[:, 0].copy(), rp[:, 1].copy(), rp[:, 2].copy(), None, None)
+    vol = wedge_volume(PAPER_WINDOW["ra"], PAPER_WINDOW["dec"], PAPER_WINDOW["r"])
+    alpha_p = vol / (m_pts * fm.h ** 3)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    pairs_mid = lpp.window_pairs(pts, alpha_p, win_a["norm_I"], tuple(fm.observer), "midpoint", 8, 250, box)
+    t_pairs = time.perf_counter() - tp
+    pairs_end = lpp.window_pairs(pts, alpha_p, win_a["norm_I"], tuple(fm.observer), "endpoint", 8, 250, box)
+    # templates, averaged over each shell's modes
+    kgrid = np.exp(np.linspace(np.log(1e-5), np.log(1e3), 4096))
+    pfid = power_spectrum(kgrid)
+    x = 8.0 * kgrid
+    wth = 3.0 * (np.sin(x) - x * np.cos(x)) / x ** 3
+    s8 = math.sqrt(float(np.sum(0.5 * (np.diff(np.log(kgrid))) *
+                              ((kgrid ** 3 * pfid * wth ** 2)[1:] + (kgrid ** 3 * pfid * wth ** 2)[:-1])) /
+                       (2 * math.pi ** 2)))
+    par = np.array([[-1.0, 1.0, 0.0, s8, 0.0]])
+    kf = 2 * math.pi / box
+    kfine = np.exp(np.linspace(np.log(0.5 * kf), np.log(1.2 * kf * nb * dn[0] / dn[1]), 256))
+    shells = _shell_modes(n, nb, dn)
+
+    def template(win):
+        sel = win["counts"] > 0
+        t = lpp.template_multipoles(pfid, 1e-5, 1e3, win["r_eff"][sel], win["Q"][:, sel], par, kfine, 1.0, 0.0)[0]
+        out = np.zeros((9, nb))
+        for b, (qs, mult) in enumerate(shells):
+            kk = kf * np.sqrt(qs)
+            for o in range(9):
+                out[o, b] = np.sum(mult * np.interp(np.log(kk), np.log(kfine), t[o])) / np.sum(mult)
+        return out
+    tmpl = {"a_fft_endpoint": template(win_a), "a_pairs_midpoint": template(pairs_mid),
+            "a_pairs_endpoint": template(pairs_end), "c_fft_global": template(win_c)}
+    k_eff = np.asarray(kinfo["k_eff"])
+    tnames = list(lpp.TEMPLATE_SERIES)
+    rec = {"workload": (f"{n_mocks} field-level mocks, 512^3 mesh of a 3000 Mpc/h box, BOSS-NGC-like window "
+                        f"RA 120-260 Dec -5-70 r 1000-1500 Mpc/h ({fm.count} nodes), NGP on the nodes, {nb} shells "
+                        f"of width {dn[0] * kf:.5f} h/Mpc"),
+           "mocks": n_mocks, "estimates_per_s": round(3 * n_mocks / t_est, 2),
+           "window_pairs_s_200k_midpoint": round(t_pairs, 2), "k_eff": [round(v, 5) for v in k_eff],
+           "n_modes": [int(v) for v in kinfo["n_modes"]]}
+
+    def stats(case, names):
+        v = np.stack(sums[case])
+        mean = v.mean(axis=0)
+        err = v.std(axis=0, ddof=1) / math.sqrt(v.shape[0])
+        return {nm: (mean[series.index(nm)], err[series.index(nm)]) for nm in names}
+    main = ["DD_l0", "GD_L2", "PLUS_l0", "PLUS_l2", "PLUS_l4", "MINUS_L4"]
+    leak = ["DD_l2", "GD_L4"]
+    out_cases = {}
+    for case, tkey in (("a", "a_pairs_midpoint"), ("a", "a_pairs_endpoint"), ("a", "a_fft_endpoint"),
+                       ("b", "a_pairs_midpoint"), ("c", "c_fft_global")):
+        st = stats(case, main + leak)
+        T = tmpl[tkey]
+        d = {}
+        for nm in main + leak:
+            mean, err = st[nm]
+            tv = T[tnames.index(nm)]
+            ref = tv if nm in main else T[tnames.index("DD_l0" if nm == "DD_l2" else "GD_L2")]
+            d[nm] = {"frac_diff": [round(float(v), 4) for v in (mean - tv) / np.abs(ref)],
+                     "err_frac": [round(float(v), 4) for v in err / np.abs(ref)]}
+        out_cases[f"case_{case}_vs_{tkey}"] = d
+    rec["comparison"] = out_cases
+    # the end-point vs midpoint difference of the window multipoles themselves
+    sel = (pairs_mid["counts"] > 0) & (pairs_end["counts"] > 0)
+    q0 = np.max(np.abs(pairs_mid["Q"][0][sel]))
+    rec["window_endpoint_vs_midpoint_max_abs_dQ_over_Q0max"] = {
+        f"l{2 * i}": round(float(np.max(np.abs(pairs_mid["Q"][i][sel] - pairs_end["Q"][i][sel])) / q0), 5)
+        for i in range(5)}
+    selw = sel & (win_a["counts"] > 0)
+    rec["window_fft_vs_pairs_endpoint_max_abs_dQ_over_Q0max"] = {
+        f"l{2 * i}": round(float(np.max(np.abs(win_a["Q"][i][selw] - pairs_end["Q"][i][selw])) / q0), 5)
+        for i in range(5)}
+    log(f"validation: {n_mocks} mocks x 3 estimates in {t_est:.1f} s; pairs {t_pairs:.2f} s")
+    return rec
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, gal, ran):
+    """The FP64 oracle (oracle.estimator.mesh64, the paper's Cartesian-tensor
+    FFT route) timed on a bounded sample of the same workload, on the host
+    threads scipy's FFT is given (oracle.mesh.workers()).
+
+    The oracle's estimate is a sum of independent units, one per monomial of
+    its Cartesian tensors: deposit the per-object coefficient on the grid and
+    on the interlaced grid, transform both, combine, compensate, multiply by
+    the monomial of khat and accumulate.  At l <= 4 it runs 23 such units on
+    the density set (galaxies and randoms) and 59 on the shape set
+    (galaxies), plus the shell sums.  The sample times one unit of each kind
+    at the full mesh and one shell sum; the estimate's time is
+    23 t_density + 59 t_shape + 15 t_shell."""
+    import numpy as np
+    from oracle import estimator as E, mesh as M
     n, box, origin, p = wl["mesh"], wl["box"], wl["origin"], wl["assignment"]
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=wl["observer"], assignment=p,
+                   interlacing=wl["interlacing"], n_kbins=wl["n_kbins"], lmax=4)
+    kx, ky, kz, kk = E._khat(n)
+    comp = M.compensation(n, p)
+    phase = M.interlace_phase(n)
     gpos, rpos = gal.pos(), ran.pos()
     allpos = np.concatenate([gpos, rpos])
     alpha = gal.w.sum() / ran.w.sum()
     w = np.concatenate([gal.w, -alpha * ran.w])
     t0 = time.perf_counter()
-    D = M.deposit(allpos, w, n, box, origin, p)
+    acc = kx * kx * E._transform(cfg, allpos, w, comp, phase)
     ta = time.perf_counter() - t0
-    log(f"cpu baseline: density deposit {ta:.1f} s")
+    log(f"cpu baseline: one density-set unit {ta:.1f} s")
     t0 = time.perf_counter()
-    F = np.fft.fftn(D)
-    tb = time.perf_counter() - t0
-    del D, F
-    log(f"cpu baseline: fft {tb:.1f} s")
-    t0 = time.perf_counter()
-    G = M.deposit(gpos, gal.w * (gal.g1 + 1j * gal.g2), n, box, origin, p)
+    acc = acc + kx * ky * E._transform(cfg, gpos, gal.w * (gal.g1 + 1j * gal.g2), comp, phase)
     tc = time.perf_counter() - t0
-    del G
-    log(f"cpu baseline: shape deposit {tc:.1f} s")
-    t_est = 2 * (23 * (ta + tb) + 59 * (tc + tb))
-    return {"value": 1.0 / t_est, "unit": "estimates/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one interlaced copy at {n}^3: FP64 deposit of {gal.n + ran.n} density objects "
-                       f"({ta:.1f} s), one numpy FFT ({tb:.1f} s), complex deposit of {gal.n} shape objects "
-                       f"({tc:.1f} s); scaled to 2 x (23 density + 59 shape) transforms per estimate; "
-                       "numpy FFT and bincount are single-threaded"),
-            "seconds_sampled": ta + tb + tc}
+    log(f"cpu baseline: one shape-set unit {tc:.1f} s")
+    num, den = cfg.bin_width()
+    t0 = time.perf_counter()
+    bidx = M.bin_index(n, cfg.n_kbins, num, den)
+    E._bin_sums(cfg, bidx, acc * np.conj(acc))
+    tb = time.perf_counter() - t0
+    del acc, bidx, kx, ky, kz, kk
+    t_est = 23 * ta + 59 * tc + 15 * tb
+    return {"value": 1.0 / t_est, "unit": "estimates/s", "cores": M.workers(), "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "sample": (f"one unit of each kind of the FP64 oracle's FFT route at {n}^3 (deposit on both grids, two "
+                       f"scipy FFTs, interlace combine, compensation, monomial product): density set of "
+                       f"{gal.n + ran.n} objects {ta:.1f} s, shape set of {gal.n} objects {tc:.1f} s, one shell "
+                       f"sum {tb:.1f} s; estimate = 23 + 59 units + 15 shell sums"),
+            "seconds_sampled": round(ta + tc + tb, 1)}
 
 
 def main():
@@ -352,14 +597,22 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--batch-mocks", type=int, default=8,
+    ap.add_argument("--batch-mocks", type=int, default=64,
                     help="mocks of the 256^3 batch workload (spread over its 64-mock size ladder) "
                          "timed through the graph-captured batch path; 0 skips it")
+    ap.add_argument("--lmax8", type=int, default=1,
+                    help="1: also time the l <= 8 estimate of the same catalogs (FP32)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--emulator", type=int, default=1,
                     help="1: window multipoles of the 512^3 randoms, the plain template path over the 22,000-point "
                          "design and the emulator trained on 20,000 of them (accuracy on the other 2,000, speedup)")
     ap.add_argument("--emu-epochs", type=int, default=1500)
+    ap.add_argument("--validation-mocks", type=int, default=64,
+                    help="field-level mocks of the paper's validation (its 512^3, 3000 Mpc/h box and BOSS-NGC-like "
+                         "window), LPP / inconsistent GPP / GPP estimates against the window-convolved templates; "
+                         "0 skips it")
+    ap.add_argument("--only", default="",
+                    help="comma-separated legs to run alone (validation); the main estimate line is then not printed")
     ap.add_argument("--serial", type=int, default=0,
                     help="1: run each estimate's deposits and transforms on one stream (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -390,6 +643,13 @@ def main():
     from synth import WORKLOADS, make_catalogs
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.only:
+        legs = set(args.only.split(","))
+        rec = {}
+        if "validation" in legs:
+            rec["validation_f2"] = validation_f2(lpp, torch, args.validation_mocks)
+        print(json.dumps(rec), flush=True)
+        return
     wl = dict(WORKLOADS[args.workload])
     t0 = time.perf_counter()
     # above 512^3 the galaxies are drawn from a 512^3 GRF of the same box (the
@@ -430,6 +690,17 @@ def main():
             "alg_bytes_per_launch": round(alg_bytes), "avg_launch_ms": round(avg_ms, 4), "launches": launches,
             "stage_ms_per_step": {k: round(v[0] / psteps, 3) for k, v in prof.items()},
             "stages_serial_ms_per_step": round(sum(v[0] for v in prof.values()) / psteps, 2)}
+    # the whole estimate against the same peak: the algorithmic byte model, and
+    # the counter-measured bytes of every kernel of one estimate
+    mb = model_bytes_c2(wl, gal.n, ran.n) if args.workload == "c2" else None
+    cb = committed_estimate_traffic() if args.workload == "c2" else None
+    roof["whole_estimate"] = {
+        "model_bytes": None if mb is None else round(mb),
+        "model_frac": None if mb is None else round(mb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "counter_bytes": None if cb is None else round(cb),
+        "counter_frac": None if cb is None else round(cb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"whole estimate: model {roof['whole_estimate']['model_frac']}, counters {roof['whole_estimate']['counter_frac']} "
+        "of the HBM peak")
 
     extra = {}
     if args.fp64_steps > 0:
@@ -442,8 +713,21 @@ def main():
         log(f"fp64: {1e3 * dt64 / args.fp64_steps:.1f} ms/estimate")
         del plan64
 
+    if args.lmax8:
+        wl8 = dict(wl, lmax=8)
+        plan8 = plan_for(lpp, wl8, "f32")
+        dt8, res8, _ = time_steps(plan8, gdev, rdev, max(1, min(args.steps, 3)), 1, torch)
+        extra["lmax8"] = {"ms_per_step": round(1e3 * dt8 / max(1, min(args.steps, 3)), 2),
+                          "series": len(res8["series"]), "fft_fields": 1 + 5 + 9 + 13 + 17 + 5 + 9 + 13 + 17 +
+                          1 + 5 + 9 + 13 + 17 + 9 + 13 + 17}
+        log(f"lmax 8: {extra['lmax8']['ms_per_step']} ms/estimate")
+        del plan8
+        torch.cuda.empty_cache()
     if args.batch_mocks > 0:
-        extra["batch_c3"] = batch_c3(lpp, torch, args.batch_mocks, args.batch_reps)
+        extra["batch_c3"] = batch_c3(lpp, torch, args.batch_mocks, args.batch_reps,
+                                     os.path.join(ROOT, "gpurun_out", "lpp_autotune_c3.jsonl"))
+    if args.validation_mocks > 0:
+        extra["validation_f2"] = validation_f2(lpp, torch, args.validation_mocks)
     if args.emulator:
         extra["emulator_c5"] = emulator_c5(lpp, torch, wl, ran, gal, rdev, args.emu_epochs)
 

@@ -60,6 +60,8 @@ struct lpp_plan_s {
   void* d_tw = nullptr;
   void* d_phase = nullptr;
   void* d_invw = nullptr;
+  // FP32 specs of the shape set's fields in pass order (the node-parallel deposit)
+  const SpecT<float>* d_spec = nullptr;
   int device = -1;
   // per-stage timing with HIP events on the plan's stream
   bool prof_on = false;
@@ -170,6 +172,15 @@ int work_meshes(const lpp_plan_s* p) {
 }
 int max_density_fields(const lpp_plan_s* p) {
   return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxRealF64 : kGatherMaxReal, work_meshes(p));
+}
+// The fields of the shape set in the order the passes deposit them: the
+// set's base (spin 0, L = 0) first, then its other fields in table order.
+std::vector<FieldSpec> shape_specs(const lpp_plan_s* p) {
+  std::vector<FieldSpec> out;
+  if (p->cfg.spectra & (LPP_PLUS | LPP_MINUS)) out.push_back(make_spec(0, 0, 0, 0));
+  for (const Field& f : p->tab.fields)
+    if (f.fam != FAM_DD) out.push_back(f.spec);
+  return out;
 }
 int max_shape_fields(const lpp_plan_s* p) {
   if (node_gather(p)) return kNodeFields;
@@ -283,9 +294,15 @@ lpp_status ensure_tables(lpp_plan_s* p) {
   const size_t o_tw = align_up(8 * (nb + 1));
   const size_t o_ph = o_tw + align_up(2 * rs * N);
   const size_t o_iw = o_ph + align_up(2 * rs * (3 * N + 1));
-  const size_t total = o_iw + align_up(rs * N);
+  const std::vector<FieldSpec> sg = shape_specs(p);
+  const size_t o_sg = o_iw + align_up(rs * N);
+  const size_t total = o_sg + align_up(sizeof(SpecT<float>) * sg.size());
   std::vector<char> host(total, 0);
   std::memcpy(host.data() + o_thr, p->tab.thr.data(), 8 * (nb + 1));
+  for (size_t i = 0; i < sg.size(); ++i) {
+    const SpecT<float> v = to_spec<float>(sg[i]);
+    std::memcpy(host.data() + o_sg + i * sizeof(SpecT<float>), &v, sizeof v);
+  }
   const int pw = p->cfg.assignment;
   for (int m = 0; m < N; ++m) {
     const double a = -2.0 * M_PI * m / N;
@@ -332,6 +349,7 @@ lpp_status ensure_tables(lpp_plan_s* p) {
   p->d_tw = c + o_tw;
   p->d_phase = c + o_ph;
   p->d_invw = c + o_iw;
+  p->d_spec = reinterpret_cast<const SpecT<float>*>(c + o_sg);
   return LPP_OK;
 }
 
@@ -571,12 +589,12 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   double* base_rows[2] = {acc + static_cast<size_t>(2) * nb * na, acc + static_cast<size_t>(2) * nb * na + 4 * nb};
   // kernel groups, each timed as one stage when profiling is on
   auto deposit = [&](const GObjSet<T>& set, const uint32_t* starts, const FieldSpec* specs, int nf, int cplx,
-                     const Footprint& fp, void* const* W) -> hipError_t {
+                     const Footprint& fp, void* const* W, size_t j0) -> hipError_t {
     hipError_t e = prof_begin(p);
     if (e == hipSuccess) {
       if constexpr (std::is_same<T, float>::value) {
         if (cplx && node_gather(p))
-          e = launch_gather_nodes(set, starts, p->geo, specs, nf, W, fp.cube, true, gs);
+          e = launch_gather_nodes(set, starts, p->geo, p->d_spec + j0, nf, W, fp.cube, true, gs);
         else
           e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
       } else {
@@ -621,7 +639,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
       for (int q = 0; q < nf; ++q) specs[q] = jobs[j0 + q].spec;
       void* const* W = Wset[pass & 1];
       if (overlap && pass >= 2) LPP_TRY(hipStreamWaitEvent(gs, p->ev_done[pass & 1], 0));
-      LPP_TRY(deposit(set, starts, specs, nf, cplx, fp, W));
+      LPP_TRY(deposit(set, starts, specs, nf, cplx, fp, W, j0));
       if (overlap) {
         LPP_TRY(hipEventRecord(p->ev_dep[pass & 1], gs));
         LPP_TRY(hipStreamWaitEvent(st, p->ev_dep[pass & 1], 0));
@@ -892,7 +910,8 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
                                 streaming(p));
     return e;
   };
-  const int per = resolved_tuning(p).gather_density;  // one packed mesh each, in work set 0
+  // one packed mesh each, in work set 0 (the row kernel: at most kGatherMaxReal per pass)
+  const int per = std::min(resolved_tuning(p).gather_density, kGatherMaxReal);
   int pending = -1;  // field waiting in slot 0 of Zc
   bool counted = false;
   auto bin_pair = [&](int fa, int fb) -> hipError_t {

@@ -29,31 +29,6 @@ struct V2<double> {
 };
 
 template <typename T>
-struct SpecT {
-  int s, L, M, cs;
-  int nq[5];
-  T q[5][9];
-  T binom[5];
-  T scale;
-};
-
-template <typename T>
-SpecT<T> to_spec(const FieldSpec& f) {
-  SpecT<T> o{};
-  o.s = f.s;
-  o.L = f.L;
-  o.M = f.M;
-  o.cs = f.cs;
-  for (int j = 0; j < 5; ++j) {
-    o.nq[j] = f.nq[j];
-    o.binom[j] = static_cast<T>(f.binom[j]);
-    for (int i = 0; i < 9; ++i) o.q[j][i] = static_cast<T>(f.q[j][i]);
-  }
-  o.scale = static_cast<T>(f.scale);
-  return o;
-}
-
-template <typename T>
 __device__ __forceinline__ T ipow(T b, int e) {
   T r = static_cast<T>(1);
   for (int i = 0; i < e; ++i) r *= b;
@@ -459,34 +434,35 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   }
 }
 
-// ---- node-parallel deposit of complex (shape) fields ----
+// ---- node-parallel deposit ----
 //
 // For the sparse shape set (galaxies only: a few tens of objects per tile
-// region) the row kernel above is bound by its per-tile chain and runs one
-// pass per four fields.  This kernel deposits up to kNodeFields complex
-// fields per pass: one thread per node of an 8^3 tile and all fields'
-// accumulators in its registers, so there is no cross-thread reduction.
+// region) the row kernel above is bound by its per-tile chain of dependent
+// loads and the cross-thread reduction of its partial rows, at one pass per
+// four fields.  This kernel deposits up to kNodeFields complex fields per
+// pass: one thread per node of an 8^3 tile with all fields' accumulators in
+// its registers, so there is no cross-thread reduction.  (It also takes real
+// fields, K = 1; for the dense density set it measured slower than the row
+// kernel, whose per-row window products serve several nodes, so the
+// library instantiates only K = 2.)
 //   1. the tile region's 11^3 cells: per cell the object count, one exclusive
 //      scan over the region in (z, y, x) cell order, and each cell's first
 //      object in the sorted set;
-//   2. staging, in chunks of kNodeCap objects: region-local position, then
-//      one (object, field) pair per thread for the line-of-sight weights;
+//   2. staging, in chunks of kNodeCap objects: region-local positions and
+//      line-of-sight angles, then the line-of-sight weighted values with one
+//      field per wavefront (the lanes do not diverge);
 //   3. every node sums, in a fixed order, the objects of the 4 x 4 x 4 cells
 //      that reach it (cells n-2 .. n+1 per axis): 16 runs of 4 consecutive
 //      cells in the staged order;
-//   4. one store per field and grid copy; a wavefront writes 64 consecutive
-//      nodes (one y row of a z-group in the z-blocked order).
-// The result is bitwise reproducible and equal, node by node, to a sum over
-// the same objects in another order (the row kernel's), up to rounding.
+//   4. one store per field (real fields: grid and interlaced grid packed)
+//      or per field and grid copy (complex fields); a wavefront writes 64
+//      consecutive nodes (one y row of a z-group in the z-blocked order).
+// The result is bitwise reproducible and equal, node by node, to the row
+// kernel's sum over the same objects in another order, up to rounding.
 
-constexpr int kNodeT = 512;         // threads: one per node of the 8^3 tile
+constexpr int kNodeT = 512;            // threads: one per node of the 8^3 tile
 constexpr int kNodeCells = R * R * R;  // 11^3 region cells
-constexpr int kNodeCap = 256;       // staged objects per chunk
-
-template <typename T, int NF>
-struct SpecSetN {
-  SpecT<T> f[NF];
-};
+constexpr int kNodeCap = 256;          // staged objects per chunk
 
 template <typename T>
 struct MeshSetN {
@@ -511,19 +487,24 @@ __device__ __forceinline__ uint32_t block_scan512(uint32_t v, uint32_t* sh, uint
   return base + inc - v;
 }
 
-template <typename T, int P, int NF>
+// K = 1: NF real fields, mesh q <- (grid, interlaced grid) of field q;
+// K = 2: NF complex fields, mesh q * copies + c <- grid copy c of field q.
+template <typename T, int P, int K, int NF>
 __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
-                                                              int N, int lgN, int interlace, T H, T relx, T rely,
-                                                              T relz, SpecSetN<T, NF> fs, MeshSetN<T> out,
-                                                              const uint8_t* __restrict__ tile_flags, int zblocked) {
+                                                                 int N, int lgN, int interlace, T H, T relx, T rely,
+                                                                 T relz, const SpecT<T>* __restrict__ specs,
+                                                                 MeshSetN<T> out,
+                                                                 const uint8_t* __restrict__ tile_flags,
+                                                                 int zblocked) {
   using T2 = typename V2<T>::type;
-  constexpr int ROWS = 3 + 2 * NF;
+  constexpr int ROWS = 3 + K * NF;
+  constexpr int NA = 2 * K * NF;             // accumulators: [field][copy][component]
   __shared__ uint32_t coff[kNodeCells + 1];  // staged offset of each region cell (z, y, x order)
   __shared__ uint32_t cbeg[kNodeCells];      // its first object in the sorted set
   __shared__ uint32_t wsum[kNodeT / 64];
   __shared__ __align__(16) T su[ROWS][kNodeCap];
   __shared__ T trig[4][kNodeCap];            // cos theta, sin theta, cos phi, sin phi of the staged objects
-  __shared__ T amp[2][kNodeCap];             // w g1, w g2
+  __shared__ T amp[K][kNodeCap];             // w (K = 1); w g1, w g2 (K = 2)
   __shared__ SpecT<T> sspec[NF];             // the fields' line-of-sight polynomials
   const int copies = interlace ? 2 : 1;
   const int nt = N / TT;
@@ -536,9 +517,7 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
   const int tx = tile % nt, ty = (tile / nt) % nt, tz = tile / (nt * nt);
   const int t0x = tx * TT, t0y = ty * TT, t0z = tz * TT;
   if (tile_flags != nullptr && tile_flags[tx + nt * (ty + nt * tz)] == 0) return;
-#pragma unroll
-  for (int q = 0; q < NF; ++q)
-    if (tid == q) sspec[q] = fs.f[q];
+  if (tid < NF) sspec[tid] = specs[tid];
 
   // 1. region cells: counts, scan, first objects.  Thread t takes the three
   //    consecutive cells 3t .. 3t+2 of the (z, y, x) order.
@@ -584,9 +563,9 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
     ky = (tid >> 3) & 7;
     kz = tid >> 6;
   }
-  T acc[4 * NF];  // [field][copy][re, im]
+  T acc[NA];
 #pragma unroll
-  for (int i = 0; i < 4 * NF; ++i) acc[i] = 0;
+  for (int i = 0; i < NA; ++i) acc[i] = 0;
 
   const T half = static_cast<T>(0.5);
   for (uint32_t c0 = 0; c0 < total; c0 += kNodeCap) {
@@ -621,7 +600,7 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
       trig[2][d] = st > 0 ? xx / st : static_cast<T>(1);
       trig[3][d] = st > 0 ? xy / st : static_cast<T>(0);
       amp[0][d] = o.wr[src];
-      amp[1][d] = o.wi[src];
+      if (K == 2) amp[K - 1][d] = o.wi[src];
     }
     __syncthreads();
     // 2b. the line-of-sight weighted values: wavefront w takes the fields
@@ -633,11 +612,15 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
         const SpecT<T>& f = sspec[q];
         const bool plain = f.L == 0 && f.s == 0;
         for (int d = lane; d < nc; d += 64) {
-          const T ar = amp[0][d], ai = amp[1][d];
           T gr = 1, gi = 0;
           if (!plain) los_weight(f, trig[0][d], trig[1][d], trig[2][d], trig[3][d], gr, gi);
-          su[3 + 2 * q][d] = ar * gr - ai * gi;
-          su[4 + 2 * q][d] = ar * gi + ai * gr;
+          if (K == 1) {
+            su[3 + q][d] = amp[0][d] * gr;
+          } else {
+            const T ar = amp[0][d], ai = amp[K - 1][d];
+            su[3 + 2 * q][d] = ar * gr - ai * gi;
+            su[3 + 2 * q + (K - 1)][d] = ar * gi + ai * gr;
+          }
         }
       }
     }
@@ -656,13 +639,13 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
                                        window<T, P>(uz - nzc - half)
                                  : static_cast<T>(0);
 #pragma unroll
-          for (int q = 0; q < NF; ++q) {
-            const T vr = su[3 + 2 * q][d], vi = su[4 + 2 * q][d];
-            acc[4 * q + 0] += vr * w0;
-            acc[4 * q + 1] += vi * w0;
-            acc[4 * q + 2] += vr * w1;
-            acc[4 * q + 3] += vi * w1;
-          }
+          for (int q = 0; q < NF; ++q)
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+              const T v = su[3 + K * q + c][d];
+              acc[(2 * q + 0) * K + c] += v * w0;
+              acc[(2 * q + 1) * K + c] += v * w1;
+            }
         }
       }
     __syncthreads();
@@ -671,8 +654,12 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
   const int64_t idx = node_at(t0x + kx, t0y + ky, t0z + kz, N, zblocked);
 #pragma unroll
   for (int q = 0; q < NF; ++q) {
-    out.m[q * copies][idx] = T2{acc[4 * q + 0], acc[4 * q + 1]};
-    if (interlace) out.m[q * copies + 1][idx] = T2{acc[4 * q + 2], acc[4 * q + 3]};
+    if (K == 1) {
+      out.m[q][idx] = T2{acc[2 * q], acc[2 * q + 1]};
+    } else {
+      out.m[q * copies][idx] = T2{acc[(2 * q) * K], acc[(2 * q) * K + 1]};
+      if (interlace) out.m[q * copies + 1][idx] = T2{acc[(2 * q + 1) * K], acc[(2 * q + 1) * K + 1]};
+    }
   }
 }
 
@@ -1019,15 +1006,15 @@ hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* or
   return hipGetLastError();
 }
 
-template <typename T, int NF>
-hipError_t dispatch_nodes(int p, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
-                          const FieldSpec* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
+template <int K, int NF>
+hipError_t dispatch_nodes(int p, const GObjSet<float>& o, const uint32_t* starts, const Geometry& g,
+                          const SpecT<float>* specs, void* const* meshes, const uint8_t* tiles, int zb,
+                          hipStream_t st) {
+  using T = float;
   const T H = static_cast<T>(g.los_h), rx = static_cast<T>(g.los_rel[0]), ry = static_cast<T>(g.los_rel[1]),
           rz = static_cast<T>(g.los_rel[2]);
-  SpecSetN<T, NF> fs;
-  for (int q = 0; q < NF; ++q) fs.f[q] = to_spec<T>(specs[q]);
   MeshSetN<T> ms{};
-  const int nm = g.interlace ? 2 * NF : NF;
+  const int nm = (K == 2 && g.interlace) ? 2 * NF : NF;
   for (int m = 0; m < nm; ++m) ms.m[m] = static_cast<typename V2<T>::type*>(meshes[m]);
   int lg = 0;
   while ((1 << lg) < g.N) ++lg;
@@ -1035,40 +1022,38 @@ hipError_t dispatch_nodes(int p, const GObjSet<T>& o, const uint32_t* starts, co
   const dim3 grid(static_cast<unsigned>(nt) * nt * nt);
   switch (p) {
     case 1:
-      gather_nodes_kernel<T, 1, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
-                                                              tiles, zb);
+      gather_nodes_kernel<T, 1, K, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz,
+                                                                 specs, ms, tiles, zb);
       break;
     case 2:
-      gather_nodes_kernel<T, 2, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
-                                                              tiles, zb);
+      gather_nodes_kernel<T, 2, K, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz,
+                                                                 specs, ms, tiles, zb);
       break;
     default:
-      gather_nodes_kernel<T, 3, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz, fs, ms,
-                                                              tiles, zb);
+      gather_nodes_kernel<T, 3, K, NF><<<grid, kNodeT, 0, st>>>(o, starts, g.N, lg, g.interlace, H, rx, ry, rz,
+                                                                 specs, ms, tiles, zb);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
-                               const FieldSpec* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
-                               bool zblocked, hipStream_t st) {
-  static_assert(kNodeFields == 10, "node passes of 1 to 10 fields");
-  const int zb = zblocked ? 1 : 0;
-  if (g.N % TT != 0) return hipErrorInvalidValue;
-  switch (nf) {
-    case 1: return dispatch_nodes<float, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 2: return dispatch_nodes<float, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 3: return dispatch_nodes<float, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 4: return dispatch_nodes<float, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 5: return dispatch_nodes<float, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 6: return dispatch_nodes<float, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 7: return dispatch_nodes<float, 7>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 8: return dispatch_nodes<float, 8>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 9: return dispatch_nodes<float, 9>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 10: return dispatch_nodes<float, 10>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    default: return hipErrorInvalidValue;
+template <int K, int NF>
+hipError_t nodes_upto(int nf, int p, const GObjSet<float>& o, const uint32_t* starts, const Geometry& g,
+                      const SpecT<float>* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
+  if constexpr (NF == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (nf == NF) return dispatch_nodes<K, NF>(p, o, starts, g, specs, meshes, tiles, zb, st);
+    return nodes_upto<K, NF - 1>(nf, p, o, starts, g, specs, meshes, tiles, zb, st);
   }
+}
+
+hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
+                               const SpecT<float>* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
+                               bool zblocked, hipStream_t st) {
+  const int zb = zblocked ? 1 : 0;
+  if (g.N % TT != 0 || nf < 1) return hipErrorInvalidValue;
+  return nodes_upto<2, kNodeFields>(nf, g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
 }
 
 template <typename T>

@@ -41,6 +41,33 @@ struct FieldSpec {
   double scale;            // kappa_{LM} * s!
 };
 
+// A FieldSpec in the deposit's precision, as the kernels read it (kernel
+// arguments, or a device table for the node-parallel deposit).
+template <typename T>
+struct SpecT {
+  int s, L, M, cs;
+  int nq[5];
+  T q[5][9];
+  T binom[5];
+  T scale;
+};
+
+template <typename T>
+SpecT<T> to_spec(const FieldSpec& f) {
+  SpecT<T> o{};
+  o.s = f.s;
+  o.L = f.L;
+  o.M = f.M;
+  o.cs = f.cs;
+  for (int j = 0; j < 5; ++j) {
+    o.nq[j] = f.nq[j];
+    o.binom[j] = static_cast<T>(f.binom[j]);
+    for (int i = 0; i < 9; ++i) o.q[j][i] = static_cast<T>(f.q[j][i]);
+  }
+  o.scale = static_cast<T>(f.scale);
+  return o;
+}
+
 // Family of a field and the series it accumulates into.
 enum Family { FAM_DD = 0, FAM_GD = 1, FAM_PLUS = 2, FAM_MINUS = 3 };
 
@@ -186,16 +213,17 @@ constexpr int kGatherMaxReal = 8;
 constexpr int kGatherMaxRealF64 = 8;
 constexpr int kGatherMaxComplex = 4;
 constexpr int kGatherMaxComplexF64 = 4;
-// complex fields per pass of the node-parallel shape deposit (FP32)
+// complex (shape) fields per pass of the node-parallel deposit (FP32)
 constexpr int kNodeFields = 10;
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
                          int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
                          hipStream_t st);
 // The same for nf <= kNodeFields complex FP32 fields with one thread per node
-// of each 8^3 tile (same mesh order and results up to the order of the sums).
+// of each 8^3 tile (same mesh order and results up to the order of the
+// sums); the fields' specs are read from the device table `specs` (nf entries).
 hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
-                               const FieldSpec* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
+                               const SpecT<float>* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
                                bool zblocked, hipStream_t st);
 
 // plain-layout 3D transform (the public entry point)

@@ -4,15 +4,21 @@
     Per-kernel launch count, average and total duration from a
     ``--kernel-trace`` SQLite database (rocprofv3's ``*_results.db``).
 
-``traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB [--kernel REGEX]``
+``traffic FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB [--kernel REGEX | --estimates K]``
     HBM bytes per launch of the kernels whose name matches REGEX, from a
     ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the same program.
     Both counters are scaled by what they read for a plain device copy of
     known size (``bench.py --copy-calibration``: 1 GiB read and 1 GiB written
     per ``__amd_rocclr_copyBuffer`` launch), and the SHA-256 of the kernel
     source and of the host code that sequences its launches is recorded, so
-    that a stale figure can be recognised.  Without
-    --kernel: a table of read and written bytes per launch of every kernel.
+    that a stale figure can be recognised.  With --estimates K: the bytes of
+    every library kernel launched by a run of K estimates, per estimate (the
+    record keeps the SHA-256 of every library source).  Without either: a
+    table of read and written bytes per launch of every kernel.
+
+``sq DB [DB ...] --kernel REGEX``
+    Mean value per launch of every counter in ``--pmc`` runs, for the
+    kernels whose name matches REGEX.
 """
 from __future__ import annotations
 
@@ -103,7 +109,30 @@ def main() -> None:
                    help="source files whose SHA-256 the record keeps (default: the FFT kernels and the "
                         "host code that sets their launch sequence)")
     t.add_argument("--command", default="")
+    t.add_argument("--estimates", type=int, default=0)
+    q = sub.add_parser("sq")
+    q.add_argument("dbs", nargs="+")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--command", default="")
     args = ap.parse_args()
+
+    if args.mode == "sq":
+        pat = re.compile(args.kernel)
+        if args.command:
+            print(f"# command: {args.command}")
+        per: dict[str, dict[str, list[float]]] = {}
+        for db in args.dbs:
+            con = sqlite3.connect(db)
+            for kname, cname, value in con.execute("select name, counter_name, counter_value from pmc_events"):
+                k = _short(kname)
+                if pat.search(k):
+                    per.setdefault(k, {}).setdefault(cname, []).append(float(value))
+        for k in sorted(per):
+            print(f"## {k}")
+            for c in sorted(per[k]):
+                vs = per[k][c]
+                print(f"{c:32s} {statistics.mean(vs):16.1f}   ({len(vs)} launches)")
+        return
 
     if args.mode == "kernels":
         rows = kernel_table(args.db)
@@ -125,6 +154,20 @@ def main() -> None:
         return
 
     fs, ws = scale(args.copy_fetch_db, "FETCH_SIZE"), scale(args.copy_write_db, "WRITE_SIZE")
+    if args.estimates > 0:
+        rd = sum(v for n, vs in counter(args.fetch_db, "FETCH_SIZE").items() if n.startswith("lpp::") or
+                 "lpp::" in n for v in vs) * fs / args.estimates
+        wr = sum(v for n, vs in counter(args.write_db, "WRITE_SIZE").items() if n.startswith("lpp::") or
+                 "lpp::" in n for v in vs) * ws / args.estimates
+        digests = {}
+        for name in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+            with open(os.path.join(HERE, "csrc", name), "rb") as f:
+                digests[name] = hashlib.sha256(f.read()).hexdigest()
+        rec = {"estimates": args.estimates, "read_bytes_per_estimate": round(rd), "write_bytes_per_estimate": round(wr),
+               "bytes_per_estimate": round(rd + wr), "fetch_scale_bytes_per_unit": fs,
+               "write_scale_bytes_per_unit": ws, "sources_sha256": digests, "command": args.command}
+        print(json.dumps(rec, indent=1))
+        return
     if not args.kernel:
         fetch_all, write_all = counter(args.fetch_db, "FETCH_SIZE"), counter(args.write_db, "WRITE_SIZE")
         dur = {}
