@@ -17,8 +17,13 @@
     table of read and written bytes per launch of every kernel.
 
 ``sq DB [DB ...] --kernel REGEX``
-    Mean value per launch of every counter in ``--pmc`` runs, for the
-    kernels whose name matches REGEX.
+    Per launch of the kernels whose name matches REGEX, every counter of the
+    ``--pmc`` runs given: the SQ counters summed over the shader engines that
+    report them, the GRBM counters averaged over the XCDs (each reports the
+    whole GPU's clock), then the mean over launches; and, where the counters
+    are there, the VALU issue fraction (wave64 VALU instructions x 4 cycles
+    over the SIMDs' cycles), the active lanes per VALU instruction and the
+    mean resident waves per CU (SQ_WAVE_CYCLES counts in units of 4 cycles).
 """
 from __future__ import annotations
 
@@ -30,6 +35,7 @@ import re
 import sqlite3
 import statistics
 
+CUS, SIMDS = 256, 1024
 COPY_BYTES = 1 << 30  # bytes read and bytes written by one calibration copy
 HERE = os.path.dirname(os.path.abspath(__file__))
 # a traffic record holds for these sources only: the strided-pass kernel and
@@ -123,15 +129,30 @@ def main() -> None:
         per: dict[str, dict[str, list[float]]] = {}
         for db in args.dbs:
             con = sqlite3.connect(db)
-            for kname, cname, value in con.execute("select name, counter_name, counter_value from pmc_events"):
+            inst: dict[tuple, list[float]] = {}
+            for kname, disp, cname, value in con.execute(
+                    "select name, dispatch_id, counter_name, counter_value from pmc_events"):
                 k = _short(kname)
                 if pat.search(k):
-                    per.setdefault(k, {}).setdefault(cname, []).append(float(value))
+                    inst.setdefault((k, disp, cname), []).append(float(value))
+            for (k, _, cname), vs in inst.items():
+                v = statistics.mean(vs) if cname.startswith("GRBM_") else sum(vs)
+                per.setdefault(k, {}).setdefault(cname, []).append(v)
+        print(f"# MI355X: {SIMDS} SIMDs in {CUS} CUs; a wave64 VALU instruction occupies its SIMD for 4 cycles")
         for k in sorted(per):
+            m = {c: statistics.mean(vs) for c, vs in per[k].items()}
             print(f"## {k}")
-            for c in sorted(per[k]):
-                vs = per[k][c]
-                print(f"{c:32s} {statistics.mean(vs):16.1f}   ({len(vs)} launches)")
+            for c in sorted(m):
+                print(f"{c:32s} {m[c]:18.1f}   ({len(per[k][c])} launches)")
+            clk = m.get("GRBM_GUI_ACTIVE")
+            if clk and "SQ_INSTS_VALU" in m:
+                print(f"{'= VALU issue fraction':32s} {4 * m['SQ_INSTS_VALU'] / (SIMDS * clk):18.3f}")
+            if m.get("SQ_INSTS_VALU") and "SQ_THREAD_CYCLES_VALU" in m:
+                print(f"{'= active lanes per VALU instr.':32s} {m['SQ_THREAD_CYCLES_VALU'] / m['SQ_INSTS_VALU']:18.1f}")
+            if clk and "SQ_WAVE_CYCLES" in m:
+                print(f"{'= resident waves per CU':32s} {4 * m['SQ_WAVE_CYCLES'] / (CUS * clk):18.2f}")
+            if clk:
+                print(f"{'= duration at 2.4 GHz (ms)':32s} {clk / 2.4e6:18.4f}")
         return
 
     if args.mode == "kernels":
@@ -164,7 +185,7 @@ def main() -> None:
             with open(os.path.join(HERE, "csrc", name), "rb") as f:
                 digests[name] = hashlib.sha256(f.read()).hexdigest()
         rec = {"estimates": args.estimates, "read_bytes_per_estimate": round(rd), "write_bytes_per_estimate": round(wr),
-               "bytes_per_estimate": round(rd + wr), "fetch_scale_bytes_per_unit": fs,
+               "bytes_per_estimate": round(rd) + round(wr), "fetch_scale_bytes_per_unit": fs,
                "write_scale_bytes_per_unit": ws, "sources_sha256": digests, "command": args.command}
         print(json.dumps(rec, indent=1))
         return
@@ -198,7 +219,7 @@ def main() -> None:
             digests[os.path.basename(src)] = hashlib.sha256(f.read()).hexdigest()
     rd, wr = statistics.mean(fetch) * fs, statistics.mean(write) * ws
     rec = {"kernel": args.kernel, "launches": len(fetch), "read_bytes_per_launch": round(rd),
-           "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd + wr),
+           "write_bytes_per_launch": round(wr), "bytes_per_launch": round(rd) + round(wr),
            "fetch_scale_bytes_per_unit": fs, "write_scale_bytes_per_unit": ws,
            "sources_sha256": digests, "command": args.command}
     print(json.dumps(rec, indent=1))

@@ -985,6 +985,40 @@ def test_full_size_512_all_series_against_stored_oracle(lpp):
           + ", ".join(f"{k} {v:.1e}" for k, v in own.items()))
 
 
+def test_batch_256_mock_against_stored_oracle(lpp):
+    """One mock of the 256^3 batch workload's settings (TSC + interlacing,
+    l <= 4, 50 shells), a 30,000 + 300,000 subsample, through the batch path
+    (lpp_estimate_batch: one captured graph, then a replay) next to two other
+    mocks, against the FP64 oracle stored in tests/golden/c3_subsample_256.json
+    by tests/golden/make_c3_subsample.py: every series at 1e-4 (scale and own
+    value), counts bit-exact, on the capture and on the replay."""
+    import json
+    import os
+    import sys
+    import torch
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_subsample_256.json")))
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_c3_subsample as MK
+    g, r = MK.catalogs()
+    cs = MK.checksums(g, r)
+    for k, v in gold["checksums"].items():
+        assert abs(cs[k] - v) <= 1e-12 * max(1.0, abs(v)), ("the catalog generator changed", k, cs[k], v)
+    ref = dict(gold)
+    for k in ("n_modes", "k_eff", "k_lo", "re", "im"):
+        ref[k] = np.asarray(gold[k])
+    wl = MK.WORKLOADS["c3"]
+    others = [MK.make_catalogs(wl, mock=m, n_gal=20000 + 5000 * m, n_ran=200000) for m in (6, 7)]
+    gals = [_device_catalog(g, torch)] + [_device_catalog(o[0], torch) for o in others]
+    rans = [_device_catalog(r, torch)] + [_device_catalog(o[1], torch) for o in others]
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision="f32", lmax=4, n_kbins=wl["n_kbins"])
+    for _ in range(2):
+        outs = plan.estimate_batch(gals, rans)
+        assert all(not isinstance(o, Exception) for o in outs), outs
+        _compare(outs[0], ref, 1e-4)
+    assert plan.batch_stats() == (1, 2)
+
+
 def _device_catalog(c, torch, dtype=None):
     return Catalog(*[None if v is None else torch.tensor(v, device="cuda", dtype=dtype)
                      for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
