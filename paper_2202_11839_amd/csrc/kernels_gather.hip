@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
 //      field per wavefront (the lanes do not diverge);
 //   3. every node sums, in a fixed order, the objects of the 4 x 4 x 4 cells
 //      that reach it (cells n-2 .. n+1 per axis): 16 runs of 4 consecutive
-//      cells in the staged order;
+//      cells in the staged order, walked as one sequence per lane;
 //   4. one store per field (real fields: grid and interlaced grid packed)
 //      or per field and grid copy (complex fields); a wavefront writes 64
 //      consecutive nodes (one y row of a z-group in the z-blocked order).
@@ -550,6 +550,8 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
     run += cnt[u];
   }
   if (tid == 0) coff[kNodeCells] = total;
+  // the same in every lane: keep it (and the chunk bounds below) in scalar registers
+  total = __builtin_amdgcn_readfirstlane(total);
   __syncthreads();
 
   // this thread's node and its place in the stores
@@ -625,13 +627,41 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
       }
     }
     __syncthreads();
-    // 3. this node's sums: cells x in kx..kx+3, y in ky..ky+3, z in kz..kz+3 of the region
+    // 3. this node's sums: cells x in kx..kx+3, y in ky..ky+3, z in kz..kz+3 of
+    //    the region, as 16 runs r = 4 dz + dy of four cells along x.  The
+    //    non-empty runs (a 16-bit mask per lane) are walked as one sequence
+    //    per lane, so that a wavefront spends as many steps as its busiest
+    //    node has objects, not the sum over the runs of the busiest node's
+    //    objects in each run (most runs are empty or hold one object).  The
+    //    order of the terms is the same as run by run.
     const T nxc = static_cast<T>(kx + 2), nyc = static_cast<T>(ky + 2), nzc = static_cast<T>(kz + 2);
-    for (int dz = 0; dz < 4; ++dz)
-      for (int dy = 0; dy < 4; ++dy) {
-        const int cell0 = kx + R * ((ky + dy) + R * (kz + dz));
+    {
+      const int cbase = kx + R * (ky + R * kz);
+      uint32_t runs = 0, left = 0;
+      // (not unrolled: the run's offset stays a scalar, and sixteen cell
+      // indices are not kept live across the chunks)
+#pragma unroll 1
+      for (int r = 0; r < 16; ++r) {
+        const int cell0 = cbase + R * ((r & 3) + R * (r >> 2));
         const uint32_t lo = max(coff[cell0], c0), hi = min(coff[cell0 + 4], c1);
-        for (uint32_t k = lo; k < hi; ++k) {
+        if (lo < hi) {
+          runs |= 1u << r;
+          left += hi - lo;
+        }
+      }
+      // one step per object of this node; the loop's only exit is its count
+      // (an exit from inside the divergent branch made the compiler copy the
+      // accumulators on every step)
+      uint32_t k = 0, hi = 0;
+      for (; left > 0; --left) {
+        if (k >= hi) {
+          const int r = __builtin_ctz(runs);
+          runs &= runs - 1;
+          const int cell0 = cbase + R * ((r & 3) + R * (r >> 2));
+          k = max(coff[cell0], c0);
+          hi = min(coff[cell0 + 4], c1);
+        }
+        {
           const int d = static_cast<int>(k - c0);
           const T ux = su[0][d], uy = su[1][d], uz = su[2][d];
           const T w0 = window<T, P>(ux - nxc) * window<T, P>(uy - nyc) * window<T, P>(uz - nzc);
@@ -647,7 +677,9 @@ __global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, c
               acc[(2 * q + 1) * K + c] += v * w1;
             }
         }
+        ++k;
       }
+    }
     __syncthreads();
   }
   // 4. stores
