@@ -583,6 +583,10 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   ba.invw = p->d_invw;
   ba.partial = partial;
   ba.nblocks = p->tune.bin_blocks > 0 ? p->tune.bin_blocks : bin_blocks(N);
+  ba.qmax = static_cast<int>(p->tab.thr[nb]);
+  // the density kernels walk column pairs: fewer workgroups
+  BinArgs bd = ba;
+  bd.nblocks = pair_bin_blocks(N, ba.nblocks);
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
   // The base kernels write rows [re, im, cnt, ksum] of width 4nb; they are
   // reduced into their own rows after the series rows.
@@ -655,10 +659,10 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
           void* g2 = (cplx && il) ? W[m0 + 1] : nullptr;
           LPP_TRY(prof_begin(p));
           if (cplx) LPP_TRY(launch_base_gg<T>(ba, g1, g2, Bg, st));
-          else LPP_TRY(launch_base_dd<T>(ba, g1, Bd, st));
+          else LPP_TRY(launch_base_dd<T>(bd, g1, Bd, st));
           LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
           LPP_TRY(prof_begin(p));
-          LPP_TRY(launch_reduce_partials(partial, ba.nblocks, 4 * nb, base_rows[cplx], st));
+          LPP_TRY(launch_reduce_partials(partial, cplx ? ba.nblocks : bd.nblocks, 4 * nb, base_rows[cplx], st));
           LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
           ++q;
           continue;
@@ -685,12 +689,13 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
           ++q;
         }
         LPP_TRY(prof_begin(p));
-        if (!cplx) LPP_TRY(launch_bin_dd<T>(ba, fs, g1, n, base, st));
+        if (!cplx) LPP_TRY(launch_bin_dd<T>(bd, fs, g1, n, base, st));
         else LPP_TRY(launch_bin_gg<T>(ba, fs, g1, il ? g2 : nullptr, n, base, kind, st));
         LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
         LPP_TRY(prof_begin(p));
+        const int nblk = cplx ? ba.nblocks : bd.nblocks;
         for (int i = 0; i < n; ++i)
-          LPP_TRY(launch_reduce_partials(partial + static_cast<size_t>(2) * i * nb * ba.nblocks, ba.nblocks, 2 * nb,
+          LPP_TRY(launch_reduce_partials(partial + static_cast<size_t>(2) * i * nb * nblk, nblk, 2 * nb,
                                          acc + static_cast<size_t>(2) * nb * series[i], st));
         LPP_TRY(prof_end(p, LPP_STAGE_OTHER, n));
       }

@@ -19,8 +19,17 @@
 // Density fields are real: their two interlaced copies are packed as the real
 // and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
 // with F1(k) = [P(k) + P*(-k)]/2, F2(k) = [P(k) - P*(-k)]/(2i).  Those kernels
-// walk half of k-space (z-index < N/2 with the usual tie-breaks on the
-// z = 0 and y = 0 planes) and count each mode pair (k, -k) twice.
+// walk column pairs: a column A = (x, y) of the half plane 0 <= y < N/2 (on
+// y = 0, x < N/2) together with its mirror column M = (-x, -y), whose z-groups
+// are read whole.  Group g of A holds z = 8g .. 8g+7, whose mirrors N - z are
+// elements 7 .. 1 of group N/8 - 1 - g of M, plus element 0 of the group read
+// one step earlier (carried in registers), so every HBM access is an aligned
+// 64-byte run read once.  The z-groups of A are walked in the order
+// c = (g + N/16) mod N/8, which puts nz = 0 in the middle and the groups
+// inside the last shell on one range of c; a thread takes one chunk of that
+// range (the chunk's first carried element is one extra 8-byte load).  Each
+// mode pair (k, -k) is counted twice from its mode in A (once from both
+// modes in the self-mirrored column (0, 0)).
 #include "device_common.h"
 
 namespace lpp {
@@ -103,6 +112,62 @@ __device__ __forceinline__ bool run_live(int z0, int N, int qxy, int qmax) {
   return mz * mz + qxy < qmax;
 }
 
+// Column pairs (density kernels).  A unit is one chunk of kPairChunk (or
+// fewer) consecutive c of one column A: unit u = column + (N * N/2) * chunk,
+// the column x + N y, so that the lanes of a wavefront take consecutive x of
+// the same z-groups (contiguous 64-byte runs in A, and in reverse order in M).
+__host__ __device__ inline int pair_chunk(int N) { return N / kRun < (N >= 512 ? 16 : 4) ? N / kRun : (N >= 512 ? 16 : 4); }
+__host__ __device__ inline int64_t pair_units(int N) {
+  return static_cast<int64_t>(N) * (N / 2) * (N / kRun / pair_chunk(N));
+}
+
+struct PairUnit {
+  int ix, iy, mx, my, nx, ny, qxy;
+  int c0, c1;  // this unit's c range (inclusive), inside the live range of the column
+  int clo;     // the column's first live c
+  bool self;   // A is its own mirror (the column (0, 0))
+};
+
+// largest s with s * s <= v (v >= 0)
+__device__ __forceinline__ int isqrt_floor(int v) {
+  int s = static_cast<int>(sqrtf(static_cast<float>(v)));
+  while (s * s > v) --s;
+  while ((s + 1) * (s + 1) <= v) ++s;
+  return s;
+}
+
+// the unit's column pair and chunk; false if nothing of it lies inside the
+// last shell (qmax <= (N/2)^2, so the live range of c stays in [0, N/8))
+__device__ __forceinline__ bool pair_unit(int64_t u, int N, int qmax, int C, PairUnit& p) {
+  const int64_t half = static_cast<int64_t>(N) * (N / 2);
+  const int k = static_cast<int>(u / half);
+  const int r = static_cast<int>(u - k * half);
+  p.ix = r % N;
+  p.iy = r / N;  // < N/2
+  if (p.iy == 0 && p.ix >= N / 2) return false;  // mirrors of (x, 0), 0 < x < N/2; (N/2, 0) is never inside
+  p.nx = sgn_mode(p.ix, N);
+  p.ny = p.iy;
+  p.qxy = p.nx * p.nx + p.ny * p.ny;
+  if (p.qxy >= qmax) return false;
+  const int zl = isqrt_floor(qmax - 1 - p.qxy);  // largest |nz| inside
+  const int H = N / (2 * kRun);
+  p.clo = H - (zl + kRun - 1) / kRun;
+  const int chi = H + zl / kRun;
+  p.c0 = max(k * C, p.clo);
+  p.c1 = min(k * C + C - 1, chi);
+  if (p.c0 > p.c1) return false;
+  p.mx = (N - p.ix) & (N - 1);
+  p.my = (N - p.iy) & (N - 1);
+  p.self = p.ix == 0 && p.iy == 0;
+  return true;
+}
+
+// z-group of A at position c of the walk, and the start of a z-group's run
+__device__ __forceinline__ int pair_group(int c, int N) { return (c + N / (2 * kRun)) % (N / kRun); }
+__device__ __forceinline__ int64_t group_run(int x, int y, int g, int N) {
+  return ((static_cast<int64_t>(g) * N + y) * N + x) * kRun;
+}
+
 // Shell sums go to one LDS row set per wavefront (its flushes come in program
 // order, and one instruction's lanes in a fixed order), and the rows of the
 // four wavefronts are added in a fixed order when the block stores its
@@ -163,8 +228,10 @@ __device__ __forceinline__ void rows_store(const unsigned char* dyn, size_t off,
 // ---- the bases: B = F at every mode inside the last shell, with |F|^2, the
 // mode count and the sum of |n| per shell (rows [re, im, counts, sum |n|]) ----
 
-// density base from the packed pair of real copies, half k-space, B also
-// written at -k as conj(F)
+// density base from the packed pair of real copies over column pairs: B is
+// written at every mode of A and, as conj(F), at the mirrors in M (whole
+// runs: group N/8 - 1 - g of M once the next step has its element 0; the
+// unit's last one with an extra element of A)
 template <typename T>
 __global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const typename V2<T>::type* __restrict__ P,
                                                               typename V2<T>::type* __restrict__ B) {
@@ -181,42 +248,71 @@ __global__ void __launch_bounds__(kBinThreads) base_dd_kernel(BinArgs a, const t
   const T* invw = static_cast<const T*>(a.invw);
   const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
-  const int mask = N - 1;
-  const int64_t NN = static_cast<int64_t>(N) * N;
-  const int64_t nruns = NN * (N / 2 / kRun);  // runs (x, y, z-group) with z < N/2
+  const int G8 = N / kRun, C = pair_chunk(N);
+  const int64_t units = pair_units(N);
   Acc acc{-1, 0, 0, 0, 0};
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
-       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int ix = static_cast<int>(r % N);
-    const int iy = static_cast<int>((r / N) % N);
-    const int z0 = static_cast<int>(r / NN) * kRun;
-    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
-    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
-    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
-    const int mx = (N - ix) & mask, my = (N - iy) & mask;
-    const T wxy = invw[ix] * invw[iy];
-    const T2 pxy = phase[nx + ny + 3 * N / 2];
-    T2 pv[kRun];
+  for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < units;
+       u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    PairUnit pu;
+    if (!pair_unit(u, N, qmax, C, pu)) continue;
+    const T wxy = invw[pu.ix] * invw[pu.iy];
+    const T2 pxy = phase[pu.nx + pu.ny + 3 * N / 2];
+    const double wt = pu.self ? 1.0 : 2.0;
+    // F at z-index iz of A from P there and at its mirror
+    auto unpack = [&](T2 pa, T2 pm, int iz) -> T2 {
+      const T2 f1{static_cast<T>(0.5) * (pa.x + pm.x), static_cast<T>(0.5) * (pa.y - pm.y)};
+      const T2 f2{static_cast<T>(0.5) * (pa.y + pm.y), static_cast<T>(-0.5) * (pa.x - pm.x)};
+      return combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[sgn_mode(iz, N) + N / 2]), wxy * iw[iz]);
+    };
+    int g = pair_group(pu.c0, N);
+    // element 0 of the mirror group of the step before the first: the mirror of A's z = 8g
+    T2 carry = P[group_run(pu.mx, pu.my, (G8 - g) % G8, N)];
+    T2 bm[kRun];  // B of the previous step's mirror group (element 0 pending)
+    for (int c = pu.c0; c <= pu.c1; ++c, g = pair_group(c, N)) {
+      const int gm = G8 - 1 - g;
+      const int64_t run = group_run(pu.ix, pu.iy, g, N), mrun = group_run(pu.mx, pu.my, gm, N);
+      T2 pa[kRun], pm[kRun], fa[kRun];
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) pv[j] = P[run + j];
+      for (int j = 0; j < kRun; ++j) pa[j] = P[run + j];
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-      const int iz = z0 + j, nz = iz;  // iz < N/2
-      if (iz == 0 && !(iy < N / 2)) continue;                            // z=0 plane: y in [0, N/2)
-      if (iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2)) continue;  // y=0 line: x in (0, N/2)
-      const int q = nx * nx + ny * ny + nz * nz;
-      const int b = shell_of(q, sthr, nb, inv_dn);
-      if (b < 0) continue;
-      const int64_t midx = zb_index(mx, my, (N - iz) & mask, N);
-      const T2 pm = P[midx];
-      // unpack the two real copies
-      const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
-      const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
-      const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
-      B[run + j] = F;
-      B[midx] = T2{F.x, -F.y};
-      acc_add<true>(acc, b, 2.0 * (static_cast<double>(F.x) * F.x + static_cast<double>(F.y) * F.y), 0.0, 2.0,
-                    2.0 * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+      for (int j = 0; j < kRun; ++j) pm[j] = P[mrun + j];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) fa[j] = unpack(pa[j], j ? pm[kRun - j] : carry, kRun * g + j);
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) B[run + j] = fa[j];
+      if (!pu.self) {
+        const int64_t prev = group_run(pu.mx, pu.my, (gm + 1) % G8, N);
+        if (c > pu.c0) {
+          bm[0] = T2{fa[0].x, -fa[0].y};
+#pragma unroll
+          for (int j = 0; j < kRun; ++j) B[prev + j] = bm[j];
+        } else if (c == pu.clo) {
+          // the column's first live group: its element 0's mirror has no earlier step
+          const int nz = sgn_mode(kRun * g, N);
+          if (pu.qxy + nz * nz < qmax) B[prev] = T2{fa[0].x, -fa[0].y};
+        }
+#pragma unroll
+        for (int j = 1; j < kRun; ++j) bm[j] = T2{fa[kRun - j].x, -fa[kRun - j].y};
+      }
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) {
+        const int nz = sgn_mode(kRun * g + j, N);
+        const int q = pu.qxy + nz * nz;
+        const int b = shell_of(q, sthr, nb, inv_dn);
+        if (b < 0) continue;
+        acc_add<true>(acc, b, wt * (static_cast<double>(fa[j].x) * fa[j].x + static_cast<double>(fa[j].y) * fa[j].y),
+                      0.0, wt, wt * sqrt(static_cast<double>(q)), sre, sim, scnt, sks);
+      }
+      carry = pm[0];
+    }
+    if (!pu.self) {
+      // the last mirror group's element 0 is the mirror of element 0 of A's next group
+      const int gn = (pair_group(pu.c1, N) + 1) % G8;
+      const T2 f = unpack(P[group_run(pu.ix, pu.iy, gn, N)], carry, kRun * gn);
+      bm[0] = T2{f.x, -f.y};
+      const int64_t last = group_run(pu.mx, pu.my, G8 - 1 - pair_group(pu.c1, N), N);
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) B[last + j] = bm[j];
     }
   }
   acc_flush<true>(acc, sre, sim, scnt, sks);
@@ -310,9 +406,8 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
   const T* invw = static_cast<const T*>(a.invw);
   const int qmax = sthr[nb];
   const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
-  const int mask = N - 1;
-  const int64_t NN = static_cast<int64_t>(N) * N;
-  const int64_t nruns = NN * (N / 2 / kRun);  // runs (x, y, z-group) with z < N/2
+  const int G8 = N / kRun, C = pair_chunk(N);
+  const int64_t units = pair_units(N);
   int cur[NFB];
   double sr[NFB];
 #pragma unroll
@@ -320,52 +415,60 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
     cur[f] = -1;
     sr[f] = 0.0;
   }
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < nruns;
-       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int ix = static_cast<int>(r % N);
-    const int iy = static_cast<int>((r / N) % N);
-    const int z0 = static_cast<int>(r / NN) * kRun;
-    const int nx = sgn_mode(ix, N), ny = sgn_mode(iy, N);
-    if (!run_live(z0, N, nx * nx + ny * ny, qmax)) continue;
-    const int64_t run = r * kRun;  // = zb_index(ix, iy, z0, N)
-    const int mx = (N - ix) & mask, my = (N - iy) & mask;
-    const T wxy = invw[ix] * invw[iy];
-    const T2 pxy = phase[nx + ny + 3 * N / 2];
-    T2 bv[kRun];
+  for (int64_t u = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; u < units;
+       u += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    PairUnit pu;
+    if (!pair_unit(u, N, qmax, C, pu)) continue;
+    const T wxy = invw[pu.ix] * invw[pu.iy];
+    const T2 pxy = phase[pu.nx + pu.ny + 3 * N / 2];
+    const double wt = pu.self ? 1.0 : 2.0;
+    int gA = pair_group(pu.c0, N);
+    T2 carry[NFB];  // element 0 of the previous step's mirror group, per field
+    {
+      const int64_t prev = group_run(pu.mx, pu.my, (G8 - gA) % G8, N);
 #pragma unroll
-    for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
-    int bq[kRun];
-#pragma unroll
-    for (int j = 0; j < kRun; ++j) {
-      const int iz = z0 + j;  // iz < N/2
-      const bool keep = !(iz == 0 && !(iy < N / 2)) && !(iz == 0 && iy == 0 && !(ix > 0 && ix < N / 2));
-      bq[j] = keep ? shell_of(nx * nx + ny * ny + iz * iz, sthr, nb, inv_dn) : -1;
+      for (int f = 0; f < NFB; ++f) carry[f] = g.P[f][prev];
     }
+    for (int c = pu.c0; c <= pu.c1; ++c, gA = pair_group(c, N)) {
+      const int64_t run = group_run(pu.ix, pu.iy, gA, N), mrun = group_run(pu.mx, pu.my, G8 - 1 - gA, N);
+      T2 bv[kRun];
 #pragma unroll
-    for (int f = 0; f < NFB; ++f) {
-      const T2* __restrict__ P = g.P[f];
-      T2 pv[kRun];
-#pragma unroll
-      for (int j = 0; j < kRun; ++j) pv[j] = P[run + j];
+      for (int j = 0; j < kRun; ++j) bv[j] = B[run + j];
+      int bq[kRun];
 #pragma unroll
       for (int j = 0; j < kRun; ++j) {
-        const int b = bq[j];
-        if (b < 0) continue;
-        const int iz = z0 + j, nz = iz;
-        const T2 pm = P[zb_index(mx, my, (N - iz) & mask, N)];
-        const T2 f1{static_cast<T>(0.5) * (pv[j].x + pm.x), static_cast<T>(0.5) * (pv[j].y - pm.y)};
-        const T2 f2{static_cast<T>(0.5) * (pv[j].y + pm.y), static_cast<T>(-0.5) * (pv[j].x - pm.x)};
-        const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
-        const int q = nx * nx + ny * ny + nz * nz;
-        const T rq = inv_sqrt<T>(q);
-        const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
-        if (b != cur[f]) {
-          if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
-          cur[f] = b;
-          sr[f] = 0.0;
+        const int nz = sgn_mode(kRun * gA + j, N);
+        bq[j] = shell_of(pu.qxy + nz * nz, sthr, nb, inv_dn);
+      }
+#pragma unroll
+      for (int f = 0; f < NFB; ++f) {
+        const T2* __restrict__ P = g.P[f];
+        T2 pa[kRun], pm[kRun];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) pa[j] = P[run + j];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) pm[j] = P[mrun + j];
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+          const int b = bq[j];
+          if (b < 0) continue;
+          const int iz = kRun * gA + j, nz = sgn_mode(iz, N);
+          const T2 m = j ? pm[kRun - j] : carry[f];
+          const T2 f1{static_cast<T>(0.5) * (pa[j].x + m.x), static_cast<T>(0.5) * (pa[j].y - m.y)};
+          const T2 f2{static_cast<T>(0.5) * (pa[j].y + m.y), static_cast<T>(-0.5) * (pa[j].x - m.x)};
+          const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
+          const int q = pu.qxy + nz * nz;
+          const T rq = inv_sqrt<T>(q);
+          const T hk = harmonic(g.h[f], pu.nx * rq, pu.ny * rq, nz * rq);
+          if (b != cur[f]) {
+            if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
+            cur[f] = b;
+            sr[f] = 0.0;
+          }
+          // Re[h F conj(B)] for both modes of the pair (once each in the self-mirrored column)
+          sr[f] += wt * static_cast<double>(hk * (F.x * bv[j].x + F.y * bv[j].y));
         }
-        // 2 Re[h F conj(B)]
-        sr[f] += 2.0 * static_cast<double>(hk * (F.x * bv[j].x + F.y * bv[j].y));
+        carry[f] = pm[0];
       }
     }
   }
@@ -488,6 +591,11 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const doub
 
 }  // namespace
 
+int pair_bin_blocks(int N, int nblocks) {
+  const int64_t want = (pair_units(N) + kBinThreads - 1) / kBinThreads;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, nblocks)));
+}
+
 int bin_blocks(int N) {
   const int64_t runs = static_cast<int64_t>(N) * N * N / kRun;
   int64_t want = (runs + kBinThreads - 1) / kBinThreads;
@@ -499,7 +607,7 @@ int bin_blocks(int N) {
 template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st) {
   using T2 = typename V2<T>::type;
-  if (a.nb > kMaxBins) return hipErrorInvalidValue;
+  if (a.nb > kMaxBins || a.qmax > a.N * a.N / 4) return hipErrorInvalidValue;
   base_dd_kernel<T><<<a.nblocks, kBinThreads, bin_lds_bytes<T>(a.N, 4 * a.nb), st>>>(a, static_cast<const T2*>(packed),
                                                                           static_cast<T2*>(base));
   return hipGetLastError();
@@ -531,7 +639,7 @@ hipError_t bin_dd_group_n(const BinArgs& a, const FieldSpec* const* f, const voi
 template <typename T>
 hipError_t launch_bin_dd(const BinArgs& a, const FieldSpec* const* f, const void* const* packed, int n,
                          const void* base, hipStream_t st) {
-  if (a.nb > kMaxBins || 2 * n * a.nb > 4 * kMaxBins) return hipErrorInvalidValue;
+  if (a.nb > kMaxBins || 2 * n * a.nb > 4 * kMaxBins || a.qmax > a.N * a.N / 4) return hipErrorInvalidValue;
   switch (n) {
     case 1: return bin_dd_group_n<T, 1>(a, f, packed, base, st);
     case 2: return bin_dd_group_n<T, 2>(a, f, packed, base, st);

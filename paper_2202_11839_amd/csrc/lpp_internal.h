@@ -273,12 +273,18 @@ struct BinArgs {
   const void* invw;
   double* partial;         // column-major [width][nblocks]
   int nblocks;
+  int qmax;                // thr[nb] (host copy): the density kernels need qmax <= (N/2)^2
 };
 // The binning kernels read the transformed (z-blocked) fields only at modes
 // inside the last shell, |n|^2 < T_nb, and the base kernels write the base
 // only there.
 int bin_blocks(int N);            // default workgroups of the shell-sum kernels
+// workgroups of the density kernels (column pairs) for a budget of nblocks:
+// at most one per 256 column-pair chunks
+int pair_bin_blocks(int N, int nblocks);
 constexpr int kMaxBinBlocks = 8192;
+// the density kernels (launch_base_dd, launch_bin_dd) run a.nblocks
+// workgroups: pass pair_bin_blocks(N, budget) there and to the reduction
 template <typename T>
 hipError_t launch_base_dd(const BinArgs& a, const void* packed, void* base, hipStream_t st);
 template <typename T>
