@@ -279,6 +279,31 @@ def test_distant_observer_matches_global_plane_parallel(lpp, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_objects_on_the_pole_axis_match_oracle(lpp, prec):
+    """The pole edge case of the line-of-sight basis: a fifth of the galaxies
+    lie on the z-axis through the observer (sin theta = 0 exactly, half of
+    them above it, theta = 0, half below, theta = pi), where phi is taken as
+    0, so their shapes are read in the basis (e_theta, e_phi) = (+-x, y)
+    (App. E, eq. def_standard_rotation).  The axis is a cell boundary of the
+    mesh (x = y = 0 with the origin at -50 and H = 6.25), so that the
+    device's position, rebuilt from the cell and the offset in it, is exactly
+    on the axis too; every series against the oracle."""
+    box, n = 100.0, 16
+    origin = (-50.0, -50.0, -50.0)
+    obs = (0.0, 0.0, 0.0)
+    g, r = _cats(29, 600, 2000, origin, box)
+    rng = np.random.default_rng(290)
+    on = rng.choice(g.n, size=g.n // 5, replace=False)
+    g.x[on] = 0.0
+    g.y[on] = 0.0
+    g.z[on] = rng.uniform(5.0, 45.0, on.size) * np.where(np.arange(on.size) % 2 == 0, 1.0, -1.0)
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=obs, assignment=3, interlacing=1, n_kbins=6, lmax=4)
+    ref = E.mesh64(g, r, cfg)
+    plan = lpp.Plan(n, box, origin, obs, assignment=3, interlacing=1, precision=prec, lmax=4, n_kbins=6)
+    _compare(plan.estimate(g, r), ref, 1e-9 if prec == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_global_line_of_sight_matches_oracle_gpp(lpp, prec):
     """The plan's global-line-of-sight mode against the oracle's
     global-plane-parallel estimator (Sec. II.C), with the observer inside the
