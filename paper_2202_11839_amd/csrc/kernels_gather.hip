@@ -6,7 +6,8 @@
 // objects in the cells [t0-2, t0+TX] (x) and [t0-2, t0+TT] (y, z) (the TSC stencil
 // of the grid reaches nodes c-1..c+2 of an object in cell c, the interlaced
 // grid nodes c-1..c+1).  The workgroup stages those objects in LDS (in
-// chunks of CAP objects), computing each object's line-of-sight weighted
+// chunks of at most CAP objects, to which every region row gives an equal
+// share of its objects), computing each object's line-of-sight weighted
 // value once, and every thread then sums the contributions to one x-row of TX
 // nodes in registers, in a fixed order.  Every node of the mesh is written
 // exactly once with a plain store: no atomics, no separate clearing pass, and
@@ -221,7 +222,10 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
   // contiguous ranges of the cell-sorted objects (two when the row wraps)
   __shared__ uint32_t seg_beg[R2][2];
   __shared__ uint32_t seg_cnt[R2];   // objects in the first range
-  __shared__ uint32_t roff[R2 + 1];  // offsets of the rows in staging order
+  __shared__ uint32_t roff[R2 + 1];  // offsets of the rows in the sorted order of the region
+  __shared__ uint32_t soff[R2 + 1];  // first slot of each row in a chunk's staging order
+  __shared__ uint32_t sq[R2];        // each row's share of a chunk, ceil(n_r / chunks)
+  __shared__ uint32_t nchunks;
   __shared__ __align__(16) T su[ROWS][CAP];  // [0..2] region-local positions, then the values
   static_assert(R2 <= 2 * 64, "row scan uses two values per lane of one wavefront");
   const int copies = (K == 2 && interlace) ? 2 : 1;
@@ -281,6 +285,27 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
     if (tid * 2 < R2) roff[tid * 2] = exc;
     if (tid * 2 + 1 < R2) roff[tid * 2 + 1] = exc + cnt[0];
     if (tid == 63) roff[R2] = inc;
+    // chunks: the fewest whose per-row shares, ceil(n_r / chunks), fit in CAP;
+    // row r takes the slots [soff[r], soff[r] + share) of every chunk
+    const uint32_t all = __shfl(inc, 63, 64);
+    uint32_t n = all <= static_cast<uint32_t>(CAP) ? 1u : (all + CAP - 1) / CAP;
+    if (n > 1) {
+      while (__shfl(wave_inclusive_scan((cnt[0] + n - 1) / n + (cnt[1] + n - 1) / n), 63, 64) >
+             static_cast<uint32_t>(CAP))
+        ++n;
+    }
+    if (tid == 0) nchunks = n;
+    const uint32_t q0 = (cnt[0] + n - 1) / n, q1 = (cnt[1] + n - 1) / n;
+    const uint32_t qinc = wave_inclusive_scan(q0 + q1);
+    if (tid * 2 < R2) {
+      soff[tid * 2] = qinc - q0 - q1;
+      sq[tid * 2] = q0;
+    }
+    if (tid * 2 + 1 < R2) {
+      soff[tid * 2 + 1] = qinc - q1;
+      sq[tid * 2 + 1] = q1;
+    }
+    if (tid == 63) soff[R2] = qinc;
   }
   __syncthreads();
   const uint32_t total = roff[R2];
@@ -305,17 +330,33 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0;
 
-  for (uint32_t c0 = 0; c0 < total; c0 += CAP) {
-    const uint32_t c1 = min(total, c0 + static_cast<uint32_t>(CAP));
-    // stage the chunk [c0, c1): each thread takes objects k, finds its row by bisection
-    for (uint32_t k = c0 + tid; k < c1; k += kThreads) {
-      int lo = 0, hi = R2;  // roff[lo] <= k < roff[hi]
+  // More objects than fit in LDS are staged in chunks, and every region row
+  // gives each chunk an equal share of its objects (its next ceil(n_r / nch)
+  // in sorted order, in slots of its own; a row's last share may leave slots
+  // empty, which are staged as objects of zero weight), so that every thread
+  // has objects in every chunk: cut into ranges of the sorted order instead,
+  // a chunk would hold a few z layers of the region and leave the threads of
+  // the other rows idle.  (One chunk when everything fits: the staged order
+  // is then the sorted order.)
+  // (block-uniform counts kept in scalar registers: read from LDS they would
+  // otherwise take vector registers from the accumulators)
+  const uint32_t nch = __builtin_amdgcn_readfirstlane(nchunks);
+  for (uint32_t ch = 0; ch < nch; ++ch) {
+    const uint32_t nc = __builtin_amdgcn_readfirstlane(soff[R2]);
+    // stage the chunk: each thread takes slots d, finds the row by bisection
+    for (uint32_t d = tid; d < nc; d += kThreads) {
+      int lo = 0, hi = R2;  // soff[lo] <= d < soff[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (roff[mid] <= k) lo = mid; else hi = mid;
+        if (soff[mid] <= d) lo = mid; else hi = mid;
       }
       const int r = lo;
-      const uint32_t j = k - roff[r];
+      const uint32_t j = ch * sq[r] + (d - soff[r]);  // the row's j-th object
+      if (j >= roff[r + 1] - roff[r]) {  // an empty slot of the row's last share
+#pragma unroll
+        for (int q = 0; q < ROWS; ++q) su[q][d] = static_cast<T>(0);
+        continue;
+      }
       const uint32_t src = j < seg_cnt[r] ? seg_beg[r][0] + j : seg_beg[r][1] + (j - seg_cnt[r]);
       const ObjPos<T> rec = o.pos[src];
       const uint32_t key = rec.key;
@@ -324,7 +365,6 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
       const int cz = static_cast<int>(key >> (2 * lgN));
       const int lx = (cx - t0x + 2) & mask, ly = r % R, lz = r / R;
       const T fx = rec.fx, fy = rec.fy, fz = rec.fz;
-      const uint32_t d = k - c0;
       su[0][d] = static_cast<T>(lx) + fx;
       su[1][d] = static_cast<T>(ly) + fy;
       su[2][d] = static_cast<T>(lz) + fz;
@@ -355,10 +395,9 @@ __global__ void __launch_bounds__(kThreads) gather_kernel(GObjSet<T> o, const ui
     {
       const T nyc = static_cast<T>(ny + 2), nzc = static_cast<T>(nz + 2);
       const int row = ny + (nz + part) * R;  // rows y = ny..ny+3 at z = nz + part are contiguous
-      const uint32_t lo = max(roff[row], c0), hi = min(roff[row + 4], c1);
+      const uint32_t lo = soff[row], hi = soff[row + 4];
       const T half = static_cast<T>(0.5);
-      for (uint32_t k = lo; k < hi; ++k) {
-        const uint32_t d = k - c0;
+      for (uint32_t d = lo; d < hi; ++d) {
         const T ux = su[0][d], uy = su[1][d], uz = su[2][d];
         const T w0 = window<T, P>(uy - nyc) * window<T, P>(uz - nzc);
         const T w1 = interlace ? window<T, P>(uy - nyc - half) * window<T, P>(uz - nzc - half) : static_cast<T>(0);
