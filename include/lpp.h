@@ -363,8 +363,10 @@ typedef struct {
                               lpp_set_profiling always runs them one after the other)      */
   int32_t fft_streaming;   /* 8 + a bit mask of the passes of the 3D transform (1 x, 2 y, 4 z)
                               that use non-temporal loads and stores; 0 = the default
-                              (x and z; y too when its workgroups read runs of 128 bytes
-                              or more: FP32 with 16 y lines, or FP64)                     */
+                              (meshes of at most 256 MiB, which stay in the Infinity Cache
+                              between passes: z only; larger: x and z, y too when its
+                              workgroups read runs of 128 bytes or more: FP32 with 16 y
+                              lines, or FP64)                                             */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

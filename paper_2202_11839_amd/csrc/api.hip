@@ -1252,6 +1252,8 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   s = search(&lpp_tuning::fft_rows_x, {8, 16}, {LPP_STAGE_FFT_X});
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_y, {8, 16}, {LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::fft_cols_z, {8, 16}, {LPP_STAGE_FFT_YZ});
+  if (s == LPP_OK)  // non-temporal accesses: all passes, none, or the z pass only (x, y cached)
+    s = search(&lpp_tuning::fft_streaming, {8 | 7, 8, 8 | 4, 8 | 5}, {LPP_STAGE_FFT_X, LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK)

@@ -142,6 +142,9 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     assert p64.tuning()["fft_streaming"] == 15
     p1k = pkg.Plan(1024, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert p1k.tuning()["fft_streaming"] == 13
+    # a mesh of at most 256 MiB stays in the Infinity Cache between passes: only the z pass streams
+    p256 = pkg.Plan(256, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
+    assert p256.tuning()["fft_streaming"] == 8 | 4
     # the row deposit at 1024^3 (the node deposit's meshes would not fit)
     assert p1k.tuning()["gather_shape"] == 4 and p1k.tuning()["gather_density"] == 8
     with pytest.raises(pkg.LppError):
