@@ -153,21 +153,22 @@ int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size(
 
 // Work meshes: one gather pass deposits up to kGatherMaxReal density fields
 // (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per
-// grid) into one of two sets of kWorkRow meshes.  FP32 up to N = 512 deposits
-// the shape fields with the node-parallel kernel, kNodeFields per pass, into
-// two sets of kWork meshes (42 meshes of 1.07 GB at 512^3; at 1024^3 that
-// would not fit the device).  FP64 at N >= 1024 keeps sets of kWorkF64Large
-// (two sets of eight 17 GB meshes and the bases would not fit the device),
-// and with them at most four density and two shape fields per pass.
+// grid) into one of two sets of kWorkRow meshes.  FP32 deposits the shape
+// fields with the node-parallel kernel: up to N = 512 kNodeFields per pass,
+// into two sets of kWork meshes (42 meshes of 1.07 GB at 512^3; at 1024^3
+// that would not fit the device), at 1024^3 four per pass into the kWorkRow
+// sets.  FP64 at N >= 1024 keeps sets of kWorkF64Large (two sets of eight
+// 17 GB meshes and the bases would not fit the device), and with them at
+// most four density and two shape fields per pass.
 constexpr int kWorkRow = 8;
 constexpr int kWork = 2 * kNodeFields;
 constexpr int kWorkF64Large = 4;
 static_assert(kWorkRow >= kGatherMaxReal && kWorkRow >= 2 * kGatherMaxComplex, "work meshes per gather pass");
 static_assert(kWorkRow >= kGatherMaxRealF64 && kWorkRow >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
 static_assert(kWork >= kWorkRow, "work mesh slots");
-bool node_gather(const lpp_plan_s* p) { return p->cfg.precision == LPP_F32 && p->cfg.mesh_n <= 512; }
+bool node_gather(const lpp_plan_s* p) { return p->cfg.precision == LPP_F32; }
 int work_meshes(const lpp_plan_s* p) {
-  if (node_gather(p)) return kWork;
+  if (p->cfg.precision == LPP_F32 && p->cfg.mesh_n <= 512) return kWork;
   return (p->cfg.precision == LPP_F64 && p->cfg.mesh_n >= 1024) ? kWorkF64Large : kWorkRow;
 }
 int max_density_fields(const lpp_plan_s* p) {
@@ -183,7 +184,7 @@ std::vector<FieldSpec> shape_specs(const lpp_plan_s* p) {
   return out;
 }
 int max_shape_fields(const lpp_plan_s* p) {
-  if (node_gather(p)) return kNodeFields;
+  if (node_gather(p)) return std::min(kNodeFields, work_meshes(p) / 2);
   return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex, work_meshes(p) / 2);
 }
 lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
@@ -1257,7 +1258,7 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
   if (s == LPP_OK)
-    s = node_gather(p) ? search(&lpp_tuning::gather_shape, {4, 6, 8, 10}, {LPP_STAGE_DEPOSIT})
+    s = node_gather(p) ? search(&lpp_tuning::gather_shape, {2, 4, 6, 8, 10}, {LPP_STAGE_DEPOSIT})
                        : search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;
   std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);
