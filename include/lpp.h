@@ -355,8 +355,9 @@ typedef struct {
   int32_t bin_blocks;      /* workgroups of the shell-sum kernels, 64 .. 8192               */
   int32_t gather_density;  /* density fields per deposit pass, 1 .. 8 (FP64 at N = 1024:
                               1 .. 4)                                                      */
-  int32_t gather_shape;    /* shape fields per deposit pass, 1 .. 4 (FP64 at N = 1024:
-                              1 .. 2)                                                      */
+  int32_t gather_shape;    /* shape fields per deposit pass: 1 .. 10 in FP32 up to N = 512,
+                              1 .. 4 in FP32 at N = 1024 and in FP64, 1 .. 2 in FP64 at
+                              N = 1024                                                     */
   int32_t serial;          /* 1: deposits and transforms on the plan's stream one after the
                               other; 0: the next pass's deposit runs on a second stream of the
                               plan while the current pass is transformed (profiling with

@@ -61,7 +61,8 @@ struct lpp_plan_s {
   void* d_phase = nullptr;
   void* d_invw = nullptr;
   // FP32 specs of the shape set's fields in pass order (the node-parallel deposit)
-  const SpecT<float>* d_spec = nullptr;
+  const SpecT<float>* d_spec = nullptr;     // shape fields in deposit order (node-parallel deposit), FP32
+  const SpecT<double>* d_spec64 = nullptr;  // ... and FP64
   int device = -1;
   // per-stage timing with HIP events on the plan's stream
   bool prof_on = false;
@@ -152,21 +153,20 @@ bool need_shape(const lpp_plan_s* p) { return (p->cfg.spectra & (LPP_GD | LPP_PL
 int n_acc(const lpp_plan_s* p) { return static_cast<int>(p->tab.acc_series.size()); }
 
 // Work meshes: one gather pass deposits up to kGatherMaxReal density fields
-// (one packed mesh each) or kGatherMaxComplex shape fields (one mesh per
-// grid) into one of two sets of kWorkRow meshes.  FP32 deposits the shape
-// fields with the node-parallel kernel: up to N = 512 kNodeFields per pass,
-// into two sets of kWork meshes (42 meshes of 1.07 GB at 512^3; at 1024^3
-// that would not fit the device), at 1024^3 four per pass into the kWorkRow
-// sets.  FP64 at N >= 1024 keeps sets of kWorkF64Large (two sets of eight
-// 17 GB meshes and the bases would not fit the device), and with them at
-// most four density and two shape fields per pass.
+// (one packed mesh each, the row kernel) or the shape fields of one pass
+// (one mesh per grid, the node-parallel kernel) into one of two sets of
+// work meshes: FP32 up to N = 512 sets of kWork (kNodeFields shape fields
+// per pass; 42 meshes of 1.07 GB at 512^3, which at 1024^3 would not fit
+// the device), otherwise sets of kWorkRow (four shape fields per pass),
+// and FP64 at N >= 1024 sets of kWorkF64Large (two sets of eight 17 GB
+// meshes and the bases would not fit the device: at most four density and
+// two shape fields per pass).
 constexpr int kWorkRow = 8;
 constexpr int kWork = 2 * kNodeFields;
 constexpr int kWorkF64Large = 4;
-static_assert(kWorkRow >= kGatherMaxReal && kWorkRow >= 2 * kGatherMaxComplex, "work meshes per gather pass");
-static_assert(kWorkRow >= kGatherMaxRealF64 && kWorkRow >= 2 * kGatherMaxComplexF64, "work meshes per gather pass");
+static_assert(kWorkRow >= kGatherMaxReal && kWorkRow >= 2 * kNodeFieldsF64, "work meshes per gather pass");
+static_assert(kWorkRow >= kGatherMaxRealF64, "work meshes per gather pass");
 static_assert(kWork >= kWorkRow, "work mesh slots");
-bool node_gather(const lpp_plan_s* p) { return p->cfg.precision == LPP_F32; }
 int work_meshes(const lpp_plan_s* p) {
   if (p->cfg.precision == LPP_F32 && p->cfg.mesh_n <= 512) return kWork;
   return (p->cfg.precision == LPP_F64 && p->cfg.mesh_n >= 1024) ? kWorkF64Large : kWorkRow;
@@ -184,8 +184,7 @@ std::vector<FieldSpec> shape_specs(const lpp_plan_s* p) {
   return out;
 }
 int max_shape_fields(const lpp_plan_s* p) {
-  if (node_gather(p)) return std::min(kNodeFields, work_meshes(p) / 2);
-  return std::min(p->cfg.precision == LPP_F64 ? kGatherMaxComplexF64 : kGatherMaxComplex, work_meshes(p) / 2);
+  return std::min(p->cfg.precision == LPP_F64 ? kNodeFieldsF64 : kNodeFields, work_meshes(p) / 2);
 }
 lpp_tuning resolved_tuning(const lpp_plan_s* p);  // launch shapes with the defaults filled in
 // passes of the 3D transform with non-temporal accesses (bit a for pass a), -1 = default
@@ -297,12 +296,15 @@ lpp_status ensure_tables(lpp_plan_s* p) {
   const size_t o_iw = o_ph + align_up(2 * rs * (3 * N + 1));
   const std::vector<FieldSpec> sg = shape_specs(p);
   const size_t o_sg = o_iw + align_up(rs * N);
-  const size_t total = o_sg + align_up(sizeof(SpecT<float>) * sg.size());
+  const size_t o_sg64 = o_sg + align_up(sizeof(SpecT<float>) * sg.size());
+  const size_t total = o_sg64 + align_up(sizeof(SpecT<double>) * sg.size());
   std::vector<char> host(total, 0);
   std::memcpy(host.data() + o_thr, p->tab.thr.data(), 8 * (nb + 1));
   for (size_t i = 0; i < sg.size(); ++i) {
     const SpecT<float> v = to_spec<float>(sg[i]);
     std::memcpy(host.data() + o_sg + i * sizeof(SpecT<float>), &v, sizeof v);
+    const SpecT<double> w = to_spec<double>(sg[i]);
+    std::memcpy(host.data() + o_sg64 + i * sizeof(SpecT<double>), &w, sizeof w);
   }
   const int pw = p->cfg.assignment;
   for (int m = 0; m < N; ++m) {
@@ -351,6 +353,7 @@ lpp_status ensure_tables(lpp_plan_s* p) {
   p->d_phase = c + o_ph;
   p->d_invw = c + o_iw;
   p->d_spec = reinterpret_cast<const SpecT<float>*>(c + o_sg);
+  p->d_spec64 = reinterpret_cast<const SpecT<double>*>(c + o_sg64);
   return LPP_OK;
 }
 
@@ -597,13 +600,13 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
                      const Footprint& fp, void* const* W, size_t j0) -> hipError_t {
     hipError_t e = prof_begin(p);
     if (e == hipSuccess) {
-      if constexpr (std::is_same<T, float>::value) {
-        if (cplx && node_gather(p))
+      if (cplx) {
+        if constexpr (std::is_same<T, float>::value)
           e = launch_gather_nodes(set, starts, p->geo, p->d_spec + j0, nf, W, fp.cube, true, gs);
         else
-          e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
+          e = launch_gather_nodes(set, starts, p->geo, p->d_spec64 + j0, nf, W, fp.cube, true, gs);
       } else {
-        e = launch_gather<T>(set, starts, p->geo, specs, nf, cplx, W, fp.cube, true, gs);
+        e = launch_gather<T>(set, starts, p->geo, specs, nf, W, fp.cube, true, gs);
       }
     }
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_DEPOSIT, 1);
@@ -832,7 +835,7 @@ lpp_status run_deposit(lpp_plan_s* p, const lpp_catalog* c, double scale, void* 
   if ((s = sort_set<T>(p, L, &rc, ws, wd, 1, false, setd, p->stream)) != LPP_OK) return s;
   const FieldSpec s0 = make_spec(0, 0, 0, 0);
   void* meshes[1] = {mesh};
-  LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, &s0, 1, 0, meshes,
+  LPP_TRY(launch_gather<T>(setd, reinterpret_cast<const uint32_t*>(wsp(p, L.starts_d)), p->geo, &s0, 1, meshes,
                            nullptr, false, p->stream));
   LPP_TRY(hipStreamSynchronize(p->stream));
   return LPP_OK;
@@ -933,7 +936,7 @@ lpp_status run_window(lpp_plan_s* p, const lpp_catalog* ran, double alpha, int l
     const int nf = static_cast<int>(std::min<size_t>(per, fields.size() - j0));
     FieldSpec specs[kWork];
     for (int q = 0; q < nf; ++q) specs[q] = fields[j0 + q].spec;
-    LPP_TRY(launch_gather<T>(setd, starts, p->geo, specs, nf, 0, W, fp.cube, true, st));
+    LPP_TRY(launch_gather<T>(setd, starts, p->geo, specs, nf, W, fp.cube, true, st));
     for (int q = 0; q < nf; ++q) LPP_TRY(fft(W[q], in_fp));
     for (int q = 0; q < nf; ++q) {
       const int gi = static_cast<int>(j0) + q;
@@ -1257,9 +1260,7 @@ lpp_status run_autotune(lpp_plan_s* p, const lpp_catalog* gal, const lpp_catalog
     s = search(&lpp_tuning::fft_streaming, {8 | 7, 8, 8 | 4, 8 | 5}, {LPP_STAGE_FFT_X, LPP_STAGE_FFT_YZ});
   if (s == LPP_OK) s = search(&lpp_tuning::bin_blocks, {1024, 2048, 4096, 8192}, {LPP_STAGE_BIN});
   if (s == LPP_OK) s = search(&lpp_tuning::gather_density, {2, 4, 6, 8}, {LPP_STAGE_DEPOSIT});
-  if (s == LPP_OK)
-    s = node_gather(p) ? search(&lpp_tuning::gather_shape, {2, 4, 6, 8, 10}, {LPP_STAGE_DEPOSIT})
-                       : search(&lpp_tuning::gather_shape, {1, 2, 3, 4}, {LPP_STAGE_DEPOSIT});
+  if (s == LPP_OK) s = search(&lpp_tuning::gather_shape, {1, 2, 4, 6, 8, 10}, {LPP_STAGE_DEPOSIT});
   p->prof_on = prof;
   std::copy(saved_ms, saved_ms + LPP_N_STAGES, p->prof_ms);
   std::copy(saved_l, saved_l + LPP_N_STAGES, p->prof_launches);

@@ -203,7 +203,9 @@ __device__ __forceinline__ void store_order(int i, int zblocked, int& kx, int& r
 // K = 1: NF real (density) fields, each written packed: grid -> .x, interlaced
 //        grid -> .y of mesh f (.y is zero without interlacing).
 // K = 2: NF complex (shape) fields; with interlacing grid -> mesh 2f and
-//        interlaced grid -> mesh 2f+1, without it grid -> mesh f.
+//        interlaced grid -> mesh 2f+1, without it grid -> mesh f.  (The
+//        library instantiates K = 1: the shape fields, few objects per
+//        tile, go through gather_nodes_kernel below.)
 // The tile is TX x TT x TT nodes (x, y, z); a 4-node x edge halves the
 // accumulators per thread and the window work per object (most of the 8 x
 // nodes of a row are out of an object's reach) for more tiles.
@@ -529,7 +531,7 @@ __device__ __forceinline__ uint32_t block_scan512(uint32_t v, uint32_t* sh, uint
 // K = 1: NF real fields, mesh q <- (grid, interlaced grid) of field q;
 // K = 2: NF complex fields, mesh q * copies + c <- grid copy c of field q.
 template <typename T, int P, int K, int NF>
-__global__ void __launch_bounds__(kNodeT, 6) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
+__global__ void __launch_bounds__(kNodeT, (sizeof(T) == 4 ? 6 : 4)) gather_nodes_kernel(GObjSet<T> o, const uint32_t* __restrict__ cell_start,
                                                                  int N, int lgN, int interlace, T H, T relx, T rely,
                                                                  T relz, const SpecT<T>* __restrict__ specs,
                                                                  MeshSetN<T> out,
@@ -1077,11 +1079,10 @@ hipError_t launch_cell_order(const uint32_t* starts, int64_t ncell, uint32_t* or
   return hipGetLastError();
 }
 
-template <int K, int NF>
-hipError_t dispatch_nodes(int p, const GObjSet<float>& o, const uint32_t* starts, const Geometry& g,
-                          const SpecT<float>* specs, void* const* meshes, const uint8_t* tiles, int zb,
+template <typename T, int K, int NF>
+hipError_t dispatch_nodes(int p, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
+                          const SpecT<T>* specs, void* const* meshes, const uint8_t* tiles, int zb,
                           hipStream_t st) {
-  using T = float;
   const T H = static_cast<T>(g.los_h), rx = static_cast<T>(g.los_rel[0]), ry = static_cast<T>(g.los_rel[1]),
           rz = static_cast<T>(g.los_rel[2]);
   MeshSetN<T> ms{};
@@ -1108,14 +1109,14 @@ hipError_t dispatch_nodes(int p, const GObjSet<float>& o, const uint32_t* starts
   return hipGetLastError();
 }
 
-template <int K, int NF>
-hipError_t nodes_upto(int nf, int p, const GObjSet<float>& o, const uint32_t* starts, const Geometry& g,
-                      const SpecT<float>* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
+template <typename T, int K, int NF>
+hipError_t nodes_upto(int nf, int p, const GObjSet<T>& o, const uint32_t* starts, const Geometry& g,
+                      const SpecT<T>* specs, void* const* meshes, const uint8_t* tiles, int zb, hipStream_t st) {
   if constexpr (NF == 0) {
     return hipErrorInvalidValue;
   } else {
-    if (nf == NF) return dispatch_nodes<K, NF>(p, o, starts, g, specs, meshes, tiles, zb, st);
-    return nodes_upto<K, NF - 1>(nf, p, o, starts, g, specs, meshes, tiles, zb, st);
+    if (nf == NF) return dispatch_nodes<T, K, NF>(p, o, starts, g, specs, meshes, tiles, zb, st);
+    return nodes_upto<T, K, NF - 1>(nf, p, o, starts, g, specs, meshes, tiles, zb, st);
   }
 }
 
@@ -1124,53 +1125,35 @@ hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_sta
                                bool zblocked, hipStream_t st) {
   const int zb = zblocked ? 1 : 0;
   if (g.N % TT != 0 || nf < 1) return hipErrorInvalidValue;
-  return nodes_upto<2, kNodeFields>(nf, g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+  return nodes_upto<float, 2, kNodeFields>(nf, g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+}
+
+hipError_t launch_gather_nodes(const GObjSet<double>& o, const uint32_t* cell_start, const Geometry& g,
+                               const SpecT<double>* specs, int nf, void* const* meshes,
+                               const uint8_t* tile_flags, bool zblocked, hipStream_t st) {
+  const int zb = zblocked ? 1 : 0;
+  if (g.N % TT != 0 || nf < 1) return hipErrorInvalidValue;
+  return nodes_upto<double, 2, kNodeFieldsF64>(nf, g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
 }
 
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
-                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
-                         hipStream_t st) {
+                         int nf, void* const* meshes, const uint8_t* tile_flags, bool zblocked, hipStream_t st) {
   static_assert(TT == kTile && TT == kZb, "footprint tiles are gather tiles and z-groups");
   const int zb = zblocked ? 1 : 0;
   if (g.N % TT != 0) return hipErrorInvalidValue;
-  if (!complex_fields) {
-    switch (nf) {
-      case 1:
-        return dispatch<T, 1, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-      case 2:
-        return dispatch<T, 1, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-      case 3:
-        return dispatch<T, 1, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-      case 4:
-        return dispatch<T, 1, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-      default:
-        break;
-    }
-    {
-      static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 8, "real passes of 5 to 8 fields");
-      switch (nf) {
-        case 5: return dispatch<T, 1, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 6: return dispatch<T, 1, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 7: return dispatch<T, 1, 7>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        case 8: return dispatch<T, 1, 8>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-        default: break;
-      }
-    }
-    return hipErrorInvalidValue;
-  }
+  static_assert(kGatherMaxReal == 8 && kGatherMaxRealF64 == 8, "real passes of 1 to 8 fields");
   switch (nf) {
-    case 1:
-      return dispatch<T, 2, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    case 2:
-      return dispatch<T, 2, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-    default:
-      break;
+    case 1: return dispatch<T, 1, 1>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 2: return dispatch<T, 1, 2>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 3: return dispatch<T, 1, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 4: return dispatch<T, 1, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 5: return dispatch<T, 1, 5>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 6: return dispatch<T, 1, 6>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 7: return dispatch<T, 1, 7>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    case 8: return dispatch<T, 1, 8>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
+    default: return hipErrorInvalidValue;
   }
-  static_assert(kGatherMaxComplex == 4 && kGatherMaxComplexF64 == 4, "complex passes of 3 and 4 fields");
-  if (nf == 3) return dispatch<T, 2, 3>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-  if (nf == 4) return dispatch<T, 2, 4>(g.p, o, cell_start, g, specs, meshes, tile_flags, zb, st);
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st) {
@@ -1194,8 +1177,8 @@ template hipError_t launch_cell_scatter<double>(const RawCat&, const Geometry&, 
 template hipError_t launch_cell_order<float>(const uint32_t*, int64_t, uint32_t*, GObjSet<float>, int, hipStream_t);
 template hipError_t launch_cell_order<double>(const uint32_t*, int64_t, uint32_t*, GObjSet<double>, int, hipStream_t);
 template hipError_t launch_gather<float>(const GObjSet<float>&, const uint32_t*, const Geometry&, const FieldSpec*,
-                                         int, int, void* const*, const uint8_t*, bool, hipStream_t);
+                                         int, void* const*, const uint8_t*, bool, hipStream_t);
 template hipError_t launch_gather<double>(const GObjSet<double>&, const uint32_t*, const Geometry&, const FieldSpec*,
-                                          int, int, void* const*, const uint8_t*, bool, hipStream_t);
+                                         int, void* const*, const uint8_t*, bool, hipStream_t);
 
 }  // namespace lpp

@@ -200,31 +200,31 @@ inline size_t footprint_bytes(int N) {
 }
 hipError_t launch_footprint(const uint32_t* cell_start, int N, Footprint fp, hipStream_t st);
 
-// Deposits nf fields of one object set in one pass and writes every node of
-// each output mesh (no clearing needed), z-blocked or (zblocked = false) plain.  With tile_flags (the footprint's
-// cube flags) the tiles that are not flagged are skipped and left unwritten.  Real fields (complex_fields = 0,
-// nf <= kGatherMaxReal, kGatherMaxRealF64 in FP64): mesh q holds field q
-// packed (grid -> real part, interlaced grid -> imaginary part).  Complex
-// fields (nf <= kGatherMaxComplex, kGatherMaxComplexF64 in FP64, where the
-// tiles are 4 nodes wide in x so that the FP64 accumulators fit):
-// with interlacing mesh 2q holds field q on the grid and mesh 2q+1 on the
-// interlaced grid, without it mesh q holds field q.
+// Deposits nf real (density) fields of one object set in one pass and
+// writes every node of each output mesh (no clearing needed), z-blocked or
+// (zblocked = false) plain.  With tile_flags (the footprint's cube flags) the
+// tiles that are not flagged are skipped and left unwritten.  nf <=
+// kGatherMaxReal (kGatherMaxRealF64 in FP64): mesh q holds field q packed
+// (grid -> real part, interlaced grid -> imaginary part).
 constexpr int kGatherMaxReal = 8;
 constexpr int kGatherMaxRealF64 = 8;
-constexpr int kGatherMaxComplex = 4;
-constexpr int kGatherMaxComplexF64 = 4;
-// complex (shape) fields per pass of the node-parallel deposit (FP32)
+// complex (shape) fields per pass of the node-parallel deposit (FP32, FP64)
 constexpr int kNodeFields = 10;
+constexpr int kNodeFieldsF64 = 4;
 template <typename T>
 hipError_t launch_gather(const GObjSet<T>& o, const uint32_t* cell_start, const Geometry& g, const FieldSpec* specs,
-                         int nf, int complex_fields, void* const* meshes, const uint8_t* tile_flags, bool zblocked,
-                         hipStream_t st);
-// The same for nf <= kNodeFields complex FP32 fields with one thread per node
-// of each 8^3 tile (same mesh order and results up to the order of the
-// sums); the fields' specs are read from the device table `specs` (nf entries).
+                         int nf, void* const* meshes, const uint8_t* tile_flags, bool zblocked, hipStream_t st);
+// Deposits nf complex (shape) fields, nf <= kNodeFields (kNodeFieldsF64 in
+// FP64), with one thread per node of each 8^3 tile: with interlacing mesh 2q
+// holds field q on the grid and mesh 2q+1 on the interlaced grid, without
+// it mesh q holds field q; the fields' specs are read from the device table
+// `specs` (nf entries).
 hipError_t launch_gather_nodes(const GObjSet<float>& o, const uint32_t* cell_start, const Geometry& g,
                                const SpecT<float>* specs, int nf, void* const* meshes, const uint8_t* tile_flags,
                                bool zblocked, hipStream_t st);
+hipError_t launch_gather_nodes(const GObjSet<double>& o, const uint32_t* cell_start, const Geometry& g,
+                               const SpecT<double>* specs, int nf, void* const* meshes,
+                               const uint8_t* tile_flags, bool zblocked, hipStream_t st);
 
 // plain-layout 3D transform (the public entry point)
 template <typename T>

@@ -145,7 +145,7 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     # a mesh of at most 256 MiB stays in the Infinity Cache between passes: only the z pass streams
     p256 = pkg.Plan(256, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert p256.tuning()["fft_streaming"] == 8 | 4
-    # the row deposit at 1024^3 (the node deposit's meshes would not fit)
+    # four shape fields per pass at 1024^3 (two sets of twenty meshes would not fit)
     assert p1k.tuning()["gather_shape"] == 4 and p1k.tuning()["gather_density"] == 8
     with pytest.raises(pkg.LppError):
         p1k.set_tuning(gather_shape=5)
