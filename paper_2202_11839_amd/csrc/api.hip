@@ -242,7 +242,7 @@ Layout layout(const lpp_plan_s* p, int64_t ng, int64_t nr) {
   L.sums_partial = take(8 * 8 * static_cast<size_t>(catalog_sum_blocks()));
   L.sums_out = take(8 * 16);
   const int nb = p->cfg.n_kbins;
-  L.bin_partial = take(8 * std::max(4, 2 * kBinGroup) * static_cast<size_t>(nb) *
+  L.bin_partial = take(8 * std::max(4, 2 * kBinGroupMax) * static_cast<size_t>(nb) *
                        std::max(bin_blocks(p->cfg.mesh_n), kMaxBinBlocks));
   L.acc = take(8 * (2 * static_cast<size_t>(nb) * n_acc(p) + 8 * static_cast<size_t>(nb)));
   for (int i = 0; i < 2; ++i) L.fp[i] = take(footprint_bytes(p->cfg.mesh_n));
@@ -654,7 +654,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
       }
       for (int m = 0; m < nf * (cplx ? copies : 1); ++m) LPP_TRY(fft(W[m], fp));
       // the set's base first (if it is in this pass), then the other fields in
-      // groups of up to kBinGroup that share the base and the kind of product
+      // groups of up to bin_group_max fields that share the base and the kind of product
       for (int q = 0; q < nf;) {
         const Job& jb = jobs[j0 + q];
         const int m0 = cplx ? q * copies : q;
@@ -673,12 +673,13 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         }
         const void* base = !cplx ? Bd : (jb.fam == FAM_GD ? Bd : Bg);
         const int kind = (cplx && jb.fam == FAM_MINUS) ? 1 : 0;
-        const FieldSpec* fs[kBinGroup];
-        const void* g1[kBinGroup];
-        const void* g2[kBinGroup];
-        int series[kBinGroup];
+        const FieldSpec* fs[kBinGroupMax];
+        const void* g1[kBinGroupMax];
+        const void* g2[kBinGroupMax];
+        int series[kBinGroupMax];
         int n = 0;
-        while (q < nf && n < kBinGroup) {
+        const int gmax = bin_group_max(cplx != 0, std::is_same<T, double>::value, nb);
+        while (q < nf && n < gmax) {
           const Job& jq = jobs[j0 + q];
           if (jq.series < 0) break;
           const void* bq = !cplx ? Bd : (jq.fam == FAM_GD ? Bd : Bg);
@@ -698,10 +699,10 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
         LPP_TRY(prof_begin(p));
         const int nblk = cplx ? ba.nblocks : bd.nblocks;
-        for (int i = 0; i < n; ++i)
-          LPP_TRY(launch_reduce_partials(partial + static_cast<size_t>(2) * i * nb * nblk, nblk, 2 * nb,
-                                         acc + static_cast<size_t>(2) * nb * series[i], st));
-        LPP_TRY(prof_end(p, LPP_STAGE_OTHER, n));
+        double* rows[kBinGroupMax];
+        for (int i = 0; i < n; ++i) rows[i] = acc + static_cast<size_t>(2) * nb * series[i];
+        LPP_TRY(launch_reduce_partials_group(partial, nblk, 2 * nb, n, rows, st));
+        LPP_TRY(prof_end(p, LPP_STAGE_OTHER, 1));
       }
       if (overlap) LPP_TRY(hipEventRecord(p->ev_done[pass & 1], st));
     }

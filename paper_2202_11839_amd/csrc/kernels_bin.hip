@@ -571,22 +571,32 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
   rows_store(dyn, rows_offset<T>(N), 2 * NFB * nb, a.partial);
 }
 
-// one block per column: strided partial sums, then a fixed-shape tree (deterministic)
+// one block per column c: strided partial sums, then a fixed-shape tree
+// (deterministic).  With n fields, column c of field i (partial column
+// i width + c) is added to dst.d[i][c], field by field in order: fields of
+// one launch that feed the same series (the 2L + 1 harmonics of one
+// multipole) add to the same row, as one launch per field would.
 constexpr int kRedThreads = 256;
+struct RowDst {
+  double* d[kBinGroupMax];
+};
 __global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const double* __restrict__ partial, int nblocks,
-                                                                      double* __restrict__ acc) {
+                                                                      int width, int n, RowDst dst) {
   __shared__ double sh[kRedThreads];
-  const int w = blockIdx.x;
-  const double* col = partial + static_cast<int64_t>(w) * nblocks;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += col[b];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+  const int c = blockIdx.x;
+  for (int i = 0; i < n; ++i) {
+    const double* col = partial + (static_cast<int64_t>(i) * width + c) * nblocks;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += col[b];
+    sh[threadIdx.x] = s;
     __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) dst.d[i][c] += sh[0];
+    __syncthreads();  // sh is reused by the next field
   }
-  if (threadIdx.x == 0) acc[w] += sh[0];
 }
 
 }  // namespace
@@ -594,6 +604,12 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partials_kernel(const doub
 int pair_bin_blocks(int N, int nblocks) {
   const int64_t want = (pair_units(N) + kBinThreads - 1) / kBinThreads;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, nblocks)));
+}
+
+int bin_group_max(bool complex_fields, bool fp64, int nb) {
+  const int by_regs = (complex_fields && !fp64) ? kBinGroupMax : kBinGroup;
+  const int by_lds = (4 * kMaxBins) / (2 * std::max(1, nb));  // LDS rows of 2 n nb sums per wavefront
+  return std::max(1, std::min(by_regs, by_lds));
 }
 
 int bin_blocks(int N) {
@@ -672,6 +688,9 @@ hipError_t bin_gg_kind(const BinArgs& a, const FieldSpec* const* f, const void* 
     case 2: return bin_gg_group_n<T, KIND, 2>(a, f, g1, g2, base, st);
     case 3: return bin_gg_group_n<T, KIND, 3>(a, f, g1, g2, base, st);
     case 4: return bin_gg_group_n<T, KIND, 4>(a, f, g1, g2, base, st);
+    case 5:  // FP32 only: five fields keep three waves per SIMD (155 VGPRs)
+      if constexpr (sizeof(T) == 4) return bin_gg_group_n<T, KIND, 5>(a, f, g1, g2, base, st);
+      else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -684,7 +703,18 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st) {
-  reduce_partials_kernel<<<width, kRedThreads, 0, st>>>(partial, nblocks, acc);
+  RowDst dst{};
+  dst.d[0] = acc;
+  reduce_partials_kernel<<<width, kRedThreads, 0, st>>>(partial, nblocks, width, 1, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials_group(const double* partial, int nblocks, int width, int n, double* const* acc,
+                                        hipStream_t st) {
+  if (n < 1 || n > kBinGroupMax) return hipErrorInvalidValue;
+  RowDst dst{};
+  for (int i = 0; i < n; ++i) dst.d[i] = acc[i];
+  reduce_partials_kernel<<<width, kRedThreads, 0, st>>>(partial, nblocks, width, n, dst);
   return hipGetLastError();
 }
 

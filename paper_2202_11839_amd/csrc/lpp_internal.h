@@ -294,6 +294,10 @@ hipError_t launch_base_gg(const BinArgs& a, const void* g1, const void* g2, void
 // (width 2 n nb).  kind 0: G conj(B(k)) (plus / cross), 1: G B(-k) (minus);
 // g2 nullable without interlacing.
 constexpr int kBinGroup = 4;
+constexpr int kBinGroupMax = 5;  // FP32 shape fields
+// fields per shell-sum launch: kBinGroupMax for FP32 shape fields, else
+// kBinGroup, fewer when 2 n nb sums per wavefront would not fit the LDS rows
+int bin_group_max(bool complex_fields, bool fp64, int nb);
 template <typename T>
 hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
                          int n, const void* base, int kind, hipStream_t st);
@@ -320,5 +324,10 @@ hipError_t launch_window_bin(const WinArgs& a, const void* D, const FieldSpec* f
 
 // acc[0..width) += sum over blocks of partial, laid out [width][nblocks] (fixed order)
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st);
+// n such reductions in one launch: columns [i width, (i + 1) width) of the
+// partial rows are added to acc[i], in the order i = 0 .. n-1 (rows acc[i]
+// may coincide; n <= kBinGroupMax)
+hipError_t launch_reduce_partials_group(const double* partial, int nblocks, int width, int n, double* const* acc,
+                                        hipStream_t st);
 
 }  // namespace lpp
