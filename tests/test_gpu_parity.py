@@ -216,6 +216,22 @@ def test_dense_deposit_in_chunks_matches_oracle(lpp, p, il, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_maximum_shell_count_matches_oracle(lpp, prec):
+    """The largest number of k-shells (256, of width 1/8 of the fundamental
+    mode on a 64^3 mesh, up to its Nyquist frequency): the shell sums of a
+    launch then hold 2 n 256 rows per wavefront, which limits a launch to
+    four fields; counts bit-exact and every series against the oracle."""
+    n, box, origin, obs = 64, 400.0, (300.0, 200.0, 250.0), (0.0, 0.0, 0.0)
+    g, r = _cats(37, 3000, 9000, origin, box)
+    cfg = E.Config(mesh=n, box=box, origin=origin, observer=obs, assignment=3, interlacing=1, n_kbins=256,
+                   dn=(1, 8), lmax=4)
+    ref = E.mesh64(g, r, cfg)
+    plan = lpp.Plan(n, box, origin, obs, assignment=3, interlacing=1, precision=prec, lmax=4, n_kbins=256,
+                    dn=(1, 8))
+    _compare(plan.estimate(g, r), ref, 1e-9 if prec == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_dense_estimate_matches_oracle(lpp, prec):
     """A dense catalog pair (2,000 galaxies and 40,000 randoms on a 16^3
     mesh, ~10 density objects per cell, so the density passes stage each tile
