@@ -91,9 +91,12 @@ def launches_per_set(res):
     """Transforms per estimate at l <= 4 with interlacing: the density set has
     15 fields (one packed mesh each), the shape set 38 (two interlaced meshes
     each): 1 + 5 + 9 plus-type, 5 + 9 cross, 9 minus.  Every transform runs
-    one y pass and one z pass of the strided kernel."""
+    one y pass of the strided kernel; the z pass runs as its own launch for
+    the density meshes and the two meshes of the shape set's base only (the
+    other shape fields take it inside the fused shell-sum kernel).  Returns
+    (density meshes, shape meshes, shape meshes with a z-pass launch)."""
     assert len(res["series"]) == 15, res["series"]
-    return 15, 76
+    return 15, 76, 2
 
 
 def strided_pass_bytes(pos, wl):
@@ -675,12 +678,12 @@ def main():
     stages = {k: v for k, v in prof.items() if v[1] > 0}
     total_ms, launches = stages["fft_yz"]
     avg_ms = total_ms / launches
-    nd_mesh, ns_mesh = launches_per_set(res)
+    nd_mesh, ns_mesh, ns_z = launches_per_set(res)
     yd, zd = strided_pass_bytes(np.concatenate([gal.pos(), ran.pos()]), wl)
     ys, zs = strided_pass_bytes(gal.pos(), wl)
-    n_strided = 2 * (nd_mesh + ns_mesh)
+    n_strided = 2 * nd_mesh + ns_mesh + ns_z
     assert launches == n_strided * psteps, (launches, n_strided)
-    alg_bytes = (nd_mesh * (yd + zd) + ns_mesh * (ys + zs)) / n_strided  # per launch
+    alg_bytes = (nd_mesh * (yd + zd) + ns_mesh * ys + ns_z * zs) / n_strided  # per launch
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     traffic = committed_traffic(strided_kernel_name(n, plan.tuning(), names_only=True))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -614,15 +614,17 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
   };
   // the binning reads modes inside the last shell only
   const int qmax = static_cast<int>(p->tab.thr[nb]);
-  auto fft = [&](void* m, const Footprint& fp) -> hipError_t {
+  // (zpass false: the z pass is left to the fused shell-sum kernel)
+  auto fft = [&](void* m, const Footprint& fp, bool zpass) -> hipError_t {
     const FftPrune pr{fp.row, fp.plane, fp.cube, qmax};
     hipError_t e = prof_begin(p);
     if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 0, pr, st, p->tune.fft_rows_x, streaming(p));
     if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_X, 1);
     if (e == hipSuccess) e = prof_begin(p);
     if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 1, pr, st, p->tune.fft_cols_y, streaming(p));
-    if (e == hipSuccess) e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_z, streaming(p));
-    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, 2);
+    if (e == hipSuccess && zpass)
+      e = launch_fft_axis_zb<T>(m, N, p->d_tw, 2, pr, st, p->tune.fft_cols_z, streaming(p));
+    if (e == hipSuccess) e = prof_end(p, LPP_STAGE_FFT_YZ, zpass ? 2 : 1);
     return e;
   };
   // Fields in gather order: each set's base first (its spectrum is the
@@ -652,7 +654,15 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         LPP_TRY(hipEventRecord(p->ev_dep[pass & 1], gs));
         LPP_TRY(hipStreamWaitEvent(st, p->ev_dep[pass & 1], 0));
       }
-      for (int m = 0; m < nf * (cplx ? copies : 1); ++m) LPP_TRY(fft(W[m], fp));
+      // The complex fields other than the set's base take their z pass inside
+      // the fused shell-sum kernel, in groups of up to zmax fields (zmax = 0:
+      // the fused kernel's LDS cannot hold this many shells at this N, and
+      // every field takes the three passes and then the shell-sum kernel).
+      const int zmax = cplx ? zbin_group_max(N, std::is_same<T, double>::value, nb) : 0;
+      for (int m = 0; m < nf * (cplx ? copies : 1); ++m) {
+        const bool fused = zmax > 0 && jobs[j0 + m / copies].series >= 0;
+        LPP_TRY(fft(W[m], fp, !fused));
+      }
       // the set's base first (if it is in this pass), then the other fields in
       // groups of up to bin_group_max fields that share the base and the kind of product
       for (int q = 0; q < nf;) {
@@ -678,7 +688,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         const void* g2[kBinGroupMax];
         int series[kBinGroupMax];
         int n = 0;
-        const int gmax = bin_group_max(cplx != 0, std::is_same<T, double>::value, nb);
+        const int gmax = zmax > 0 ? zmax : bin_group_max(cplx != 0, std::is_same<T, double>::value, nb);
         while (q < nf && n < gmax) {
           const Job& jq = jobs[j0 + q];
           if (jq.series < 0) break;
@@ -695,10 +705,13 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
         }
         LPP_TRY(prof_begin(p));
         if (!cplx) LPP_TRY(launch_bin_dd<T>(bd, fs, g1, n, base, st));
+        else if (zmax > 0)
+          LPP_TRY(launch_zbin_gg<T>(ba, fs, g1, il ? g2 : nullptr, n, base, kind, p->d_tw, fp.plane, st));
         else LPP_TRY(launch_bin_gg<T>(ba, fs, g1, il ? g2 : nullptr, n, base, kind, st));
         LPP_TRY(prof_end(p, LPP_STAGE_BIN, 1));
         LPP_TRY(prof_begin(p));
-        const int nblk = cplx ? ba.nblocks : bd.nblocks;
+        const int nblk = !cplx ? bd.nblocks : (zmax > 0 ? zbin_blocks(N, std::is_same<T, double>::value, ba.nblocks)
+                                                        : ba.nblocks);
         double* rows[kBinGroupMax];
         for (int i = 0; i < n; ++i) rows[i] = acc + static_cast<size_t>(2) * nb * series[i];
         LPP_TRY(launch_reduce_partials_group(partial, nblk, 2 * nb, n, rows, st));

@@ -39,7 +39,6 @@ namespace {
 using dev::cmul;
 using dev::cmulc;
 using dev::combine;
-using dev::harmonic;
 using dev::KSpec;
 using dev::kspec_of;
 using dev::sgn_mode;
@@ -56,6 +55,30 @@ __device__ __forceinline__ T inv_sqrt(int q) {
     return __builtin_amdgcn_rsqf(static_cast<float>(q));
   else
     return 1.0 / sqrt(static_cast<double>(q));
+}
+
+// The real harmonic h_{L,M,cs}(khat) = Q(khat_z) Re|Im (khat_x + i khat_y)^M
+// of a mode n, written as Q(nz/|n|) az / |n|^M with the azimuthal factor
+// az = Re|Im (nx + i ny)^M of the mode's (x, y) column, which every mode of a
+// z-run shares: per mode a polynomial in nz/|n| and M products.
+template <typename T>
+__device__ __forceinline__ T column_azimuth(const KSpec<T>& h, int nx, int ny) {
+  T er = 1, ei = 0;
+  for (int m = 0; m < h.M; ++m) {
+    const T tr = er * static_cast<T>(nx) - ei * static_cast<T>(ny);
+    ei = er * static_cast<T>(ny) + ei * static_cast<T>(nx);
+    er = tr;
+  }
+  return h.cs ? ei : er;
+}
+template <typename T>
+__device__ __forceinline__ T harmonic_of_column(const KSpec<T>& h, T az, int nz, T rq) {
+  const T u = static_cast<T>(nz) * rq;
+  T Q = 0;
+  for (int i = h.nq - 1; i >= 0; --i) Q = Q * u + h.q[i];
+  T sc = az;
+  for (int m = 0; m < h.M; ++m) sc *= rq;
+  return Q * sc;
 }
 
 constexpr int kBinThreads = 256;
@@ -202,25 +225,27 @@ size_t bin_lds_bytes(int N, int width) {
   return rows_offset<T>(N) + 8 * static_cast<size_t>(kBinWaves) * width;
 }
 
-// thresholds to LDS, every row to zero; returns this wavefront's row
+// thresholds to LDS, every row to zero (NW wavefronts); returns this wavefront's row
+template <int NW = kBinWaves>
 __device__ __forceinline__ double* rows_init(unsigned char* dyn, size_t off, int width, const int64_t* thr, int* sthr,
                                              int nb) {
   double* rows = reinterpret_cast<double*>(dyn + off);
   for (int i = threadIdx.x; i <= nb; i += blockDim.x) sthr[i] = static_cast<int>(thr[i]);
-  for (int i = threadIdx.x; i < kBinWaves * width; i += blockDim.x) rows[i] = 0.0;
+  for (int i = threadIdx.x; i < NW * width; i += blockDim.x) rows[i] = 0.0;
   __syncthreads();
   return rows + (threadIdx.x >> 6) * width;
 }
 
 // the block's partial row (the wavefront rows added in order), stored
 // column-major, [width][gridDim.x], for a coalesced reduction
+template <int NW = kBinWaves>
 __device__ __forceinline__ void rows_store(const unsigned char* dyn, size_t off, int width, double* partial) {
   const double* rows = reinterpret_cast<const double*>(dyn + off);
   __syncthreads();
   for (int i = threadIdx.x; i < width; i += blockDim.x) {
     double v = rows[i];
 #pragma unroll
-    for (int w = 1; w < kBinWaves; ++w) v += rows[w * width + i];
+    for (int w = 1; w < NW; ++w) v += rows[w * width + i];
     partial[static_cast<int64_t>(i) * gridDim.x + blockIdx.x] = v;
   }
 }
@@ -443,6 +468,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
 #pragma unroll
       for (int f = 0; f < NFB; ++f) {
         const T2* __restrict__ P = g.P[f];
+        const T az = column_azimuth(g.h[f], pu.nx, pu.ny);
         T2 pa[kRun], pm[kRun];
 #pragma unroll
         for (int j = 0; j < kRun; ++j) pa[j] = P[run + j];
@@ -457,9 +483,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_dd_group_kernel(BinArgs a, Dd
           const T2 f1{static_cast<T>(0.5) * (pa[j].x + m.x), static_cast<T>(0.5) * (pa[j].y - m.y)};
           const T2 f2{static_cast<T>(0.5) * (pa[j].y + m.y), static_cast<T>(-0.5) * (pa[j].x - m.x)};
           const T2 F = combine<T, T2>(f1, f2, a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
-          const int q = pu.qxy + nz * nz;
-          const T rq = inv_sqrt<T>(q);
-          const T hk = harmonic(g.h[f], pu.nx * rq, pu.ny * rq, nz * rq);
+          const T hk = harmonic_of_column(g.h[f], az, nz, inv_sqrt<T>(pu.qxy + nz * nz));
           if (b != cur[f]) {
             if (cur[f] >= 0) atomicAdd(&v[2 * f * nb + cur[f]], sr[f]);
             cur[f] = b;
@@ -531,6 +555,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
     }
 #pragma unroll
     for (int f = 0; f < NFB; ++f) {
+      const T az = column_azimuth(g.h[f], nx, ny);
       T2 g1[kRun], g2[kRun];
 #pragma unroll
       for (int j = 0; j < kRun; ++j) g1[j] = g.g1[f][run + j];
@@ -545,9 +570,7 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
         const int iz = z0 + j, nz = sgn_mode(iz, N);
         const T2 F = combine<T, T2>(g1[j], a.interlace ? g2[j] : g1[j], a.interlace, cmul(pxy, px[nz + N / 2]),
                                     wxy * iw[iz]);
-        const int q = nx * nx + ny * ny + nz * nz;
-        const T rq = inv_sqrt<T>(q);
-        const T hk = harmonic(g.h[f], nx * rq, ny * rq, nz * rq);
+        const T hk = harmonic_of_column(g.h[f], az, nz, inv_sqrt<T>(nx * nx + ny * ny + nz * nz));
         const T2 p = KIND == 0 ? cmulc(F, bv[j]) : cmul(F, bv[j]);
         if (b != cur[f]) {
           if (cur[f] >= 0) {
@@ -569,6 +592,197 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
       atomicAdd(&v[(2 * f + 1) * nb + cur[f]], sim[f]);
     }
   rows_store(dyn, rows_offset<T>(N), 2 * NFB * nb, a.partial);
+}
+
+// ---- the z pass of complex fields fused with their shell sums ----
+//
+// The last transform pass (along z) of a group's fields is followed at once
+// by the shell sums, so that the transformed fields are never written to HBM
+// and read back.  A workgroup takes the NL adjacent columns x of one row y
+// that fft_zb_kernel's z pass takes (N/8 threads per column, the same lines
+// and pruning) and, field by field, transforms the grid copy and the
+// interlaced copy of every column, combines the two in registers and passes
+// the combined modes through LDS, after which each thread holds one z-group
+// run of one column: the run's base values and shells are loaded once for all
+// fields of the group, and the sums go, as in bin_gg_group_kernel, to the
+// thread's wavefront's LDS row (fields in order, so two runs are bitwise
+// equal).  Workgroups walk the (column block, y) items in a stride of the
+// grid; a block outside the last shell is skipped whole.
+template <typename T>
+struct ZbGroup {
+  KSpec<T> h[kBinGroupMax];
+  const typename V2<T>::type* g1[kBinGroupMax];  // grid copies after the x and y passes
+  const typename V2<T>::type* g2[kBinGroupMax];  // interlaced copies (unused without interlacing)
+  int n;
+};
+
+template <typename T, int N, int NL>
+constexpr int zbin_waves() {
+  return (NL * (N / 8) + 63) / 64;
+}
+
+// KIND 0: h F conj(B(k)); KIND 1: h F B(-k)
+// waves per SIMD to keep registers for: two workgroups per CU, one of 1024
+// threads (FP32, N = 1024) or with FP64 lines of 1024 (LDS)
+template <typename T, int N, int NL>
+constexpr int zbin_min_waves() {
+  constexpr int threads = NL * (N / 8);
+  constexpr int blocks = (threads >= 1024 || (sizeof(T) == 8 && N >= 1024)) ? 1 : 2;
+  constexpr int w = blocks * threads / 256;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+template <typename T, int N, int NL, int KIND>
+__global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_gg_kernel(BinArgs a, ZbGroup<T> g,
+                                                             const typename V2<T>::type* __restrict__ B,
+                                                             const typename V2<T>::type* __restrict__ tw,
+                                                             const uint8_t* __restrict__ plane) {
+  using T2 = typename V2<T>::type;
+  constexpr int TL = N / 8;
+  constexpr int NT = NL * TL;
+  constexpr int NW = zbin_waves<T, N, NL>();
+  static_assert(NL <= N / 2 && (N / 2) % NL == 0, "column blocks inside one half of the kx range");
+  __shared__ T2 sm[NL * N];
+  __shared__ T2 stw[N];
+  __shared__ int sthr[kMaxBins + 1];
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int nb = a.nb, n = g.n;
+  T2* px = reinterpret_cast<T2*>(dyn);
+  T* iw = reinterpret_cast<T*>(px + N);
+  tables_init<T>(a, px, iw);
+  for (int i = threadIdx.x; i < N; i += NT) stw[i] = tw[i];
+  const int width = 2 * n * nb;
+  double* v = rows_init<NW>(dyn, rows_offset<T>(N), width, a.thr, sthr, nb);  // (ends with a barrier)
+  const T2* phase = static_cast<const T2*>(a.phase);
+  const T* invw = static_cast<const T*>(a.invw);
+  const int qmax = sthr[nb];
+  const float inv_dn = static_cast<float>(nb) / sqrtf(static_cast<float>(qmax));
+  constexpr int mask = N - 1;
+  constexpr int64_t hi = static_cast<int64_t>(N) * N * kZb;  // z-group stride
+  const int tid = threadIdx.x;
+  // the thread's transform line (as the z pass) ...
+  int col, t, swz;
+  if constexpr (TL >= 8) {
+    col = (tid >> 3) % NL;
+    t = (tid & 7) | ((tid / (8 * NL)) << 3);
+    swz = dev::swizzle_rows8<N>(col);
+  } else {
+    col = tid % NL;
+    t = tid / NL;
+    swz = col & 15;
+  }
+  // ... and its run for the sums: column rc, z-group rg (one run per thread)
+  const int rc = tid % NL, rg = tid / NL;
+  const int rswz = TL >= 8 ? dev::swizzle_rows8<N>(rc) : (rc & 15);
+  const int z0 = rg * kRun;
+  constexpr int nitems = (N / NL) * N;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int xc = item % (N / NL), y = item / (N / NL);
+    const int c0 = xc * NL;
+    const int mxb = c0 < N / 2 ? c0 : N - c0 - (NL - 1);  // the block's smallest |nx|
+    const int ny = sgn_mode(y, N);
+    if (mxb * mxb + ny * ny >= qmax) continue;  // (uniform over the block)
+    const int x = c0 + col, nx = sgn_mode(x, N);
+    const bool live = nx * nx + ny * ny < qmax;
+    const int64_t lbase = zb_index(x, y, 0, N);
+    bool rd[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) rd[j] = live && (plane == nullptr || plane[t + j * TL] != 0);
+    const T wxy = invw[x] * invw[y];
+    const T2 pxy = phase[nx + ny + 3 * N / 2];
+    const int rx = c0 + rc, rnx = sgn_mode(rx, N);
+    const int qxy = rnx * rnx + ny * ny;
+    const bool rlive = run_live(z0, N, qxy, qmax);
+    int bq[kRun];  // the run's shells (-1: outside the last shell)
+#pragma unroll
+    for (int j = 0; j < kRun; ++j) {
+      const int nz = sgn_mode(z0 + j, N);
+      bq[j] = rlive ? shell_of(qxy + nz * nz, sthr, nb, inv_dn) : -1;
+    }
+#pragma unroll 1
+    for (int f = 0; f < n; ++f) {
+      // Opaque copies of the line position and the run start: what depends
+      // on them only (load offsets, LDS addresses of the transform's
+      // exchanges, output rows, the modes' unit vectors and shells) is then
+      // recomputed where it is used instead of being held in registers across
+      // the field loop and the transforms, which would halve the occupancy.
+      int tq = t, cq = col, sq = swz, zq = z0;
+      asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq), "+v"(zq));
+      // both copies' loads in flight before the first transform
+      T2 v1[8], w[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = tq + j * TL;
+        const int64_t off = lbase + (e >> 3) * hi + (e & 7);
+        v1[j] = w[j] = T2{0, 0};
+        if (rd[j]) {
+          v1[j] = dev::nt_load(g.g1[f] + off);
+          if (a.interlace) w[j] = dev::nt_load(g.g2[f] + off);
+        }
+      }
+      dev::fft_column_regs<T, N>(stw, sm, cq, tq, v1, sq);
+      if (a.interlace) {
+        asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq));
+        dev::fft_column_regs<T, N>(stw, sm, cq, tq, w, sq);
+      }
+      asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq));
+      // combined, compensated modes of the lines to LDS, runs back
+      int row[8];
+      dev::fft_rows<N>(tq, row);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int iz = row[q], nz = sgn_mode(iz, N);
+        sm[dev::sidx<N>(cq, iz, sq)] =
+            combine<T, T2>(v1[q], w[q], a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
+      }
+      __syncthreads();
+      T2 F[kRun];
+#pragma unroll
+      for (int j = 0; j < kRun; ++j) F[j] = sm[dev::sidx<N>(rc, zq + j, rswz)];
+      __syncthreads();  // (sm is the next transform's exchange buffer)
+      if (rlive) {
+        // the run's base values (again for every field, from the L2 after
+        // the first: held across the transforms they would cost registers
+        // and with them occupancy)
+        T2 bv[kRun];
+        const int64_t run = zb_index(rx, y, zq, N);
+        const int mx = (N - rx) & mask, my = (N - y) & mask;
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+          bv[j] = T2{0, 0};
+          if (KIND == 0) bv[j] = B[run + j];
+          else if (bq[j] >= 0) bv[j] = B[zb_index(mx, my, (N - zq - j) & mask, N)];
+        }
+        const KSpec<T>& h = g.h[f];
+        const T az = column_azimuth(h, rnx, ny);
+        int cur = -1;
+        double sre = 0.0, sim = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRun; ++j) {
+          const int b = bq[j];
+          if (b < 0) continue;
+          const int nz = sgn_mode(zq + j, N);
+          const T hk = harmonic_of_column(h, az, nz, inv_sqrt<T>(qxy + nz * nz));
+          const T2 p = KIND == 0 ? cmulc(F[j], bv[j]) : cmul(F[j], bv[j]);
+          if (b != cur) {
+            if (cur >= 0) {
+              atomicAdd(&v[2 * f * nb + cur], sre);
+              atomicAdd(&v[(2 * f + 1) * nb + cur], sim);
+            }
+            cur = b;
+            sre = sim = 0.0;
+          }
+          sre += static_cast<double>(hk * p.x);
+          sim += static_cast<double>(hk * p.y);
+        }
+        if (cur >= 0) {
+          atomicAdd(&v[2 * f * nb + cur], sre);
+          atomicAdd(&v[(2 * f + 1) * nb + cur], sim);
+        }
+      }
+    }
+  }
+  rows_store<NW>(dyn, rows_offset<T>(N), width, a.partial);
 }
 
 // one block per column c: strided partial sums, then a fixed-shape tree
@@ -702,6 +916,104 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void
   return kind == 0 ? bin_gg_kind<T, 0>(a, f, g1, g2, n, base, st) : bin_gg_kind<T, 1>(a, f, g1, g2, n, base, st);
 }
 
+namespace {
+
+// columns per workgroup of the fused kernel: 8 in FP32 (runs of 512
+// contiguous bytes, as the z pass), 4 in FP64 (the same bytes per run, and
+// LDS for two workgroups per CU)
+constexpr int zbin_lines(bool fp64) { return fp64 ? 4 : 8; }
+
+}  // namespace
+
+// workgroups of the fused kernel for a budget of nblocks: at most one per item
+int zbin_blocks(int N, bool fp64, int nblocks) {
+  const int items = (N / zbin_lines(fp64)) * N;
+  return std::max(1, std::min(items, nblocks));
+}
+
+namespace {
+
+// dynamic LDS (the per-axis tables and a row of 2 n nb sums per wavefront),
+// and all of it with the static arrays (lines, twiddles, thresholds)
+template <typename T, int N>
+size_t zbin_dyn_lds(int n, int nb) {
+  constexpr int NW = zbin_waves<T, N, zbin_lines(sizeof(T) == 8)>();
+  return rows_offset<T>(N) + 8 * static_cast<size_t>(NW) * 2 * n * nb;
+}
+template <typename T, int N>
+size_t zbin_lds(int n, int nb) {
+  constexpr int NL = zbin_lines(sizeof(T) == 8);
+  return static_cast<size_t>(NL + 1) * N * sizeof(typename V2<T>::type) + 4 * (kMaxBins + 1) + zbin_dyn_lds<T, N>(n, nb);
+}
+
+template <typename T, int N>
+int zbin_group_max_n(int nb) {
+  const int cap = sizeof(T) == 4 ? kBinGroupMax : kBinGroup;
+  int n = 0;
+  while (n < cap && zbin_lds<T, N>(n + 1, nb) <= 160 * 1024) ++n;
+  return n;
+}
+
+template <typename T, int N, int KIND>
+hipError_t zbin_launch(const BinArgs& a, const ZbGroup<T>& g, const void* base, const void* tw, const uint8_t* plane,
+                       hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  constexpr int NL = zbin_lines(sizeof(T) == 8);
+  const int grid = zbin_blocks(N, sizeof(T) == 8, a.nblocks);
+  zbin_gg_kernel<T, N, NL, KIND><<<grid, NL * (N / 8), zbin_dyn_lds<T, N>(g.n, a.nb), st>>>(
+      a, g, static_cast<const T2*>(base), static_cast<const T2*>(tw), plane);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t zbin_n(const BinArgs& a, const ZbGroup<T>& g, const void* base, int kind, const void* tw,
+                  const uint8_t* plane, hipStream_t st) {
+  if (g.n < 1 || g.n > zbin_group_max_n<T, N>(a.nb)) return hipErrorInvalidValue;
+  return kind == 0 ? zbin_launch<T, N, 0>(a, g, base, tw, plane, st) : zbin_launch<T, N, 1>(a, g, base, tw, plane, st);
+}
+
+}  // namespace
+
+int zbin_group_max(int N, bool fp64, int nb) {
+  if (nb < 1 || nb > kMaxBins) return 0;
+  switch (N) {
+    case 16: return fp64 ? zbin_group_max_n<double, 16>(nb) : zbin_group_max_n<float, 16>(nb);
+    case 32: return fp64 ? zbin_group_max_n<double, 32>(nb) : zbin_group_max_n<float, 32>(nb);
+    case 64: return fp64 ? zbin_group_max_n<double, 64>(nb) : zbin_group_max_n<float, 64>(nb);
+    case 128: return fp64 ? zbin_group_max_n<double, 128>(nb) : zbin_group_max_n<float, 128>(nb);
+    case 256: return fp64 ? zbin_group_max_n<double, 256>(nb) : zbin_group_max_n<float, 256>(nb);
+    case 512: return fp64 ? zbin_group_max_n<double, 512>(nb) : zbin_group_max_n<float, 512>(nb);
+    case 1024: return fp64 ? zbin_group_max_n<double, 1024>(nb) : zbin_group_max_n<float, 1024>(nb);
+    default: return 0;
+  }
+}
+
+template <typename T>
+hipError_t launch_zbin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
+                          int n, const void* base, int kind, const void* tw, const uint8_t* plane, hipStream_t st) {
+  using T2 = typename V2<T>::type;
+  // (the partial rows hold 2 kBinGroupMax nb sums per workgroup; the LDS
+  // bound on n is checked per N)
+  if (a.nb < 1 || a.nb > kMaxBins || n < 1 || n > kBinGroupMax) return hipErrorInvalidValue;
+  ZbGroup<T> g{};
+  g.n = n;
+  for (int i = 0; i < n; ++i) {
+    g.h[i] = kspec_of<T>(*f[i]);
+    g.g1[i] = static_cast<const T2*>(g1[i]);
+    g.g2[i] = static_cast<const T2*>(g2 ? g2[i] : g1[i]);
+  }
+  switch (a.N) {
+    case 16: return zbin_n<T, 16>(a, g, base, kind, tw, plane, st);
+    case 32: return zbin_n<T, 32>(a, g, base, kind, tw, plane, st);
+    case 64: return zbin_n<T, 64>(a, g, base, kind, tw, plane, st);
+    case 128: return zbin_n<T, 128>(a, g, base, kind, tw, plane, st);
+    case 256: return zbin_n<T, 256>(a, g, base, kind, tw, plane, st);
+    case 512: return zbin_n<T, 512>(a, g, base, kind, tw, plane, st);
+    case 1024: return zbin_n<T, 1024>(a, g, base, kind, tw, plane, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_reduce_partials(const double* partial, int nblocks, int width, double* acc, hipStream_t st) {
   RowDst dst{};
   dst.d[0] = acc;
@@ -726,6 +1038,12 @@ template hipError_t launch_bin_gg<float>(const BinArgs&, const FieldSpec* const*
                                          const void* const*, int, const void*, int, hipStream_t);
 template hipError_t launch_bin_gg<double>(const BinArgs&, const FieldSpec* const*, const void* const*,
                                           const void* const*, int, const void*, int, hipStream_t);
+template hipError_t launch_zbin_gg<float>(const BinArgs&, const FieldSpec* const*, const void* const*,
+                                          const void* const*, int, const void*, int, const void*, const uint8_t*,
+                                          hipStream_t);
+template hipError_t launch_zbin_gg<double>(const BinArgs&, const FieldSpec* const*, const void* const*,
+                                           const void* const*, int, const void*, int, const void*, const uint8_t*,
+                                           hipStream_t);
 template hipError_t launch_bin_dd<float>(const BinArgs&, const FieldSpec* const*, const void* const*, int, const void*,
                                          hipStream_t);
 template hipError_t launch_bin_dd<double>(const BinArgs&, const FieldSpec* const*, const void* const*, int,

@@ -298,6 +298,16 @@ constexpr int kBinGroupMax = 5;  // FP32 shape fields
 // fields per shell-sum launch: kBinGroupMax for FP32 shape fields, else
 // kBinGroup, fewer when 2 n nb sums per wavefront would not fit the LDS rows
 int bin_group_max(bool complex_fields, bool fp64, int nb);
+// The z pass of a group of complex fields fused with their shell sums
+// (kernels_bin.hip): g1/g2 after the x and y passes of fft_zb_kernel, plane =
+// the footprint's z-plane flags (nullable).  zbin_group_max: the most fields
+// per launch whose LDS fits one CU (0: the fused kernel cannot take nb shells
+// at this N).
+int zbin_group_max(int N, bool fp64, int nb);
+int zbin_blocks(int N, bool fp64, int nblocks);  // its workgroups (partial rows) for a budget of nblocks
+template <typename T>
+hipError_t launch_zbin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
+                          int n, const void* base, int kind, const void* tw, const uint8_t* plane, hipStream_t st);
 template <typename T>
 hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void* const* g1, const void* const* g2,
                          int n, const void* base, int kind, hipStream_t st);
