@@ -368,6 +368,11 @@ typedef struct {
                               between passes: z only; larger: x and z, y too when its
                               workgroups read runs of 128 bytes or more: FP32 with 16 y
                               lines, or FP64)                                             */
+  int32_t unfused;         /* 1: every shape field takes the z pass as a launch of its own and
+                              the shell-sum kernel reads the transformed fields back (the
+                              path taken anyway where the fused kernel's LDS cannot hold the
+                              shells: N = 1024 with more than 296 shells in FP32, 432 in FP64);
+                              0: the shape fields' z pass runs inside their shell sums     */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field
  * (LPP_E_INVALID for an unsupported value, the plan unchanged). */

@@ -31,7 +31,7 @@ EXPORTS = ["lpp_plan_create", "lpp_plan_destroy", "lpp_workspace_size", "lpp_set
            "lpp_mlp_destroy", "lpp_mlp_set_stream", "lpp_mlp_num_params", "lpp_mlp_get_params", "lpp_mlp_set_params",
            "lpp_mlp_forward", "lpp_mlp_train_step", "lpp_mlp_fit", "lpp_emulator_encode", "lpp_emulator_predict"]
 TUNING_FIELDS = ["fft_rows_x", "fft_cols_y", "fft_cols_z", "bin_blocks", "gather_density", "gather_shape", "serial",
-                 "fft_streaming"]
+                 "fft_streaming", "unfused"]
 STAGES = ["sort", "deposit", "fft_x", "fft_yz", "bin", "other"]
 
 

@@ -658,7 +658,7 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
       // the fused shell-sum kernel, in groups of up to zmax fields (zmax = 0:
       // the fused kernel's LDS cannot hold this many shells at this N, and
       // every field takes the three passes and then the shell-sum kernel).
-      const int zmax = cplx ? zbin_group_max(N, std::is_same<T, double>::value, nb) : 0;
+      const int zmax = (cplx && p->tune.unfused == 0) ? zbin_group_max(N, std::is_same<T, double>::value, nb) : 0;
       for (int m = 0; m < nf * (cplx ? copies : 1); ++m) {
         const bool fused = zmax > 0 && jobs[j0 + m / copies].series >= 0;
         LPP_TRY(fft(W[m], fp, !fused));
@@ -1136,6 +1136,7 @@ bool tuning_valid(const lpp_plan_s* p, const lpp_tuning& t) {
   if (t.gather_shape < 0 || t.gather_shape > max_shape_fields(p)) return false;
   if (t.serial != 0 && t.serial != 1) return false;
   if (t.fft_streaming != 0 && (t.fft_streaming < 8 || t.fft_streaming > 15)) return false;
+  if (t.unfused != 0 && t.unfused != 1) return false;
   return true;
 }
 
@@ -1165,6 +1166,7 @@ bool parse_tuning_line(const std::string& line, std::string& key, lpp_tuning& t)
   if (!field("serial", t.serial)) t.serial = 0;  // optional
   if (!field("fft_streaming", t.fft_streaming)) t.fft_streaming = 0;
   if (!field("fft_cols_z", t.fft_cols_z)) t.fft_cols_z = 0;
+  if (!field("unfused", t.unfused)) t.unfused = 0;
   return field("fft_rows_x", t.fft_rows_x) && field("fft_cols_y", t.fft_cols_y) &&
          field("bin_blocks", t.bin_blocks) && field("gather_density", t.gather_density) &&
          field("gather_shape", t.gather_shape);
@@ -1175,9 +1177,9 @@ std::string tuning_line(const std::string& key, const lpp_tuning& t) {
   std::snprintf(b, sizeof b,
                 "{\"key\": \"%s\", \"fft_rows_x\": %d, \"fft_cols_y\": %d, \"fft_cols_z\": %d, "
                 "\"bin_blocks\": %d, \"gather_density\": %d, \"gather_shape\": %d, \"serial\": %d, "
-                "\"fft_streaming\": %d}",
+                "\"fft_streaming\": %d, \"unfused\": %d}",
                 key.c_str(), t.fft_rows_x, t.fft_cols_y, t.fft_cols_z, t.bin_blocks, t.gather_density, t.gather_shape,
-                t.serial, t.fft_streaming);
+                t.serial, t.fft_streaming, t.unfused);
   return b;
 }
 

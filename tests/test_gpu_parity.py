@@ -621,7 +621,7 @@ def test_tuning_variants_match_oracle(lpp, prec):
     variants = [dict(fft_rows_x=16), dict(fft_cols_y=8), dict(fft_cols_y=16), dict(fft_cols_z=8), dict(fft_cols_z=16),
                 dict(bin_blocks=64), dict(bin_blocks=8192), dict(gather_density=1), dict(gather_density=3),
                 dict(gather_shape=1), dict(gather_shape=2), dict(serial=1), dict(fft_streaming=8),
-                dict(fft_streaming=13)]
+                dict(fft_streaming=13), dict(unfused=1), dict(unfused=1, gather_shape=3)]
     if prec == "f32":
         variants += [dict(gather_shape=3), dict(gather_density=4), dict(gather_density=6)]
     base = plan.tuning()

@@ -119,10 +119,10 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     t = plan.tuning()
     # FP32 up to N = 512: ten shape fields per pass (the node-parallel deposit)
     assert t == {"fft_rows_x": 8, "fft_cols_y": 16, "fft_cols_z": 8, "bin_blocks": 8192, "gather_density": 8,
-                 "gather_shape": 10, "serial": 0, "fft_streaming": 15}
+                 "gather_shape": 10, "serial": 0, "fft_streaming": 15, "unfused": 0}
     for bad in (dict(fft_rows_x=3), dict(fft_rows_x=4), dict(fft_rows_x=64), dict(fft_cols_y=32), dict(fft_cols_z=4),
                 dict(bin_blocks=10), dict(bin_blocks=100000), dict(gather_density=9), dict(gather_shape=11),
-                dict(serial=2), dict(fft_streaming=7), dict(fft_streaming=16)):
+                dict(serial=2), dict(fft_streaming=7), dict(fft_streaming=16), dict(unfused=2), dict(unfused=-1)):
         with pytest.raises(pkg.LppError):
             plan.set_tuning(**bad)
         assert plan.tuning() == t
@@ -172,7 +172,8 @@ def test_tuning_defaults_validation_and_cache(tmp_path, monkeypatch):
     monkeypatch.setenv("LPP_AUTOTUNE_CACHE", str(cache))
     tuned = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", lmax=4, n_kbins=50)
     assert tuned.tuning() == {"fft_rows_x": 16, "fft_cols_y": 8, "fft_cols_z": 16, "bin_blocks": 4096,
-                              "gather_density": 2, "gather_shape": 1, "serial": 0, "fft_streaming": 13}
+                              "gather_density": 2, "gather_shape": 1, "serial": 0, "fft_streaming": 13,
+                              "unfused": 0}
     other = pkg.Plan(512, 1700.0, (-50.0, -50.0, -50.0), precision="f32", assignment=2, lmax=4, n_kbins=50)
     assert other.tuning() == t
 
