@@ -14,7 +14,10 @@
 // on change; the block's accumulators go to a per-block partial row that a
 // second kernel reduces in block order.  The fields of one gather pass that
 // share the base and the kind of product are summed by one launch, which
-// reads the base once for all of them.
+// reads the base once for all of them.  For complex (shape) fields the z pass
+// of the transform is fused into that launch (zbin_gg_kernel below), so the
+// transformed fields never go to HBM; bin_gg_group_kernel reads them back
+// from HBM where the fused kernel's LDS cannot hold the shells.
 //
 // Density fields are real: their two interlaced copies are packed as the real
 // and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
@@ -603,11 +606,12 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
 // and pruning) and, field by field, transforms the grid copy and the
 // interlaced copy of every column, combines the two in registers and passes
 // the combined modes through LDS, after which each thread holds one z-group
-// run of one column: the run's base values and shells are loaded once for all
-// fields of the group, and the sums go, as in bin_gg_group_kernel, to the
-// thread's wavefront's LDS row (fields in order, so two runs are bitwise
-// equal).  Workgroups walk the (column block, y) items in a stride of the
-// grid; a block outside the last shell is skipped whole.
+// run of one column: the run's shells are found once for all fields of the
+// group (its base values are read per field, from the L2 after the first),
+// and the sums go, as in bin_gg_group_kernel, to the thread's wavefront's LDS
+// row (fields in order, so two runs are bitwise equal).  Workgroups walk the
+// (column block, y) items in a stride of the grid; a block outside the last
+// shell is skipped whole.
 template <typename T>
 struct ZbGroup {
   KSpec<T> h[kBinGroupMax];
@@ -621,7 +625,6 @@ constexpr int zbin_waves() {
   return (NL * (N / 8) + 63) / 64;
 }
 
-// KIND 0: h F conj(B(k)); KIND 1: h F B(-k)
 // waves per SIMD to keep registers for: two workgroups per CU, one of 1024
 // threads (FP32, N = 1024) or with FP64 lines of 1024 (LDS)
 template <typename T, int N, int NL>
@@ -632,6 +635,7 @@ constexpr int zbin_min_waves() {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
+// KIND 0: h F conj(B(k)); KIND 1: h F B(-k)
 template <typename T, int N, int NL, int KIND>
 __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_gg_kernel(BinArgs a, ZbGroup<T> g,
                                                              const typename V2<T>::type* __restrict__ B,
