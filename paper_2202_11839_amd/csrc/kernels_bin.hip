@@ -625,14 +625,18 @@ constexpr int zbin_waves() {
   return (NL * (N / 8) + 63) / 64;
 }
 
-// waves per SIMD to keep registers for: two workgroups per CU, one of 1024
-// threads (FP32, N = 1024) or with FP64 lines of 1024 (LDS)
+// Waves per SIMD the kernel keeps registers for (its launch bound): four in
+// FP32 (at most 128 VGPRs), two in FP64; the fields per launch are then
+// chosen so that the LDS of a workgroup (lines, tables, shell rows) lets that
+// many waves reside (zbin_group_max).
+template <typename T>
+constexpr int zbin_waves_per_simd() {
+  return sizeof(T) == 4 ? 4 : 2;
+}
 template <typename T, int N, int NL>
 constexpr int zbin_min_waves() {
-  constexpr int threads = NL * (N / 8);
-  constexpr int blocks = (threads >= 1024 || (sizeof(T) == 8 && N >= 1024)) ? 1 : 2;
-  constexpr int w = blocks * threads / 256;
-  return w < 1 ? 1 : (w > 8 ? 8 : w);
+  constexpr int own = (NL * (N / 8) + 255) / 256;  // one workgroup's waves per SIMD
+  return own > zbin_waves_per_simd<T>() ? own : zbin_waves_per_simd<T>();
 }
 
 // KIND 0: h F conj(B(k)); KIND 1: h F B(-k)
@@ -922,10 +926,12 @@ hipError_t launch_bin_gg(const BinArgs& a, const FieldSpec* const* f, const void
 
 namespace {
 
-// columns per workgroup of the fused kernel: 8 in FP32 (runs of 512
-// contiguous bytes, as the z pass), 4 in FP64 (the same bytes per run, and
-// LDS for two workgroups per CU)
-constexpr int zbin_lines(bool fp64) { return fp64 ? 4 : 8; }
+// columns per workgroup of the fused kernel: 4 (runs of 256 contiguous bytes
+// in FP32, 512 in FP64).  Small workgroups keep the LDS per wave low: at 512^3
+// in FP32 four workgroups of 256 threads with three fields' shell rows reside
+// per CU (16 waves), against two of 512 threads with eight columns (the
+// shape shell sums 27.2 -> 25.1 ms per estimate).
+constexpr int zbin_lines(bool /*fp64*/) { return 4; }
 
 }  // namespace
 
@@ -952,9 +958,16 @@ size_t zbin_lds(int n, int nb) {
 
 template <typename T, int N>
 int zbin_group_max_n(int nb) {
+  // the most fields per launch that keep the workgroups per CU of one field:
+  // as many as the launch bound's waves allow, if the LDS holds them
+  constexpr int threads = zbin_lines(sizeof(T) == 8) * (N / 8);
+  constexpr int block_waves = (threads + 63) / 64;
+  constexpr int by_waves = 4 * zbin_waves_per_simd<T>() / block_waves > 0 ? 4 * zbin_waves_per_simd<T>() / block_waves : 1;
+  auto blocks = [&](int n) { return std::min<size_t>(by_waves, (160 * 1024) / zbin_lds<T, N>(n, nb)); };
+  if (blocks(1) < 1) return 0;
   const int cap = sizeof(T) == 4 ? kBinGroupMax : kBinGroup;
-  int n = 0;
-  while (n < cap && zbin_lds<T, N>(n + 1, nb) <= 160 * 1024) ++n;
+  int n = 1;
+  while (n < cap && blocks(n + 1) >= blocks(1)) ++n;
   return n;
 }
 
