@@ -631,7 +631,13 @@ constexpr int zbin_waves() {
 // many waves reside (zbin_group_max).
 template <typename T>
 constexpr int zbin_waves_per_simd() {
-  return sizeof(T) == 4 ? 4 : 2;
+  return sizeof(T) == 4 ? 4 : 3;
+}
+// the per-axis tables in LDS in FP32; FP64 reads them from the global tables
+// (cached), which leaves the LDS for a third workgroup per CU
+template <typename T, int N>
+constexpr size_t zbin_tables_lds() {
+  return sizeof(T) == 4 ? rows_offset<T>(N) : 0;
 }
 template <typename T, int N, int NL>
 constexpr int zbin_min_waves() {
@@ -655,12 +661,22 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
   __shared__ int sthr[kMaxBins + 1];
   extern __shared__ __align__(16) unsigned char dyn[];
   const int nb = a.nb, n = g.n;
-  T2* px = reinterpret_cast<T2*>(dyn);
-  T* iw = reinterpret_cast<T*>(px + N);
-  tables_init<T>(a, px, iw);
+  constexpr size_t roff = zbin_tables_lds<T, N>();
+  const T2* px;
+  const T* iw;
+  if constexpr (roff > 0) {
+    T2* lpx = reinterpret_cast<T2*>(dyn);
+    T* liw = reinterpret_cast<T*>(lpx + N);
+    tables_init<T>(a, lpx, liw);
+    px = lpx;
+    iw = liw;
+  } else {
+    px = static_cast<const T2*>(a.phase) + N;  // (as tables_init: nx = i - N/2 at i + N)
+    iw = static_cast<const T*>(a.invw);
+  }
   for (int i = threadIdx.x; i < N; i += NT) stw[i] = tw[i];
   const int width = 2 * n * nb;
-  double* v = rows_init<NW>(dyn, rows_offset<T>(N), width, a.thr, sthr, nb);  // (ends with a barrier)
+  double* v = rows_init<NW>(dyn, roff, width, a.thr, sthr, nb);  // (ends with a barrier)
   const T2* phase = static_cast<const T2*>(a.phase);
   const T* invw = static_cast<const T*>(a.invw);
   const int qmax = sthr[nb];
@@ -790,7 +806,7 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
       }
     }
   }
-  rows_store<NW>(dyn, rows_offset<T>(N), width, a.partial);
+  rows_store<NW>(dyn, roff, width, a.partial);
 }
 
 // one block per column c: strided partial sums, then a fixed-shape tree
@@ -948,7 +964,7 @@ namespace {
 template <typename T, int N>
 size_t zbin_dyn_lds(int n, int nb) {
   constexpr int NW = zbin_waves<T, N, zbin_lines(sizeof(T) == 8)>();
-  return rows_offset<T>(N) + 8 * static_cast<size_t>(NW) * 2 * n * nb;
+  return zbin_tables_lds<T, N>() + 8 * static_cast<size_t>(NW) * 2 * n * nb;
 }
 template <typename T, int N>
 size_t zbin_lds(int n, int nb) {
