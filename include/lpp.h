@@ -369,9 +369,9 @@ typedef struct {
                               workgroups read runs of 128 bytes or more: FP32 with 16 y
                               lines, or FP64)                                             */
   int32_t unfused;         /* 1: every shape field takes the z pass as a launch of its own and
-                              the shell-sum kernel reads the transformed fields back (the
-                              path taken anyway where the fused kernel's LDS cannot hold the
-                              shells: N = 1024 with more than 296 shells in FP32, 432 in FP64);
+                              the shell-sum kernel reads the transformed fields back (also
+                              the path for a size whose shells the fused kernel's LDS could
+                              not hold, which no supported mesh and shell count reaches);
                               0: the shape fields' z pass runs inside their shell sums     */
 } lpp_tuning;
 /* Current launch shapes with defaults resolved; set validates each field

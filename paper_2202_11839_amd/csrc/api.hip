@@ -656,8 +656,8 @@ lpp_status device_pipeline(lpp_plan_s* p, const Layout& L, const RawCat& rg, con
       }
       // The complex fields other than the set's base take their z pass inside
       // the fused shell-sum kernel, in groups of up to zmax fields (zmax = 0:
-      // the fused kernel's LDS cannot hold this many shells at this N, and
-      // every field takes the three passes and then the shell-sum kernel).
+      // the unfused tuning, or a shell count the fused kernel's LDS could not
+      // hold: every field takes the three passes and then the shell-sum kernel).
       const int zmax = (cplx && p->tune.unfused == 0) ? zbin_group_max(N, std::is_same<T, double>::value, nb) : 0;
       for (int m = 0; m < nf * (cplx ? copies : 1); ++m) {
         const bool fused = zmax > 0 && jobs[j0 + m / copies].series >= 0;

@@ -17,7 +17,7 @@
 // reads the base once for all of them.  For complex (shape) fields the z pass
 // of the transform is fused into that launch (zbin_gg_kernel below), so the
 // transformed fields never go to HBM; bin_gg_group_kernel reads them back
-// from HBM where the fused kernel's LDS cannot hold the shells.
+// from HBM when the plan's tuning asks for the unfused path.
 //
 // Density fields are real: their two interlaced copies are packed as the real
 // and imaginary parts of one complex mesh, P = D1 + i D2, and are separated
