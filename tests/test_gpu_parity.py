@@ -1099,6 +1099,38 @@ def test_batch_256_mock_against_stored_oracle(lpp):
     assert plan.batch_stats() == (1, 2)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_shell_sums_match_the_unfused_path(lpp, prec):
+    """The shape fields' z pass fused with their shell sums against the same
+    z pass as launches of its own followed by the shell-sum kernel (tuning
+    field unfused = 1), on the 256^3 batch workload's settings (a 30,000 +
+    300,000 subsample, TSC + interlacing, l <= 4, 50 shells): both transform,
+    combine and weigh every mode with the same operations, so the series may
+    differ only by the order of the FP64 shell sums (1e-10 of each series'
+    scale); counts bit-exact."""
+    import os
+    import sys
+    import torch
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_c3_subsample as MK
+    g, r = MK.catalogs()
+    wl = MK.WORKLOADS["c3"]
+    plan = lpp.Plan(wl["mesh"], wl["box"], wl["origin"], wl["observer"], assignment=wl["assignment"],
+                    interlacing=wl["interlacing"], precision=prec, lmax=4, n_kbins=wl["n_kbins"])
+    dt = torch.float32 if prec == "f32" else torch.float64
+    gd, rd = _device_catalog(g, torch, dt), _device_catalog(r, torch, dt)
+    fused = plan.estimate(gd, rd)
+    plan.set_tuning(unfused=1)
+    assert plan.tuning()["unfused"] == 1
+    sep = plan.estimate(gd, rd)
+    assert list(fused["n_modes"]) == list(sep["n_modes"])
+    scales = _series_scale(sep)
+    for i, name in enumerate(sep["series"]):
+        for part in ("re", "im"):
+            d = np.abs(np.asarray(fused[part][i]) - np.asarray(sep[part][i]))
+            assert np.all(d <= 1e-10 * scales[i] + 1e-300), (name, part, float((d / scales[i]).max()))
+
+
 def _device_catalog(c, torch, dtype=None):
     return Catalog(*[None if v is None else torch.tensor(v, device="cuda", dtype=dtype)
                      for v in (c.x, c.y, c.z, c.w, c.nbar, c.g1, c.g2)])
