@@ -730,8 +730,14 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
       // exchanges, output rows, the modes' unit vectors and shells) is then
       // recomputed where it is used instead of being held in registers across
       // the field loop and the transforms, which would halve the occupancy.
+      // (The masks restore the ranges the asm hides, no-ops on the values:
+      // with t < N/8 and the swizzle below 64 the exchanges' row addresses
+      // t + j N/8 become one base plus immediate offsets.)
       int tq = t, cq = col, sq = swz, zq = z0;
       asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq), "+v"(zq));
+      tq &= TL - 1;
+      cq &= NL - 1;
+      sq &= (TL >= 8 ? 63 : 15);
       // both copies' loads in flight before the first transform
       T2 v1[8], w[8];
 #pragma unroll
@@ -747,9 +753,15 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
       dev::fft_column_regs<T, N>(stw, sm, cq, tq, v1, sq);
       if (a.interlace) {
         asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq));
+        tq &= TL - 1;
+        cq &= NL - 1;
+        sq &= (TL >= 8 ? 63 : 15);
         dev::fft_column_regs<T, N>(stw, sm, cq, tq, w, sq);
       }
       asm volatile("" : "+v"(tq), "+v"(cq), "+v"(sq));
+      tq &= TL - 1;
+      cq &= NL - 1;
+      sq &= (TL >= 8 ? 63 : 15);
       // combined, compensated modes of the lines to LDS, runs back
       int row[8];
       dev::fft_rows<N>(tq, row);
