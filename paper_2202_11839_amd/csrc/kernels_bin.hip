@@ -74,11 +74,22 @@ __device__ __forceinline__ T column_azimuth(const KSpec<T>& h, int nx, int ny) {
   }
   return h.cs ? ei : er;
 }
+// (The polynomial takes a fixed number of terms, five up to degree 4, else
+// nine: the coefficients past nq are zero, so the leading steps give exact
+// zeros, and no per-mode loop reads the count and the coefficients again.)
 template <typename T>
 __device__ __forceinline__ T harmonic_of_column(const KSpec<T>& h, T az, int nz, T rq) {
   const T u = static_cast<T>(nz) * rq;
-  T Q = 0;
-  for (int i = h.nq - 1; i >= 0; --i) Q = Q * u + h.q[i];
+  T Q;
+  if (h.nq <= 5) {
+    Q = h.q[4];
+#pragma unroll
+    for (int i = 3; i >= 0; --i) Q = Q * u + h.q[i];
+  } else {
+    Q = h.q[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) Q = Q * u + h.q[i];
+  }
   T sc = az;
   for (int m = 0; m < h.M; ++m) sc *= rq;
   return Q * sc;
@@ -738,16 +749,27 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
       tq &= TL - 1;
       cq &= NL - 1;
       sq &= (TL >= 8 ? 63 : 15);
-      // both copies' loads in flight before the first transform
+      // both copies' loads in flight before the first transform (element e
+      // = t + j N/8 of a line sits at (e >> 3) hi + (e & 7): with N/8 a
+      // multiple of 8 that is the thread's first element plus j (N/64) hi)
       T2 v1[8], w[8];
+      {
+        int64_t off0;
+        constexpr int64_t jstep = TL >= 8 ? (TL / 8) * hi : 0;
+        if constexpr (TL >= 8) off0 = lbase + (tq >> 3) * hi + (tq & 7);
+        else off0 = lbase;
+        auto off = [&](int j) -> int64_t {
+          if constexpr (TL >= 8) return off0 + j * jstep;
+          const int e = tq + j * TL;
+          return off0 + (e >> 3) * hi + (e & 7);
+        };
+        const T2* __restrict__ s1 = g.g1[f];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int e = tq + j * TL;
-        const int64_t off = lbase + (e >> 3) * hi + (e & 7);
-        v1[j] = w[j] = T2{0, 0};
-        if (rd[j]) {
-          v1[j] = dev::nt_load(g.g1[f] + off);
-          if (a.interlace) w[j] = dev::nt_load(g.g2[f] + off);
+        for (int j = 0; j < 8; ++j) v1[j] = rd[j] ? dev::nt_load(s1 + off(j)) : T2{0, 0};
+        if (a.interlace) {
+          const T2* __restrict__ s2 = g.g2[f];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) w[j] = rd[j] ? dev::nt_load(s2 + off(j)) : T2{0, 0};
         }
       }
       dev::fft_column_regs<T, N>(stw, sm, cq, tq, v1, sq);
@@ -767,9 +789,9 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
       dev::fft_rows<N>(tq, row);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int iz = row[q], nz = sgn_mode(iz, N);
+        const int iz = row[q];  // (signed mode nz at nz + N/2 = iz ^ N/2 of the phase table)
         sm[dev::sidx<N>(cq, iz, sq)] =
-            combine<T, T2>(v1[q], w[q], a.interlace, cmul(pxy, px[nz + N / 2]), wxy * iw[iz]);
+            combine<T, T2>(v1[q], w[q], a.interlace, cmul(pxy, px[iz ^ (N / 2)]), wxy * iw[iz]);
       }
       __syncthreads();
       T2 F[kRun];
@@ -789,7 +811,7 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
           if (KIND == 0) bv[j] = B[run + j];
           else if (bq[j] >= 0) bv[j] = B[zb_index(mx, my, (N - zq - j) & mask, N)];
         }
-        const KSpec<T>& h = g.h[f];
+        const KSpec<T> h = g.h[f];  // (a copy: the field's coefficients read once)
         const T az = column_azimuth(h, rnx, ny);
         int cur = -1;
         double sre = 0.0, sim = 0.0;
