@@ -612,9 +612,9 @@ __global__ void __launch_bounds__(kBinThreads) bin_gg_group_kernel(BinArgs a, Gg
 //
 // The last transform pass (along z) of a group's fields is followed at once
 // by the shell sums, so that the transformed fields are never written to HBM
-// and read back.  A workgroup takes the NL adjacent columns x of one row y
-// that fft_zb_kernel's z pass takes (N/8 threads per column, the same lines
-// and pruning) and, field by field, transforms the grid copy and the
+// and read back.  A workgroup takes NL adjacent columns x of one row y (the
+// z pass's lines: N/8 threads per column, the same pruning as in
+// fft_zb_kernel) and, field by field, transforms the grid copy and the
 // interlaced copy of every column, combines the two in registers and passes
 // the combined modes through LDS, after which each thread holds one z-group
 // run of one column: the run's shells are found once for all fields of the
@@ -637,7 +637,7 @@ constexpr int zbin_waves() {
 }
 
 // Waves per SIMD the kernel keeps registers for (its launch bound): four in
-// FP32 (at most 128 VGPRs), two in FP64; the fields per launch are then
+// FP32 (at most 128 VGPRs), three in FP64 (168); the fields per launch are then
 // chosen so that the LDS of a workgroup (lines, tables, shell rows) lets that
 // many waves reside (zbin_group_max).
 template <typename T>
@@ -738,9 +738,9 @@ __global__ void __launch_bounds__(NL* N / 8, (zbin_min_waves<T, N, NL>())) zbin_
     for (int f = 0; f < n; ++f) {
       // Opaque copies of the line position and the run start: what depends
       // on them only (load offsets, LDS addresses of the transform's
-      // exchanges, output rows, the modes' unit vectors and shells) is then
-      // recomputed where it is used instead of being held in registers across
-      // the field loop and the transforms, which would halve the occupancy.
+      // exchanges, output rows, the modes' unit vectors) is then recomputed
+      // where it is used instead of being held in registers across the field
+      // loop and the transforms, which would halve the occupancy.
       // (The masks restore the ranges the asm hides, no-ops on the values:
       // with t < N/8 and the swizzle below 64 the exchanges' row addresses
       // t + j N/8 become one base plus immediate offsets.)
